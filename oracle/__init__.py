@@ -1,0 +1,28 @@
+"""FP64 CPU oracle for adaptive multigrid on the Shamir domain-wall operator.
+
+TEST INFRASTRUCTURE ONLY.  This package is the plain, slow, obviously correct
+reference that the GPU library is checked against.  Only the test suite, the
+smoke check of the entry module and the CPU-baseline leg of the benchmark may
+import it; the product library never does, and it shares no code with it.
+
+Contents, each following the paper (Cohen, Brower, Clark, Osborn, "Multigrid
+Algorithms for Domain-Wall Fermions", Lattice 2011):
+
+* ``dwf``       -- the 5D Shamir operator D and its adjoint (Sec. 2, last
+                   paragraph: fifth dimension; Sec. 4: one site plus ten unit
+                   neighbours).  The paper never writes D; the standard Shamir
+                   form used here is a stated reading.
+* ``transfer``  -- chirality-split, block-orthonormalised near-null basis,
+                   restrictor R and prolongator P with R P = 1 (Sec. 1, R/P
+                   definition; Sec. 2, blocks spanning the fifth dimension).
+* ``coarse``    -- Galerkin coarse operator D_c = R D P as a 9-point stencil of
+                   dense blocks (Sec. 2, V-cycle step 3; Sec. 4, coarsening of
+                   the unsquared operator).
+* ``solvers``   -- minimal-residual smoother, GCR / flexible GCR, CG on the
+                   normal equations, the five-step V-cycle (Sec. 2 and Sec. 3).
+* ``setup``     -- adaptive near-null vector search (Sec. 2, adaptive setup).
+* ``dense``     -- explicit matrices on tiny lattices (pins only).
+* ``nullnet``   -- forward/backward of the gauge-covariant proposal network.
+
+Every function works in complex128.
+"""
