@@ -1,0 +1,213 @@
+/*
+ * mgdwf.h -- C ABI of the MI355X library for adaptive multigrid on the
+ * Shamir domain-wall fermion operator.
+ *
+ * Method: S. D. Cohen, R. C. Brower, M. A. Clark, J. C. Osborn, "Multigrid
+ * Algorithms for Domain-Wall Fermions" (Lattice 2011).  Section numbers below
+ * refer to that paper.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Canonical arrays are complex128, interleaved (re, im) doubles, C order:
+ *   4D site     x4 = ((t*Lz + z)*Ly + y)*Lx + x;  direction mu = 0..3 is x, y, z, t
+ *   fermion     ((x4*Ls + s)*4 + spin)*3 + colour          (12*Ls*V4 complex)
+ *   gauge       ((x4*4 + mu)*3 + a)*3 + b = U_mu(x)[a][b]   (36*V4 complex)
+ *   vector set  [k][fermion]                                 (k = 0..n-1)
+ *   coarse site X4 = ((T*LZ + Z)*LY + Y)*LX + X, X = x / block_x, ...
+ *   coarse vec  (X4*2 + chi)*Nv + k; chi = 0 spins {0,1} (P+), chi = 1 spins {2,3}
+ *   coarse op   Dc[X4][d][row][col], row/col = chi*Nv + k, d = 0 self,
+ *               d = 1+2mu neighbour +mu, d = 2+2mu neighbour -mu;
+ *               (D_c y)(X) = sum_d Dc[X][d] y(X + delta_d), periodic.
+ * Several right-hand sides (nrhs) are stacked along a leading axis.
+ *
+ * Pointers: every array argument is a DEVICE pointer on the handle's device
+ * (for instance a torch tensor's data_ptr()) unless the argument list says
+ * otherwise.  The caller owns every buffer it passes; the library copies what
+ * it keeps (gauge field, basis, coarse operator) into its own internal layouts
+ * and never retains a caller pointer after a call returns.
+ *
+ * Streams: a handle is bound to the HIP stream given at creation and is not
+ * thread safe.  apply/restrict/prolong/apply_coarse are stream ordered and
+ * asynchronous; set_gauge, set_nullvecs, build_coarse, setup, solve and the
+ * get_* calls return after their work has completed.
+ *
+ * Errors: every call returns an mgdwf_status; nothing throws across this
+ * boundary and nothing aborts.  mgdwf_last_error(h) gives a message for the
+ * last failure on h (mgdwf_last_error(NULL) for a failed create).  Arguments
+ * are validated before any device work.  On MGDWF_ERR_NOT_CONVERGED the
+ * solution buffer holds the best iterate and the report is filled; after any
+ * other error outputs are undefined.
+ */
+#ifndef MGDWF_H
+#define MGDWF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mgdwf_ctx* mgdwf_handle;
+
+typedef enum {
+  MGDWF_OK = 0,
+  MGDWF_ERR_INVALID_ARG = 1,  /* bad size, block, precision, null pointer   */
+  MGDWF_ERR_OOM = 2,          /* device allocation failed                   */
+  MGDWF_ERR_HIP = 3,          /* a HIP runtime call failed                  */
+  MGDWF_ERR_NOT_CONVERGED = 4,/* solve hit max iterations / stagnated       */
+  MGDWF_ERR_STATE = 5,        /* call out of order, e.g. solve before setup */
+  MGDWF_ERR_NUMERIC = 6       /* NaN/Inf, or a rank-deficient block panel   */
+} mgdwf_status;
+
+typedef enum { MGDWF_F64 = 0, MGDWF_F32 = 1, MGDWF_F16 = 2, MGDWF_BF16 = 3 } mgdwf_prec;
+
+/* The fine operator (Sec. 2, fifth-dimension paragraph; Sec. 4, stencil of one
+ * site plus ten unit neighbours).  Shamir form:
+ *   (D psi)(x,s) = (5 - M5) psi(x,s)
+ *       - 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu,s) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu,s)]
+ *       - P_- psi(x,s+1) - P_+ psi(x,s-1),  walls closed by +m_f,
+ * gamma matrices in the chiral basis with g5 = diag(1,1,-1,-1).
+ * Every extent must be >= 2; bc[mu] is +1 (periodic) or -1 (antiperiodic). */
+typedef struct {
+  int32_t L[4];
+  int32_t Ls;
+  double M5;
+  double mf;
+  int32_t bc[4];
+} mgdwf_action;
+
+/* Two-level multigrid parameters (Sec. 2). */
+typedef struct {
+  int32_t block[4];       /* 4D block; each block spans all of Ls (Sec. 2)       */
+  int32_t nvec;           /* Nv: basis columns per chirality (coarse dof = 2 Nv)  */
+  int32_t sweeps;         /* adaptive sweeps in mgdwf_setup, including sweep 0    */
+  int32_t sweep0_iters;   /* CG iterations on D^+D v = 0 in sweep 0               */
+  int32_t sweep_iters;    /* MG-FGCR iterations per inverse-iteration sweep       */
+  int32_t nu_pre;         /* smoother steps before the coarse correction          */
+  int32_t nu_post;        /* smoother steps after it                              */
+  double coarse_tol;      /* relative residual of the coarse solve                */
+  int32_t coarse_maxiter; /* iteration cap of the coarse solve                    */
+  mgdwf_prec fine_prec;   /* F64 or F32: precision of the V-cycle's fine level    */
+  mgdwf_prec coarse_prec; /* F64, F32, F16 or BF16: storage of D_c in the V-cycle */
+} mgdwf_mg_params;
+
+/* Outer flexible GCR (Sec. 3).  Every restart recomputes the true residual
+ * b - D x in FP64 and restarts the inner cycle from it (iterative refinement). */
+typedef struct {
+  double tol;             /* stop at |b - D x| / |b| < tol (true FP64 residual)   */
+  int32_t max_outer;      /* cap on outer iterations                              */
+  int32_t restart;        /* Krylov vectors kept before a restart                 */
+} mgdwf_solve_params;
+
+typedef struct {
+  int32_t outer_iters;
+  int32_t restarts;
+  int64_t fine_applies;   /* applications of D or D^+, the paper's cost measure  */
+  int64_t coarse_applies; /* applications of D_c or D_c^+                          */
+  double true_relres;     /* |b - D x| / |b| in FP64 at return                    */
+  double seconds;         /* wall time of the call                                */
+  uint32_t flags;         /* bit 0: NaN/Inf met; bit 1: stagnation              */
+} mgdwf_solve_report;
+
+/* Setup report: median |D v|/|v| over the adaptive vectors after each sweep. */
+typedef struct {
+  int32_t sweeps_done;
+  double null_residual[8];
+  double seconds;
+} mgdwf_setup_report;
+
+/* ---- lifetime ---------------------------------------------------------- */
+
+/* Create a handle for one lattice and action, bound to `hip_stream` (a
+ * hipStream_t, NULL for the default stream) on the current device. */
+mgdwf_status mgdwf_create(const mgdwf_action* action, void* hip_stream, mgdwf_handle* out);
+mgdwf_status mgdwf_destroy(mgdwf_handle h);
+/* Message of the last failure on h, or of the last failed create if h is NULL. */
+const char* mgdwf_last_error(mgdwf_handle h);
+
+/* Copy the gauge field (canonical complex128, device) into the internal
+ * FP64 and FP32 link layouts.  Invalidates any basis / coarse operator. */
+mgdwf_status mgdwf_set_gauge(mgdwf_handle h, const double* U);
+
+/* ---- fine operator (step a1) ------------------------------------------ */
+
+/* out = D in (dagger = 0) or D^+ in (dagger = 1) for nrhs canonical fields.
+ * prec = F64 computes in FP64; F32 converts in to FP32, applies the FP32
+ * kernel and converts back.  in and out must not overlap. */
+mgdwf_status mgdwf_apply_dwf(mgdwf_handle h, const double* in, double* out, int32_t dagger,
+                             mgdwf_prec prec, int32_t nrhs);
+
+/* ---- transfer (steps a3-a5): Sec. 1 (R, P, RP = 1) and Sec. 2 --------- */
+
+/* Install nvec near-null vectors (canonical, device) with the given block:
+ * split each by chirality, orthonormalise every (block, chirality) panel in
+ * FP64 (thin QR, columns in order, positive real diagonal) and keep the basis.
+ * Fails with MGDWF_ERR_NUMERIC for a rank-deficient panel and
+ * MGDWF_ERR_INVALID_ARG if the block does not divide the lattice or
+ * nvec > 6 * Ls * (block volume). */
+mgdwf_status mgdwf_set_nullvecs(mgdwf_handle h, const int32_t block[4], const double* V,
+                                int32_t nvec);
+/* The orthonormal basis, canonical [Nv][fermion] (both chirality columns of
+ * vector k in field k). */
+mgdwf_status mgdwf_get_basis(mgdwf_handle h, double* Vhat);
+/* coarse = R fine  (R = P^+), nrhs canonical fine fields -> coarse vectors. */
+mgdwf_status mgdwf_restrict(mgdwf_handle h, const double* fine, double* coarse, int32_t nrhs);
+/* fine = P coarse. */
+mgdwf_status mgdwf_prolong(mgdwf_handle h, const double* coarse, double* fine, int32_t nrhs);
+
+/* ---- coarse operator (steps a6, a7): Sec. 2 step 3, Sec. 4 ------------ */
+
+/* Build D_c = R D P as the 9-point stencil of dense 2Nv x 2Nv blocks (FP64),
+ * plus its FP32, FP16 and BF16 copies with one scale per block. */
+mgdwf_status mgdwf_build_coarse(mgdwf_handle h);
+/* Copy the FP64 coarse operator out (canonical layout, complex128). */
+mgdwf_status mgdwf_get_coarse_op(mgdwf_handle h, double* Dc);
+/* out = D_c in (dagger 0) or D_c^+ in (dagger 1), nrhs canonical coarse
+ * vectors, computed with the operator stored in `prec` (F16/BF16 use MFMA with
+ * FP32 accumulation; inputs are converted with one scale per site and RHS). */
+mgdwf_status mgdwf_apply_coarse(mgdwf_handle h, const double* in, double* out, int32_t dagger,
+                                mgdwf_prec prec, int32_t nrhs);
+
+/* ---- setup and solve (steps a8-a11): Sec. 2, Sec. 3 -------------------- */
+
+/* Adaptive setup (Sec. 2): starting from nvec/2 random vectors V0 (canonical,
+ * device; the random numbers are inputs), run sweep 0 and the inverse-
+ * iteration sweeps, pair each vector with its fifth-dimension reflection,
+ * build the basis and D_c.  report may be NULL. */
+mgdwf_status mgdwf_setup(mgdwf_handle h, const mgdwf_mg_params* p, const double* V0,
+                         mgdwf_setup_report* report);
+/* Set the V-cycle parameters used by mgdwf_solve without a new setup
+ * (block and nvec must equal the installed basis). */
+mgdwf_status mgdwf_set_mg_params(mgdwf_handle h, const mgdwf_mg_params* p);
+
+/* Solve D x = b for nrhs right-hand sides (canonical, device) with flexible
+ * GCR preconditioned by the two-level V-cycle; x holds the initial guess on
+ * entry (zero it for a cold start).  reports[nrhs] may be NULL. */
+mgdwf_status mgdwf_solve(mgdwf_handle h, const double* b, double* x, int32_t nrhs,
+                         const mgdwf_solve_params* p, mgdwf_solve_report* reports);
+
+/* Control solver of Sec. 3: CG on the normal equations (CGNE), FP64. */
+mgdwf_status mgdwf_cgne(mgdwf_handle h, const double* b, double* x, const mgdwf_solve_params* p,
+                        mgdwf_solve_report* report);
+
+/* ---- measurement ------------------------------------------------------- */
+
+/* Kernel ids for mgdwf_time_kernel. */
+typedef enum {
+  MGDWF_K_DSLASH = 0,    /* fine operator on internal-layout fields  */
+  MGDWF_K_RESTRICT = 1,  /* R                                       */
+  MGDWF_K_PROLONG = 2,   /* P                                       */
+  MGDWF_K_COARSE = 3     /* D_c apply                               */
+} mgdwf_kernel;
+
+/* Launch kernel `k` `iters` times back to back on the handle's stream on
+ * internal buffers and return the mean time per launch in *ms, measured with
+ * HIP events recorded on that stream. */
+mgdwf_status mgdwf_time_kernel(mgdwf_handle h, mgdwf_kernel k, mgdwf_prec prec, int32_t nrhs,
+                               int32_t iters, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGDWF_H */

@@ -1,0 +1,282 @@
+"""ctypes binding of the C ABI in include/mgdwf.h.
+
+Argument marshalling only: every function here checks tensor placement,
+dtype, contiguity and size, then calls the C entry point of the same name.
+All computation happens in the HIP library.  PyTorch provides device memory
+and the stream.  The library must be built (``paper_1205_2933_amd.build``);
+importing this module without it raises immediately -- there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import torch
+
+_HERE = Path(__file__).resolve().parent
+LIB_PATH = _HERE / "libmgdwf.so"
+
+MGDWF_OK = 0
+MGDWF_ERR_INVALID_ARG = 1
+MGDWF_ERR_OOM = 2
+MGDWF_ERR_HIP = 3
+MGDWF_ERR_NOT_CONVERGED = 4
+MGDWF_ERR_STATE = 5
+MGDWF_ERR_NUMERIC = 6
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "HIP", 4: "NOT_CONVERGED", 5: "STATE", 6: "NUMERIC"}
+
+MGDWF_F64, MGDWF_F32, MGDWF_F16, MGDWF_BF16 = 0, 1, 2, 3
+PREC = {"f64": MGDWF_F64, "f32": MGDWF_F32, "f16": MGDWF_F16, "bf16": MGDWF_BF16}
+
+MGDWF_K_DSLASH, MGDWF_K_RESTRICT, MGDWF_K_PROLONG, MGDWF_K_COARSE = 0, 1, 2, 3
+
+
+class mgdwf_action(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 4), ("Ls", ctypes.c_int32), ("M5", ctypes.c_double),
+                ("mf", ctypes.c_double), ("bc", ctypes.c_int32 * 4)]
+
+
+class mgdwf_mg_params(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32 * 4), ("nvec", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("sweep0_iters", ctypes.c_int32), ("sweep_iters", ctypes.c_int32),
+                ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
+                ("coarse_tol", ctypes.c_double), ("coarse_maxiter", ctypes.c_int32),
+                ("fine_prec", ctypes.c_int), ("coarse_prec", ctypes.c_int)]
+
+
+class mgdwf_solve_params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("restart", ctypes.c_int32)]
+
+
+class mgdwf_solve_report(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("fine_applies", ctypes.c_int64), ("coarse_applies", ctypes.c_int64),
+                ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("flags", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class mgdwf_setup_report(ctypes.Structure):
+    _fields_ = [("sweeps_done", ctypes.c_int32), ("null_residual", ctypes.c_double * 8),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"sweeps_done": self.sweeps_done,
+                "null_residual": [self.null_residual[i] for i in range(self.sweeps_done)],
+                "seconds": self.seconds}
+
+
+class MgdwfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load() -> ctypes.CDLL:
+    if not LIB_PATH.exists():
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1205_2933_amd.build.build() first")
+    lib = ctypes.CDLL(str(LIB_PATH))
+    H = ctypes.c_void_p
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    sig = {
+        "mgdwf_create": ([ctypes.POINTER(mgdwf_action), P, ctypes.POINTER(H)], ctypes.c_int),
+        "mgdwf_destroy": ([H], ctypes.c_int),
+        "mgdwf_last_error": ([H], ctypes.c_char_p),
+        "mgdwf_set_gauge": ([H, P], ctypes.c_int),
+        "mgdwf_apply_dwf": ([H, P, P, i32, ctypes.c_int, i32], ctypes.c_int),
+        "mgdwf_set_nullvecs": ([H, ctypes.POINTER(i32), P, i32], ctypes.c_int),
+        "mgdwf_get_basis": ([H, P], ctypes.c_int),
+        "mgdwf_restrict": ([H, P, P, i32], ctypes.c_int),
+        "mgdwf_prolong": ([H, P, P, i32], ctypes.c_int),
+        "mgdwf_build_coarse": ([H], ctypes.c_int),
+        "mgdwf_get_coarse_op": ([H, P], ctypes.c_int),
+        "mgdwf_apply_coarse": ([H, P, P, i32, ctypes.c_int, i32], ctypes.c_int),
+        "mgdwf_setup": ([H, ctypes.POINTER(mgdwf_mg_params), P, ctypes.POINTER(mgdwf_setup_report)], ctypes.c_int),
+        "mgdwf_set_mg_params": ([H, ctypes.POINTER(mgdwf_mg_params)], ctypes.c_int),
+        "mgdwf_solve": ([H, P, P, i32, ctypes.POINTER(mgdwf_solve_params), ctypes.POINTER(mgdwf_solve_report)],
+                        ctypes.c_int),
+        "mgdwf_cgne": ([H, P, P, ctypes.POINTER(mgdwf_solve_params), ctypes.POINTER(mgdwf_solve_report)],
+                       ctypes.c_int),
+        "mgdwf_time_kernel": ([H, ctypes.c_int, ctypes.c_int, i32, i32, ctypes.POINTER(ctypes.c_double)],
+                              ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def exported_symbols():
+    """Names of the C entry points this binding declares."""
+    return [n for n in dir(_lib) if n.startswith("mgdwf_")]
+
+
+def _check(h, status: int, allow=()):
+    if status != MGDWF_OK and status not in allow:
+        msg = _lib.mgdwf_last_error(h)
+        raise MgdwfError(status, msg.decode() if msg else "")
+    return status
+
+
+def _dev(t: torch.Tensor, numel: int, name: str, dtype=torch.complex128):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """Owner of one mgdwf_handle plus the sizes needed for argument checks."""
+
+    def __init__(self, L, Ls, M5, mf, bc=(1, 1, 1, 1), stream=None):
+        a = mgdwf_action()
+        a.L[:] = list(L)
+        a.Ls, a.M5, a.mf = Ls, M5, mf
+        a.bc[:] = list(bc)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(None, _lib.mgdwf_create(ctypes.byref(a), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.L, self.Ls, self.M5, self.mf, self.bc = tuple(L), Ls, M5, mf, tuple(bc)
+        self.V4 = int(L[0] * L[1] * L[2] * L[3])
+        self.nfine = 12 * self.V4 * Ls
+        self.block = None
+        self.nvec = None
+
+    def close(self):
+        if self.h:
+            _lib.mgdwf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ncoarse(self):
+        Vc = 1
+        for m in range(4):
+            Vc *= self.L[m] // self.block[m]
+        return Vc * 2 * self.nvec
+
+
+# ---- thin wrappers, one per C entry point ---------------------------------
+
+def mgdwf_create(L, Ls, M5, mf, bc=(1, 1, 1, 1), stream=None) -> Handle:
+    return Handle(L, Ls, M5, mf, bc, stream)
+
+
+def mgdwf_destroy(h: Handle):
+    h.close()
+
+
+def mgdwf_last_error(h: Handle | None) -> str:
+    m = _lib.mgdwf_last_error(h.h if h else None)
+    return m.decode() if m else ""
+
+
+def mgdwf_set_gauge(h: Handle, U: torch.Tensor):
+    _check(h.h, _lib.mgdwf_set_gauge(h.h, _dev(U, 36 * h.V4, "U")))
+
+
+def mgdwf_apply_dwf(h: Handle, inp: torch.Tensor, out: torch.Tensor, dagger=False, prec="f64", nrhs=1):
+    n = h.nfine * nrhs
+    _check(h.h, _lib.mgdwf_apply_dwf(h.h, _dev(inp, n, "in"), _dev(out, n, "out"), int(dagger), PREC[prec], nrhs))
+
+
+def mgdwf_set_nullvecs(h: Handle, block, V: torch.Tensor, nvec: int):
+    blk = (ctypes.c_int32 * 4)(*block)
+    _check(h.h, _lib.mgdwf_set_nullvecs(h.h, blk, _dev(V, h.nfine * nvec, "V"), nvec))
+    h.block, h.nvec = tuple(block), nvec
+
+
+def mgdwf_get_basis(h: Handle, Vhat: torch.Tensor):
+    _check(h.h, _lib.mgdwf_get_basis(h.h, _dev(Vhat, h.nfine * h.nvec, "Vhat")))
+
+
+def mgdwf_restrict(h: Handle, fine: torch.Tensor, coarse: torch.Tensor, nrhs=1):
+    _check(h.h, _lib.mgdwf_restrict(h.h, _dev(fine, h.nfine * nrhs, "fine"), _dev(coarse, h.ncoarse * nrhs, "coarse"),
+                                    nrhs))
+
+
+def mgdwf_prolong(h: Handle, coarse: torch.Tensor, fine: torch.Tensor, nrhs=1):
+    _check(h.h, _lib.mgdwf_prolong(h.h, _dev(coarse, h.ncoarse * nrhs, "coarse"), _dev(fine, h.nfine * nrhs, "fine"),
+                                   nrhs))
+
+
+def mgdwf_build_coarse(h: Handle):
+    _check(h.h, _lib.mgdwf_build_coarse(h.h))
+
+
+def mgdwf_get_coarse_op(h: Handle, Dc: torch.Tensor):
+    n = h.ncoarse // (2 * h.nvec) * 9 * (2 * h.nvec) ** 2
+    _check(h.h, _lib.mgdwf_get_coarse_op(h.h, _dev(Dc, n, "Dc")))
+
+
+def mgdwf_apply_coarse(h: Handle, inp: torch.Tensor, out: torch.Tensor, dagger=False, prec="f64", nrhs=1):
+    n = h.ncoarse * nrhs
+    _check(h.h, _lib.mgdwf_apply_coarse(h.h, _dev(inp, n, "in"), _dev(out, n, "out"), int(dagger), PREC[prec], nrhs))
+
+
+def make_mg_params(block, nvec, sweeps=3, sweep0_iters=100, sweep_iters=4, nu_pre=4, nu_post=4,
+                   coarse_tol=0.1, coarse_maxiter=100, fine_prec="f64", coarse_prec="f64") -> mgdwf_mg_params:
+    p = mgdwf_mg_params()
+    p.block[:] = list(block)
+    p.nvec, p.sweeps, p.sweep0_iters, p.sweep_iters = nvec, sweeps, sweep0_iters, sweep_iters
+    p.nu_pre, p.nu_post, p.coarse_tol, p.coarse_maxiter = nu_pre, nu_post, coarse_tol, coarse_maxiter
+    p.fine_prec, p.coarse_prec = PREC[fine_prec], PREC[coarse_prec]
+    return p
+
+
+def mgdwf_setup(h: Handle, params: mgdwf_mg_params, V0: torch.Tensor) -> dict:
+    rep = mgdwf_setup_report()
+    _check(h.h, _lib.mgdwf_setup(h.h, ctypes.byref(params), _dev(V0, h.nfine * (params.nvec // 2), "V0"),
+                                 ctypes.byref(rep)))
+    h.block, h.nvec = tuple(params.block), params.nvec
+    return rep.as_dict()
+
+
+def mgdwf_set_mg_params(h: Handle, params: mgdwf_mg_params):
+    _check(h.h, _lib.mgdwf_set_mg_params(h.h, ctypes.byref(params)))
+
+
+def mgdwf_solve(h: Handle, b: torch.Tensor, x: torch.Tensor, nrhs=1, tol=1e-10, max_outer=500, restart=8,
+                allow_not_converged=False):
+    sp = mgdwf_solve_params(tol, max_outer, restart)
+    reps = (mgdwf_solve_report * nrhs)()
+    st = _lib.mgdwf_solve(h.h, _dev(b, h.nfine * nrhs, "b"), _dev(x, h.nfine * nrhs, "x"), nrhs, ctypes.byref(sp),
+                          reps)
+    _check(h.h, st, allow=(MGDWF_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+    return [r.as_dict() for r in reps]
+
+
+def mgdwf_cgne(h: Handle, b: torch.Tensor, x: torch.Tensor, tol=1e-10, max_iter=100000):
+    sp = mgdwf_solve_params(tol, max_iter, 1)
+    rep = mgdwf_solve_report()
+    _check(h.h, _lib.mgdwf_cgne(h.h, _dev(b, h.nfine, "b"), _dev(x, h.nfine, "x"), ctypes.byref(sp),
+                                ctypes.byref(rep)))
+    return rep.as_dict()
+
+
+def mgdwf_time_kernel(h: Handle, kernel: int, prec="f64", nrhs=1, iters=20) -> float:
+    ms = ctypes.c_double()
+    _check(h.h, _lib.mgdwf_time_kernel(h.h, kernel, PREC[prec], nrhs, iters, ctypes.byref(ms)))
+    return ms.value

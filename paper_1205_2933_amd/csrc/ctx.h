@@ -1,0 +1,43 @@
+// The library context behind an mgdwf_handle.
+#pragma once
+
+#include <map>
+#include <string>
+
+#include "mg_internal.h"
+#include "vecops.h"
+
+struct mgdwf_ctx {
+  mgdwf::Geometry g{};
+  double M5 = 0.0, mf = 0.0;
+  hipStream_t st = nullptr;
+  int device = 0;
+
+  mgdwf::DevBuf U64, U32;  // links, FP64 and FP32
+  bool have_gauge = false;
+
+  mgdwf::CoarseGeometry cg{};
+  bool have_basis = false, have_coarse = false;
+  mgdwf::DevBuf V64, V32;    // orthonormal basis, Nv fields
+  mgdwf::DevBuf Dc64, Dc32;  // coarse operator (internal column-major blocks)
+
+  mgdwf_mg_params mp{};
+  bool have_params = false;
+
+  std::map<std::string, mgdwf::DevBuf> ws;  // named workspaces, grown on demand
+  std::string err;
+
+  long long fine_applies = 0;    // per right-hand side, since the last reset
+  long long coarse_applies = 0;
+
+  // Workspace `name` with room for `count` elements of T (contents undefined).
+  template <class T>
+  T* buf(const std::string& name, size_t count) {
+    mgdwf::DevBuf& b = ws[name];
+    size_t need = count * sizeof(T);
+    if (b.bytes < need) b.alloc(need);
+    return b.as<T>();
+  }
+  long long fine_len() const { return 12LL * g.V5; }       // complex numbers per fine field
+  long long coarse_len() const { return (long long)cg.Vc * cg.n2; }
+};

@@ -1,0 +1,444 @@
+// Solvers: minimal-residual smoother, coarse CGNE, the two-level V-cycle,
+// flexible GCR with FP64 iterative refinement, the adaptive setup and the CGNE
+// control.  Host code that enqueues kernels on the handle's stream; scalars
+// stay on the device (slot table, see vecops.h) and the host reads them only
+// for stopping tests.
+//
+// Paper: Sec. 2 (V-cycle in five steps; adaptive setup on A x = 0; coarse
+// blocks over the whole fifth dimension), Sec. 3 (flexible GCR outer solver;
+// cost counted in fine-operator applications; CG on the squared operator as
+// the control).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "ctx.h"
+#include "solver.h"
+
+namespace mgdwf {
+
+namespace {
+
+// slot table (per right-hand side)
+constexpr int S_PP = 0, S_QQ = 1;                                 // MR smoother
+constexpr int S_CRR0 = 2, S_CRR_A = 3, S_CRR_B = 4, S_CPP = 5;    // coarse CGNE
+constexpr int S_DOT = 8;                                          // multidot block (<= 16 dots + 3)
+constexpr int S_QN = 48;                                          // |q_k|^2 at S_QN+k, <q_k, r> after it
+constexpr int S_RIN = 70, S_R64 = 71, S_B = 72, S_TMP = 73;       // FGCR residuals
+constexpr int S_GRR_A = 80, S_GRR_B = 81, S_GPAP = 82, S_G0 = 83; // CG on the normal equations
+
+template <class C2> struct Prec;
+template <> struct Prec<double2> { static constexpr const char* tag = "64"; };
+template <> struct Prec<float2> { static constexpr const char* tag = "32"; };
+
+std::vector<double> read_slots(mgdwf_ctx* c, int nrhs) {
+  std::vector<double> h((size_t)nrhs * NSLOT);
+  double* sl = c->buf<double>("slots", (size_t)nrhs * NSLOT);
+  MG_HIP(hipMemcpyAsync(h.data(), sl, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  MG_HIP(hipStreamSynchronize(c->st));
+  return h;
+}
+
+// Upload a table of device pointers (kept in a named workspace).
+template <class C2>
+const C2* const* ptr_table(mgdwf_ctx* c, const std::string& name, const std::vector<C2*>& ptrs) {
+  C2** d = c->buf<C2*>(name, std::max<size_t>(ptrs.size(), 1));
+  MG_HIP(hipMemcpyAsync(d, ptrs.data(), ptrs.size() * sizeof(C2*), hipMemcpyHostToDevice, c->st));
+  MG_HIP(hipStreamSynchronize(c->st));
+  return d;
+}
+
+// ---------------------------------------------------------------- fine ops
+template <class F2> const F2* gauge_of(mgdwf_ctx* c);
+template <> const double2* gauge_of<double2>(mgdwf_ctx* c) { return c->U64.as<double2>(); }
+template <> const float2* gauge_of<float2>(mgdwf_ctx* c) { return c->U32.as<float2>(); }
+template <class F2> const F2* basis_of(mgdwf_ctx* c);
+template <> const double2* basis_of<double2>(mgdwf_ctx* c) { return c->V64.as<double2>(); }
+template <> const float2* basis_of<float2>(mgdwf_ctx* c) { return c->V32.as<float2>(); }
+
+// out = D in (or D^+, or b - D in); optional |out|^2 into slot `dst`.
+template <class F2>
+void fine_op(mgdwf_ctx* c, const F2* in, F2* out, const F2* b, bool dag, int mode, int nrhs, int dst) {
+  double* partial = nullptr;
+  const int nb = dslash_nblocks(c->g);
+  if (dst >= 0) partial = c->buf<double>("dpart", (size_t)nb * nrhs);
+  dslash_ex<F2>(in, out, b, gauge_of<F2>(c), c->g, c->M5, c->mf, dag, mode, nrhs, partial, c->st);
+  if (dst >= 0) finalize_rhs(partial, nb, 1, c->buf<double>("slots", (size_t)nrhs * NSLOT), dst, nrhs, c->st);
+  c->fine_applies += 1;
+}
+
+// |v|^2 (and <v, w>) into slots dst, dst+1..2
+template <class C2>
+void norm_into(mgdwf_ctx* c, const C2* v, const C2* w, long long n, int nrhs, int dst) {
+  double* partial = c->buf<double>("vpart", (size_t)VEC_BLOCKS * nrhs * (2 * 16 + 3));
+  multidot_rhs<C2>(nullptr, 0, v, w, n, nrhs, partial, c->buf<double>("slots", (size_t)nrhs * NSLOT), dst, c->st);
+}
+
+template <class C2>
+void copy(mgdwf_ctx* c, const C2* in, C2* out, long long n) {
+  MG_HIP(hipMemcpyAsync(out, in, n * sizeof(C2), hipMemcpyDeviceToDevice, c->st));
+}
+
+// ---------------------------------------------------------------- V-cycle
+template <class F2, class M2>
+struct TwoLevel {
+  mgdwf_ctx* c;
+  int nrhs;
+  mgdwf_mg_params p;
+  const M2* Dc;
+  long long nf, nc;  // per-RHS lengths (complex numbers)
+  F2 *r1, *pp, *qq, *b3, *x3, *r3;
+  F2 *cb, *cx, *cr, *cp, *cq, *ct;  // coarse vectors (same real type as the fine level)
+  double* sl;
+  double* vpart;
+
+  TwoLevel(mgdwf_ctx* ctx, int n_rhs, const mgdwf_mg_params& prm, const M2* dc) : c(ctx), nrhs(n_rhs), p(prm), Dc(dc) {
+    nf = c->fine_len();
+    nc = c->coarse_len();
+    const std::string t = Prec<F2>::tag;
+    r1 = c->buf<F2>("vc_r1" + t, nf * nrhs);
+    pp = c->buf<F2>("vc_p" + t, nf * nrhs);
+    qq = c->buf<F2>("vc_q" + t, nf * nrhs);
+    b3 = c->buf<F2>("vc_b3" + t, nf * nrhs);
+    x3 = c->buf<F2>("vc_x3" + t, nf * nrhs);
+    r3 = c->buf<F2>("vc_r3" + t, nf * nrhs);
+    cb = c->buf<F2>("vc_cb" + t, nc * nrhs);
+    cx = c->buf<F2>("vc_cx" + t, nc * nrhs);
+    cr = c->buf<F2>("vc_cr" + t, nc * nrhs);
+    cp = c->buf<F2>("vc_cp" + t, nc * nrhs);
+    cq = c->buf<F2>("vc_cq" + t, nc * nrhs);
+    ct = c->buf<F2>("vc_ct" + t, nc * nrhs);
+    sl = c->buf<double>("slots", (size_t)nrhs * NSLOT);
+    vpart = c->buf<double>("vpart", (size_t)VEC_BLOCKS * nrhs * (2 * 16 + 3));
+  }
+
+  // nu steps of minimal residual along D^+ r on D x = b from x = 0.
+  void smooth(const F2* b, F2* x, F2* r, int nu) {
+    copy(c, b, r, nf * nrhs);
+    if (nu == 0) { zero<F2>(x, nf * nrhs, c->st); return; }
+    for (int i = 0; i < nu; ++i) {
+      fine_op<F2>(c, r, pp, nullptr, true, 0, nrhs, S_PP);   // p = D^+ r, |p|^2
+      fine_op<F2>(c, pp, qq, nullptr, false, 0, nrhs, S_QQ); // q = D p,   |q|^2
+      mr_update<F2>(x, r, pp, qq, nf, nrhs, sl, S_PP, S_QQ, i == 0, nullptr, c->st);
+    }
+  }
+
+  // CGNE on D_c: x = D_c^+ y with D_c D_c^+ y = b, to |r| < tol |b| or maxiter.
+  void coarse_solve(const F2* b, F2* x) {
+    const int check = 8;
+    copy(c, b, cr, nc * nrhs);
+    norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR0);
+    norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR_A);
+    coarse_apply<M2, F2>(Dc, cr, cp, true, c->cg, nrhs, c->st);
+    c->coarse_applies += 1;
+    norm_into<F2>(c, cp, nullptr, nc, nrhs, S_CPP);
+    int cur = S_CRR_A, nxt = S_CRR_B;
+    const double tol2 = p.coarse_tol * p.coarse_tol;
+    for (int it = 0; it < p.coarse_maxiter; ++it) {
+      coarse_apply<M2, F2>(Dc, cp, cq, false, c->cg, nrhs, c->st);
+      mr_update<F2>(x, cr, cp, cq, nc, nrhs, sl, cur, S_CPP, it == 0, vpart, c->st);
+      finalize_rhs(vpart, VEC_BLOCKS, 1, sl, nxt, nrhs, c->st);
+      coarse_apply<M2, F2>(Dc, cr, ct, true, c->cg, nrhs, c->st);
+      cg_dir<F2>(cp, ct, nc, nrhs, sl, nxt, cur, vpart, c->st);
+      finalize_rhs(vpart, VEC_BLOCKS, 1, sl, S_CPP, nrhs, c->st);
+      c->coarse_applies += 2;
+      std::swap(cur, nxt);
+      if ((it + 1) % check == 0 && it + 1 < p.coarse_maxiter) {
+        std::vector<double> h = read_slots(c, nrhs);
+        bool done = true;
+        for (int r = 0; r < nrhs; ++r)
+          if (!(h[r * NSLOT + cur] <= tol2 * h[r * NSLOT + S_CRR0])) done = false;
+        if (done) break;
+      }
+    }
+  }
+
+  // z = M b (the five steps of the paper's V-cycle)
+  void apply(const F2* b, F2* z) {
+    const F2* V = basis_of<F2>(c);
+    smooth(b, z, r1, p.nu_pre);                                          // x1 = S1^nu1(A, b), r1 = b - A x1
+    restrict_op<F2, F2>(V, r1, cb, c->buf<double>("rpart", restrict_partial_doubles(c->cg, nrhs)), c->g, c->cg,
+                        nrhs, c->st);                                    // b2 = R r1
+    coarse_solve(cb, cx);                                                // x2 = S2(RAP, b2)
+    prolong_op<F2, F2>(V, cx, z, true, c->g, c->cg, nrhs, c->st);       // x1 + P x2
+    if (p.nu_post > 0) {
+      fine_op<F2>(c, z, b3, b, false, 1, nrhs, -1);                      // b3 = b - A(P x2 + x1)
+      smooth(b3, x3, r3, p.nu_post);                                     // S3^nu3(A, b3)
+      add_to<F2, F2>(z, x3, nf * nrhs, c->st);
+    }
+  }
+};
+
+// ---------------------------------------------------------------- FGCR cycle
+// Up to `kmax` flexible GCR steps on D e = r (inner precision F2), e from 0.
+// Stops early when every |r|^2 <= stop2[rhs].  Returns the steps taken.
+template <class F2, class M2>
+int fgcr_cycle(mgdwf_ctx* c, TwoLevel<F2, M2>& M, F2* r, F2* e, int nrhs, int kmax, const std::vector<double>& stop2,
+               std::vector<double>* rin2_out) {
+  const long long nf = c->fine_len();
+  const std::string t = Prec<F2>::tag;
+  std::vector<F2*> Z(kmax), Q(kmax);
+  for (int k = 0; k < kmax; ++k) {
+    Z[k] = c->buf<F2>("gcr_z" + std::to_string(k) + t, nf * nrhs);
+    Q[k] = c->buf<F2>("gcr_q" + std::to_string(k) + t, nf * nrhs);
+  }
+  const F2* const* Zd = ptr_table<F2>(c, "ptrZ" + t, Z);
+  const F2* const* Qd = ptr_table<F2>(c, "ptrQ" + t, Q);
+  double* sl = c->buf<double>("slots", (size_t)nrhs * NSLOT);
+  double* vpart = c->buf<double>("vpart", (size_t)VEC_BLOCKS * nrhs * (2 * 16 + 3));
+  int k = 0;
+  for (; k < kmax; ++k) {
+    M.apply(r, Z[k]);                                           // z = M r
+    fine_op<F2>(c, Z[k], Q[k], nullptr, false, 0, nrhs, -1);    // q = D z
+    for (int pass = 0; pass < 2 && k > 0; ++pass) {             // classical Gram-Schmidt, twice
+      multidot_rhs<F2>(Qd, k, Q[k], nullptr, nf, nrhs, vpart, sl, S_DOT, c->st);
+      orth_update<F2>(Q[k], Z[k], Qd, Zd, k, nf, nrhs, sl, S_DOT, S_QN, c->st);
+    }
+    norm_into<F2>(c, Q[k], r, nf, nrhs, S_QN + k);              // |q_k|^2, <q_k, r>
+    gcr_update<F2>(e, r, Z[k], Q[k], nf, nrhs, sl, S_QN + k + 1, S_QN + k, k == 0, vpart, c->st);
+    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, S_RIN, nrhs, c->st);
+    std::vector<double> h = read_slots(c, nrhs);
+    bool done = true;
+    for (int rr = 0; rr < nrhs; ++rr) {
+      double v = h[rr * NSLOT + S_RIN];
+      if (!std::isfinite(v)) fail(MGDWF_ERR_NUMERIC, "non-finite residual in flexible GCR");
+      if (!(v <= stop2[rr])) done = false;
+    }
+    if (rin2_out) {
+      rin2_out->resize(nrhs);
+      for (int rr = 0; rr < nrhs; ++rr) (*rin2_out)[rr] = h[rr * NSLOT + S_RIN];
+    }
+    if (done) { ++k; break; }
+  }
+  return k;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- public (C++) API
+
+template <class F2, class M2>
+static void solve_impl(mgdwf_ctx* c, const M2* Dc, double2* b64, double2* x64, int nrhs, const mgdwf_solve_params& sp,
+                       mgdwf_solve_report* rep) {
+  const long long nf = c->fine_len();
+  double* sl = c->buf<double>("slots", (size_t)nrhs * NSLOT);
+  double2* r64 = c->buf<double2>("sol_r64", nf * nrhs);
+  F2* rin = c->buf<F2>(std::string("sol_rin") + Prec<F2>::tag, nf * nrhs);
+  F2* e = c->buf<F2>(std::string("sol_e") + Prec<F2>::tag, nf * nrhs);
+  TwoLevel<F2, M2> M(c, nrhs, c->mp, Dc);
+  const long long fa0 = c->fine_applies, ca0 = c->coarse_applies;
+  auto t0 = std::chrono::steady_clock::now();
+  norm_into<double2>(c, b64, nullptr, nf, nrhs, S_B);
+  std::vector<double> h = read_slots(c, nrhs);
+  std::vector<double> b2(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    b2[r] = h[r * NSLOT + S_B];
+    if (!std::isfinite(b2[r])) fail(MGDWF_ERR_NUMERIC, "non-finite right-hand side");
+  }
+  int outer = 0, restarts = 0;
+  std::vector<double> rel(nrhs, 0.0);
+  bool converged = false;
+  const int restart = std::max(1, std::min<int>(sp.restart, 16));
+  double best_prev = INFINITY;
+  int stall = 0;
+  uint32_t flags = 0;
+  while (true) {
+    fine_op<double2>(c, x64, r64, b64, false, 1, nrhs, S_R64);  // true residual, FP64
+    h = read_slots(c, nrhs);
+    converged = true;
+    double worst = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+      double rr = h[r * NSLOT + S_R64];
+      if (!std::isfinite(rr)) { flags |= 1u; fail(MGDWF_ERR_NUMERIC, "non-finite true residual"); }
+      rel[r] = b2[r] > 0 ? std::sqrt(rr / b2[r]) : 0.0;
+      if (!(rel[r] < sp.tol)) converged = false;
+      worst = std::max(worst, rel[r]);
+    }
+    if (converged || outer >= sp.max_outer) break;
+    if (worst >= 0.999 * best_prev) { if (++stall >= 3) { flags |= 2u; break; } } else stall = 0;
+    best_prev = std::min(best_prev, worst);
+    convert<double2, F2>(r64, rin, nf * nrhs, c->st);
+    std::vector<double> stop2(nrhs);
+    for (int r = 0; r < nrhs; ++r) stop2[r] = 0.25 * sp.tol * sp.tol * b2[r];
+    int kmax = std::min(restart, sp.max_outer - outer);
+    int k = fgcr_cycle<F2, M2>(c, M, rin, e, nrhs, kmax, stop2, nullptr);
+    add_to<F2, double2>(x64, e, nf * nrhs, c->st);
+    outer += k;
+    ++restarts;
+  }
+  double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rep)
+    for (int r = 0; r < nrhs; ++r) {
+      rep[r].outer_iters = outer;
+      rep[r].restarts = restarts;
+      rep[r].fine_applies = c->fine_applies - fa0;
+      rep[r].coarse_applies = c->coarse_applies - ca0;
+      rep[r].true_relres = rel[r];
+      rep[r].seconds = secs;
+      rep[r].flags = flags;
+    }
+  if (!converged) fail(MGDWF_ERR_NOT_CONVERGED, "solve did not reach the requested tolerance");
+}
+
+void mg_solve(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const mgdwf_solve_params& sp,
+              mgdwf_solve_report* rep) {
+  if (c->mp.fine_prec == MGDWF_F64) {
+    if (c->mp.coarse_prec != MGDWF_F64) fail(MGDWF_ERR_INVALID_ARG, "an FP64 fine level needs an FP64 coarse level");
+    solve_impl<double2, double2>(c, c->Dc64.as<double2>(), b64, x64, nrhs, sp, rep);
+  } else if (c->mp.fine_prec == MGDWF_F32) {
+    if (c->mp.coarse_prec == MGDWF_F32)
+      solve_impl<float2, float2>(c, c->Dc32.as<float2>(), b64, x64, nrhs, sp, rep);
+    else
+      fail(MGDWF_ERR_INVALID_ARG, "coarse precision not available for the FP32 fine level");
+  } else {
+    fail(MGDWF_ERR_INVALID_ARG, "fine precision must be F64 or F32");
+  }
+}
+
+// CG on D^+D x = 0 from x (nrhs vectors in place): the Krylov sweep of the setup.
+static void cgnr_null(mgdwf_ctx* c, double2* x, int nrhs, int iters) {
+  const long long nf = c->fine_len();
+  double* sl = c->buf<double>("slots", (size_t)nrhs * NSLOT);
+  double* vpart = c->buf<double>("vpart", (size_t)VEC_BLOCKS * nrhs * (2 * 16 + 3));
+  double2* r = c->buf<double2>("cg_r", nf * nrhs);
+  double2* p = c->buf<double2>("cg_p", nf * nrhs);
+  double2* t = c->buf<double2>("cg_t", nf * nrhs);
+  double2* Ap = c->buf<double2>("cg_ap", nf * nrhs);
+  double2* z = c->buf<double2>("cg_zero", nf * nrhs);
+  zero<double2>(z, nf * nrhs, c->st);
+  fine_op<double2>(c, x, t, nullptr, false, 0, nrhs, -1);
+  fine_op<double2>(c, t, r, z, true, 1, nrhs, S_GRR_A);  // r = -D^+ D x
+  copy(c, r, p, nf * nrhs);
+  int cur = S_GRR_A, nxt = S_GRR_B;
+  for (int i = 0; i < iters; ++i) {
+    fine_op<double2>(c, p, t, nullptr, false, 0, nrhs, S_GPAP);  // t = D p, <p, D^+D p> = |t|^2
+    fine_op<double2>(c, t, Ap, nullptr, true, 0, nrhs, -1);
+    mr_update<double2>(x, r, p, Ap, nf, nrhs, sl, cur, S_GPAP, false, vpart, c->st);
+    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, nxt, nrhs, c->st);
+    cg_dir<double2>(p, r, nf, nrhs, sl, nxt, cur, nullptr, c->st);
+    std::swap(cur, nxt);
+  }
+}
+
+static void normalise(mgdwf_ctx* c, double2* v, int nrhs) {
+  const long long nf = c->fine_len();
+  norm_into<double2>(c, v, nullptr, nf, nrhs, S_TMP);
+  scale_by_rsqrt_slot<double2>(v, v, nf, nrhs, c->buf<double>("slots", (size_t)nrhs * NSLOT), S_TMP, c->st);
+}
+
+static double median_null_residual(mgdwf_ctx* c, double2* v, int nrhs) {
+  const long long nf = c->fine_len();
+  double2* t = c->buf<double2>("cg_t", nf * nrhs);
+  fine_op<double2>(c, v, t, nullptr, false, 0, nrhs, S_TMP + 3);  // |D v|^2
+  norm_into<double2>(c, v, nullptr, nf, nrhs, S_TMP);              // |v|^2 (+ two scratch slots)
+  std::vector<double> h = read_slots(c, nrhs);
+  std::vector<double> q(nrhs);
+  for (int r = 0; r < nrhs; ++r) q[r] = std::sqrt(h[r * NSLOT + S_TMP + 3] / h[r * NSLOT + S_TMP]);
+  std::sort(q.begin(), q.end());
+  return nrhs % 2 ? q[nrhs / 2] : 0.5 * (q[nrhs / 2 - 1] + q[nrhs / 2]);
+}
+
+void install_basis(mgdwf_ctx* c, const int block[4], int nvec);  // capi.cpp
+void build_coarse(mgdwf_ctx* c);                                 // capi.cpp
+
+// Adaptive setup (paper Sec. 2): W holds nh = nvec/2 internal FP64 fields on entry.
+void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_report* rep) {
+  const int nh = p.nvec / 2;
+  const long long nf = c->fine_len();
+  auto t0 = std::chrono::steady_clock::now();
+  int nsw = 0;
+  cgnr_null(c, W, nh, p.sweep0_iters);
+  normalise(c, W, nh);
+  auto rebuild = [&]() {
+    // basis fields: the nh vectors and their fifth-dimension reflections
+    c->cg.Nv = p.nvec;
+    double2* V = c->buf<double2>("setup_vfull", nf * p.nvec);
+    copy(c, W, V, nf * nh);
+    reflect5<double2>(W, V + nf * nh, c->g, nh, c->st);
+    c->V64.alloc(nf * p.nvec * sizeof(double2));
+    copy(c, V, c->V64.as<double2>(), nf * p.nvec);
+    install_basis(c, p.block, p.nvec);
+    build_coarse(c);
+  };
+  rebuild();
+  if (rep) rep->null_residual[nsw] = median_null_residual(c, W, nh);
+  ++nsw;
+  mgdwf_mg_params sweep = p;
+  sweep.fine_prec = MGDWF_F64;
+  sweep.coarse_prec = MGDWF_F64;
+  for (int s = 1; s < p.sweeps; ++s) {
+    // inverse iteration: W <- (approximately) D^{-1} W with the current MG
+    TwoLevel<double2, double2> M(c, nh, sweep, c->Dc64.as<double2>());
+    double2* r = c->buf<double2>("setup_r", nf * nh);
+    double2* e = c->buf<double2>("setup_e", nf * nh);
+    copy(c, W, r, nf * nh);
+    std::vector<double> stop2(nh, -1.0);
+    fgcr_cycle<double2, double2>(c, M, r, e, nh, std::max(1, std::min(p.sweep_iters, 16)), stop2, nullptr);
+    copy(c, e, W, nf * nh);
+    normalise(c, W, nh);
+    rebuild();
+    if (rep && nsw < 8) rep->null_residual[nsw] = median_null_residual(c, W, nh);
+    ++nsw;
+  }
+  c->mp = p;
+  c->have_params = true;
+  if (rep) {
+    rep->sweeps_done = nsw;
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+}
+
+// CGNE control (paper Sec. 3): CG on D D^+ y = b, x = D^+ y, FP64.
+void cgne_solve(mgdwf_ctx* c, double2* b, double2* x, const mgdwf_solve_params& sp, mgdwf_solve_report* rep) {
+  const long long nf = c->fine_len();
+  const int nrhs = 1;
+  double* sl = c->buf<double>("slots", (size_t)nrhs * NSLOT);
+  double* vpart = c->buf<double>("vpart", (size_t)VEC_BLOCKS * nrhs * (2 * 16 + 3));
+  double2* r = c->buf<double2>("cg_r", nf);
+  double2* p = c->buf<double2>("cg_p", nf);
+  double2* q = c->buf<double2>("cg_t", nf);
+  const long long fa0 = c->fine_applies;
+  auto t0 = std::chrono::steady_clock::now();
+  norm_into<double2>(c, b, nullptr, nf, 1, S_B);
+  fine_op<double2>(c, x, r, b, false, 1, 1, S_GRR_A);       // r = b - D x
+  fine_op<double2>(c, r, p, nullptr, true, 0, 1, S_GPAP);   // p = D^+ r
+  int cur = S_GRR_A, nxt = S_GRR_B;
+  int it = 0;
+  double rel = 1.0;
+  const int check = 16;
+  std::vector<double> h = read_slots(c, 1);
+  const double bb = h[S_B];
+  rel = bb > 0 ? std::sqrt(h[S_GRR_A] / bb) : 0.0;
+  while (it < sp.max_outer && rel >= sp.tol) {
+    fine_op<double2>(c, p, q, nullptr, false, 0, 1, -1);      // q = D p
+    mr_update<double2>(x, r, p, q, nf, 1, sl, cur, S_GPAP, false, vpart, c->st);
+    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, nxt, 1, c->st);
+    double2* t = c->buf<double2>("cg_ap", nf);
+    fine_op<double2>(c, r, t, nullptr, true, 0, 1, -1);       // t = D^+ r
+    cg_dir<double2>(p, t, nf, 1, sl, nxt, cur, vpart, c->st);
+    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, S_GPAP, 1, c->st);
+    std::swap(cur, nxt);
+    ++it;
+    if (it % check == 0) {
+      h = read_slots(c, 1);
+      rel = std::sqrt(h[cur] / bb);
+      if (!std::isfinite(rel)) fail(MGDWF_ERR_NUMERIC, "non-finite residual in CGNE");
+    }
+  }
+  fine_op<double2>(c, x, r, b, false, 1, 1, S_R64);
+  h = read_slots(c, 1);
+  double tr = bb > 0 ? std::sqrt(h[S_R64] / bb) : 0.0;
+  if (rep) {
+    rep->outer_iters = it;
+    rep->restarts = 0;
+    rep->fine_applies = c->fine_applies - fa0;
+    rep->coarse_applies = 0;
+    rep->true_relres = tr;
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rep->flags = 0;
+  }
+  if (!(tr < sp.tol)) fail(MGDWF_ERR_NOT_CONVERGED, "CGNE did not reach the requested tolerance");
+}
+
+}  // namespace mgdwf

@@ -1,0 +1,64 @@
+// Host wrappers of the solver vector kernels (vecops.hip).
+#pragma once
+
+#include "mg_internal.h"
+
+namespace mgdwf {
+
+constexpr int NSLOT = 96;        // scalar slots per right-hand side
+constexpr int VEC_BLOCKS = 1024; // workgroups of the grid-stride vector kernels (partials per RHS)
+
+void finalize_rhs(const double* partial, int nparts, int ncomp, double* sl, int dst, int nrhs, hipStream_t st);
+
+template <class C2>
+void mr_update(C2* x, C2* r, const C2* p, const C2* q, long long n, int nrhs, const double* sl, int num, int den,
+               bool first, double* partial, hipStream_t st);
+template <class C2>
+void cg_dir(C2* p, const C2* r, long long n, int nrhs, const double* sl, int num, int den, double* partial,
+            hipStream_t st);
+template <class C2>
+void multidot_rhs(const C2* const* avec, int nv, const C2* b, const C2* c, long long n, int nrhs, double* partial,
+                  double* sl, int dst, hipStream_t st);
+template <class C2>
+void orth_update(C2* q, C2* z, const C2* const* qs, const C2* const* zs, int nv, long long n, int nrhs,
+                 const double* sl, int dots, int nrm, hipStream_t st);
+template <class C2>
+void gcr_update(C2* e, C2* r, const C2* z, const C2* q, long long n, int nrhs, const double* sl, int cr, int nq,
+                bool first, double* partial, hipStream_t st);
+template <class C2>
+void scale_by_rsqrt_slot(C2* y, const C2* x, long long n, int nrhs, const double* sl, int den, hipStream_t st);
+template <class A2, class B2>
+void convert(const A2* in, B2* out, long long n, hipStream_t st);
+template <class A2, class B2>
+void add_to(B2* y, const A2* x, long long n, hipStream_t st);
+template <class C2>
+void zero(C2* y, long long n, hipStream_t st);
+template <class C2>
+void reflect5(const C2* in, C2* out, const Geometry& g, int nf, hipStream_t st);
+
+// dslash.hip
+int dslash_nblocks(const Geometry& g);
+template <class C2>
+void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geometry& g, double M5, double mf,
+               bool dagger, int mode, int nrhs, double* partial, hipStream_t st);
+
+// transfer.hip
+size_t restrict_partial_doubles(const CoarseGeometry& cg, int nrhs);
+template <class C2, class CC2>
+void restrict_op(const C2* V, const C2* x, CC2* coarse, double* partial, const Geometry& g,
+                 const CoarseGeometry& cg, int nrhs, hipStream_t st);
+template <class C2, class CC2>
+void prolong_op(const C2* V, const CC2* coarse, C2* fine, bool accumulate, const Geometry& g,
+                const CoarseGeometry& cg, int nrhs, hipStream_t st);
+bool orthonormalise_basis(double2* V, const Geometry& g, const CoarseGeometry& cg, hipStream_t st);
+
+// coarse.hip
+void build_coarse_op(const double2* Vhat, const double2* gauge, double2* Dc, double2* work9, double2* cwork,
+                     double* partial, const Geometry& g, const CoarseGeometry& cg, double M5, double mf,
+                     hipStream_t st);
+void coarse_to_f32(const double2* Dc64, float2* Dc32, long long n, hipStream_t st);
+template <class MC2, class VC2>
+void coarse_apply(const MC2* Dc, const VC2* x, VC2* y, bool dagger, const CoarseGeometry& cg, int nrhs,
+                  hipStream_t st);
+
+}  // namespace mgdwf

@@ -1,0 +1,58 @@
+"""GPU multigrid solve: setup + flexible GCR to a true FP64 residual of 1e-10.
+
+The stopping test is checked independently with the oracle's operator on the
+host (paper Sec. 3: V-cycle-preconditioned flexible GCR; the bar 1e-10 is the
+true residual |b - D x| / |b| in FP64).
+"""
+import numpy as np
+import pytest
+import torch
+
+from inputs import gaussian_fermion, prepare_gauge, random_starts
+from oracle import dwf
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mg_solve_c1(cuda, prec):
+    import paper_1205_2933_amd as mg
+    L, Ls, mf = (4, 4, 4, 4), 8, 0.01
+    U = prepare_gauge(L, 0.3, 11)
+    h = mg.Handle(L, Ls, 1.8, mf)
+    mg.mgdwf_set_gauge(h, dev(U))
+    p = mg.make_mg_params((2, 2, 2, 2), 16, sweeps=1, sweep0_iters=100, sweep_iters=4, coarse_tol=0.1,
+                          coarse_maxiter=200, fine_prec=prec, coarse_prec=prec)
+    print(f"setup C1 {prec}", flush=True)
+    rep = mg.mgdwf_setup(h, p, dev(random_starts(L, Ls, 8, 21)))
+    print("setup report", rep, flush=True)
+    b = gaussian_fermion(L, Ls, 31)
+    x = torch.zeros_like(dev(b))
+    reps = mg.mgdwf_solve(h, dev(b), x, tol=1e-10, max_outer=400, restart=8)
+    print("solve report", reps, flush=True)
+    xs = x.cpu().numpy()
+    r = b - dwf.apply_dwf(xs, U, 1.8, mf)
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-10
+    assert reps[0]["true_relres"] < 1e-10
+
+
+def test_cgne_control(cuda):
+    import paper_1205_2933_amd as mg
+    L, Ls, mf = (4, 4, 4, 4), 8, 0.01
+    U = prepare_gauge(L, 0.3, 11)
+    h = mg.Handle(L, Ls, 1.8, mf)
+    mg.mgdwf_set_gauge(h, dev(U))
+    b = gaussian_fermion(L, Ls, 31)
+    x = torch.zeros_like(dev(b))
+    rep = mg.mgdwf_cgne(h, dev(b), x, tol=1e-10)
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(b - dwf.apply_dwf(xs, U, 1.8, mf)) / np.linalg.norm(b) < 1e-10
+    # the oracle's CGNE takes the same number of iterations up to rounding (+-3%)
+    from oracle import solvers
+    A = dwf.DWF(U, 1.8, mf)
+    _, orep = solvers.cgne(A, b, 1e-10, 5000)
+    assert abs(rep["outer_iters"] - orep.iters) <= max(16, 0.03 * orep.iters)
