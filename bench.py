@@ -1,0 +1,219 @@
+"""Benchmark: seconds per right-hand side to |b - D x| / |b| < 1e-10 (FP64 true
+residual) for the domain-wall operator on a 16^3 x 32 x Ls=16 lattice at
+m_f = 0.001, with the two-level adaptive multigrid of the library.
+
+One step = one mixed-precision multi-RHS solve of the 12 spin-colour point
+sources (FP32 fine level and coarse level inside the V-cycle, FP64 flexible
+GCR refinement).  The FP64 plain-MG time per RHS, the Dslash bandwidth and the
+setup time are measured in the same run.  Inputs are synthetic and seeded:
+SU(3) links U = exp(i 0.3 H) smoothed by two APE-style steps (seed 12),
+near-null starts seed 21.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+L = (16, 16, 16, 32)
+LS = 16
+M5 = 1.8
+MF = 0.001
+BLOCK = (4, 4, 4, 4)
+NVEC = 24
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def mg_params(mg, fine, coarse):
+    return mg.make_mg_params(BLOCK, NVEC, sweeps=1, sweep0_iters=400, sweep_iters=4, nu_pre=8, nu_post=8,
+                             coarse_tol=0.1, coarse_maxiter=400, fine_prec=fine, coarse_prec=coarse)
+
+
+def cpu_baseline(counts):
+    """Oracle (numpy FP64) per-operation times on this host, combined with the GPU
+    run's per-RHS operation counts into seconds per RHS solve (extrapolated)."""
+    import numpy as np
+
+    from inputs import gaussian_fermion, random_starts, random_su3_field
+    from oracle import coarse as oc
+    from oracle import dwf
+    from oracle import transfer as ot
+
+    threads = os.environ.get("OMP_NUM_THREADS")
+    U = random_su3_field(L, 0.3, 12)
+    psi = gaussian_fermion(L, LS, 1)
+    t = time.perf_counter()
+    dwf.apply_dwf(psi, U, M5, MF)
+    t_dslash = time.perf_counter() - t
+    del psi
+    # R and P are block local: time them on one eighth of the lattice (16^3 x 4) and scale by 8
+    Ls_ = (16, 16, 16, 4)
+    V = random_starts(Ls_, LS, NVEC, 21)
+    x = gaussian_fermion(Ls_, LS, 2)
+    Vh = V  # R and P cost the same on any basis of this shape
+    t = time.perf_counter()
+    c = ot.restrict(x, Vh, BLOCK)
+    t_r = (time.perf_counter() - t) * 8
+    t = time.perf_counter()
+    ot.prolong(c, Vh, BLOCK)
+    t_p = (time.perf_counter() - t) * 8
+    del V, x, Vh
+    Lc = tuple(L[m] // BLOCK[m] for m in range(4))
+    rng = np.random.default_rng(3)
+    Dc = rng.standard_normal(Lc[::-1] + (9, 2 * NVEC, 2 * NVEC)) + 0j
+    cv = rng.standard_normal(Lc[::-1] + (2, NVEC)) + 0j
+    t = time.perf_counter()
+    oc.apply_coarse(cv, Dc)
+    t_c = time.perf_counter() - t
+    per_rhs = (counts["fine"] * t_dslash + counts["vcycles"] * (t_r + t_p) + counts["coarse"] * t_c)
+    return {
+        "value": per_rhs, "unit": "s per RHS to 1e-10 (extrapolated)", "cores": int(threads) if threads else os.cpu_count(),
+        "kind": "oracle",
+        "sample": (f"oracle Dslash at full size ({t_dslash:.2f} s), R/P on a 16^3x4x16 slab x8 ({t_r:.2f}/{t_p:.2f} s), "
+                   f"coarse apply ({t_c:.3f} s), times the GPU per-RHS counts: {counts['fine']} D applications, "
+                   f"{counts['vcycles']} V-cycles, {counts['coarse']} coarse applications"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-solves", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1205_2933_amd as mg
+    from inputs import point_sources, prepare_gauge, random_starts
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    U = prepare_gauge(L, 0.3, 12, ape_steps=2)
+    log(f"inputs ready ({time.perf_counter() - t0:.1f} s)")
+    h = mg.Handle(L, LS, M5, MF)
+    mg.mgdwf_set_gauge(h, torch.from_numpy(U).to(dev))
+    V0 = torch.from_numpy(random_starts(L, LS, NVEC // 2, 21)).to(dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    srep = mg.mgdwf_setup(h, mg_params(mg, "f64", "f64"), V0)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    del V0
+    log(f"setup {setup_s:.2f} s, null residual {srep['null_residual']}")
+
+    nrhs = 12
+    B = torch.from_numpy(point_sources(L, LS)).to(dev)
+    X = torch.zeros_like(B)
+
+    # ---- mixed precision, 12 right-hand sides per step
+    mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f32"))
+
+    def step():
+        X.zero_()
+        return mg.mgdwf_solve(h, B, X, nrhs=nrhs, tol=1e-10, max_outer=400, restart=8)
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup step {i} done")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = None
+    for i in range(args.steps):
+        reps = step()
+        log(f"timed step {i} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    ms_per_step = 1e3 * elapsed / args.steps
+    worst = max(r["true_relres"] for r in reps)
+    assert worst < 1e-10, worst
+    s_per_rhs = elapsed / args.steps / nrhs
+
+    # ---- plain FP64 MG, single RHS (a sample of the same source set)
+    mg.mgdwf_set_mg_params(h, mg_params(mg, "f64", "f64"))
+    fp64_times, fp64_iters = [], []
+    for j in range(args.fp64_solves):
+        x1 = torch.zeros_like(B[j])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = mg.mgdwf_solve(h, B[j].contiguous(), x1, nrhs=1, tol=1e-10, max_outer=400, restart=8)[0]
+        torch.cuda.synchronize()
+        fp64_times.append(time.perf_counter() - t)
+        fp64_iters.append(r["outer_iters"])
+        log(f"fp64 solve {j}: {fp64_times[-1]:.2f} s, {r['outer_iters']} iterations")
+
+    # ---- Dslash bandwidth (HIP events on the library stream) and roofline
+    V4 = int(np.prod(L))
+    bytes64 = 2 * 12 * V4 * LS * 16 + 36 * V4 * 16
+    ms64 = mg.mgdwf_time_kernel(h, mg.MGDWF_K_DSLASH, "f64", 1, 50)
+    ms32 = mg.mgdwf_time_kernel(h, mg.MGDWF_K_DSLASH, "f32", 1, 50)
+    gbs64 = bytes64 / (ms64 * 1e-3) / 1e9
+    gbs32 = bytes64 / 2 / (ms32 * 1e-3) / 1e9
+    msR = mg.mgdwf_time_kernel(h, mg.MGDWF_K_RESTRICT, "f32", 1, 10)
+    msP = mg.mgdwf_time_kernel(h, mg.MGDWF_K_PROLONG, "f32", 1, 10)
+    msC = mg.mgdwf_time_kernel(h, mg.MGDWF_K_COARSE, "f32", 1, 50)
+    rp_bytes32 = (NVEC + 1) * 12 * V4 * LS * 8
+
+    r0 = reps[0]
+    counts = {"fine": int(r0["fine_applies"]), "vcycles": int(r0["outer_iters"]), "coarse": int(r0["coarse_applies"])}
+    out = {
+        "metric": "s to ||r||/||b||<1e-10, 16^3x32xLs16 m=0.001 (mixed+MRHS vs FP64); Dslash GB/s",
+        "value": s_per_rhs,
+        "unit": "s per RHS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 V-cycle / f64 outer",
+        "data": "synthetic",
+        "config": {"workload": "DWF MG solve, 16^3x32 Ls=16 M5=1.8 m_f=0.001, SU(3) eps=0.3 + 2 APE, "
+                               "12 point sources per step, blocks 4^4, Nv=24 (12 + reflections)",
+                   "nrhs": nrhs, "tol": 1e-10},
+        "rhs_per_s": 1.0 / s_per_rhs,
+        "fp64_mg_s_per_rhs": float(np.mean(fp64_times)),
+        "fp64_mg_outer_iters": fp64_iters,
+        "mixed_over_fp64_speedup": float(np.mean(fp64_times)) / s_per_rhs,
+        "mixed_outer_iters": int(r0["outer_iters"]),
+        "mixed_fine_applies_per_rhs": counts["fine"],
+        "max_true_relres": worst,
+        "setup_s": setup_s,
+        "null_residual": srep["null_residual"],
+        "dslash": {"f64_us": ms64 * 1e3, "f64_GBs": gbs64, "f32_us": ms32 * 1e3, "f32_GBs": gbs32,
+                   "f64_frac_peak": gbs64 / HBM_PEAK_GBS, "f32_frac_peak": gbs32 / HBM_PEAK_GBS},
+        "restrict_f32_GBs": rp_bytes32 / (msR * 1e-3) / 1e9,
+        "prolong_f32_GBs": rp_bytes32 / (msP * 1e-3) / 1e9,
+        "coarse_apply_f32_us": msC * 1e3,
+        "roofline": {"bound": "hbm", "kernel": "dslash f32", "achieved": gbs32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs32 / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(counts)
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

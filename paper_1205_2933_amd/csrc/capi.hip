@@ -91,14 +91,13 @@ void build_coarse(mgdwf_ctx* c) {
   need(c->have_basis, MGDWF_ERR_STATE, "no basis installed");
   const CoarseGeometry& cg = c->cg;
   const long long ndc = (long long)cg.Vc * 9 * cg.n2 * cg.n2;
-  c->Dc64.alloc(ndc * sizeof(double2));
+  c->Dc.m64.alloc(ndc * sizeof(double2));
   double2* work9 = c->buf<double2>("dc_work9", 9 * c->fine_len());
   double2* cwork = c->buf<double2>("dc_cwork", 9LL * cg.Vc * cg.n2);
   double* partial = c->buf<double>("dc_partial", restrict_partial_doubles(cg, 9));
-  build_coarse_op(c->V64.as<double2>(), c->U64.as<double2>(), c->Dc64.as<double2>(), work9, cwork, partial, c->g, cg,
-                  c->M5, c->mf, c->st);
-  c->Dc32.alloc(ndc * sizeof(float2));
-  coarse_to_f32(c->Dc64.as<double2>(), c->Dc32.as<float2>(), ndc, c->st);
+  build_coarse_op(c->V64.as<double2>(), c->U64.as<double2>(), c->Dc.m64.as<double2>(), work9, cwork, partial, c->g,
+                  cg, c->M5, c->mf, c->st);
+  finish_coarse_op(c->Dc, c->DcH, cg, c->st);
   MG_HIP(hipStreamSynchronize(c->st));
   // the build workspaces are large; give them back
   c->ws.erase("dc_work9");
@@ -262,7 +261,7 @@ mgdwf_status mgdwf_get_coarse_op(mgdwf_handle h, double* Dc) {
     need(h->have_coarse, MGDWF_ERR_STATE, "coarse operator not built");
     long long nblk = 9LL * h->cg.Vc;
     long long tot = nblk * h->cg.n2 * h->cg.n2;
-    hipLaunchKernelGGL(k_dc_canonical, dim3(ceil_div(tot, 256)), dim3(256), 0, h->st, h->Dc64.as<double2>(),
+    hipLaunchKernelGGL(k_dc_canonical, dim3(ceil_div(tot, 256)), dim3(256), 0, h->st, h->Dc.m64.as<double2>(),
                        reinterpret_cast<double2*>(Dc), nblk, h->cg.n2);
     MG_LAUNCH_CHECK();
     MG_HIP(hipStreamSynchronize(h->st));
@@ -275,18 +274,17 @@ mgdwf_status mgdwf_apply_coarse(mgdwf_handle h, const double* in, double* out, i
   return guarded(h, [&] {
     need(in && out && nrhs >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
     need(h->have_coarse, MGDWF_ERR_STATE, "coarse operator not built");
+    need(prec >= MGDWF_F64 && prec <= MGDWF_BF16, MGDWF_ERR_INVALID_ARG, "bad coarse precision");
     const long long n = h->coarse_len() * nrhs;
+    const CoarseStore& s = dagger ? h->DcH : h->Dc;
     if (prec == MGDWF_F64) {
-      coarse_apply<double2, double2>(h->Dc64.as<double2>(), reinterpret_cast<const double2*>(in),
-                                     reinterpret_cast<double2*>(out), dagger != 0, h->cg, nrhs, h->st);
-    } else if (prec == MGDWF_F32) {
+      coarse_apply64(s, reinterpret_cast<const double2*>(in), reinterpret_cast<double2*>(out), h->cg, nrhs, h->st);
+    } else {
       float2* a = h->buf<float2>("cio_a32", n);
       float2* b = h->buf<float2>("cio_b32", n);
       convert<double2, float2>(reinterpret_cast<const double2*>(in), a, n, h->st);
-      coarse_apply<float2, float2>(h->Dc32.as<float2>(), a, b, dagger != 0, h->cg, nrhs, h->st);
+      coarse_apply32(s, prec, a, b, h->cg, nrhs, h->buf<char>("cio_pack", coarse_pack_bytes(h->cg, nrhs)), h->st);
       convert<float2, double2>(b, reinterpret_cast<double2*>(out), n, h->st);
-    } else {
-      fail(MGDWF_ERR_INVALID_ARG, "coarse precision not available");
     }
   });
 }
@@ -371,7 +369,10 @@ mgdwf_status mgdwf_time_kernel(mgdwf_handle h, mgdwf_kernel k, mgdwf_prec prec, 
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     need(ms && iters >= 1 && nrhs >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
-    check_prec_fine(prec);
+    if (k == MGDWF_K_COARSE)
+      need(prec >= MGDWF_F64 && prec <= MGDWF_BF16, MGDWF_ERR_INVALID_ARG, "bad coarse precision");
+    else
+      check_prec_fine(prec);
     need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
     const long long nf = h->fine_len() * nrhs;
     hipEvent_t e0, e1;
@@ -407,11 +408,10 @@ mgdwf_status mgdwf_time_kernel(mgdwf_handle h, mgdwf_kernel k, mgdwf_prec prec, 
                                          false, h->g, h->cg, nrhs, h->st);
           } else if (k == MGDWF_K_COARSE) {
             if (prec == MGDWF_F64)
-              coarse_apply<double2, double2>(h->Dc64.as<double2>(), h->buf<double2>("t_c", nc),
-                                             h->buf<double2>("t_d", nc), false, h->cg, nrhs, h->st);
+              coarse_apply64(h->Dc, h->buf<double2>("t_c", nc), h->buf<double2>("t_d", nc), h->cg, nrhs, h->st);
             else
-              coarse_apply<float2, float2>(h->Dc32.as<float2>(), h->buf<float2>("t_c32", nc),
-                                           h->buf<float2>("t_d32", nc), false, h->cg, nrhs, h->st);
+              coarse_apply32(h->Dc, prec, h->buf<float2>("t_c32", nc), h->buf<float2>("t_d32", nc), h->cg, nrhs,
+                             h->buf<char>("t_pack", coarse_pack_bytes(h->cg, nrhs)), h->st);
           } else {
             fail(MGDWF_ERR_INVALID_ARG, "unknown kernel id");
           }

@@ -51,6 +51,16 @@ struct CoarseArgs {
   int n2;
 };
 
+CoarseArgs coarse_args(const CoarseGeometry& cg) {
+  CoarseArgs a;
+  for (int m = 0; m < 4; ++m) a.Lc[m] = cg.Lc[m];
+  a.Vc = cg.Vc;
+  a.n2 = cg.n2;
+  return a;
+}
+
+__device__ __forceinline__ int opposite(int d) { return d == 0 ? 0 : (((d - 1) ^ 1) + 1); }
+
 __device__ __forceinline__ int coarse_neighbour(const CoarseArgs& a, int X, int d) {
   if (d == 0) return X;
   const int mu = (d - 1) >> 1;
@@ -64,56 +74,212 @@ __device__ __forceinline__ int coarse_neighbour(const CoarseArgs& a, int X, int 
   return ((c[3] * a.Lc[2] + c[2]) * a.Lc[1] + c[1]) * a.Lc[0] + c[0];
 }
 
-// y = D_c x (DAG false) or D_c^+ x; one workgroup (4 wavefronts) per coarse
-// site and RHS; wavefront w handles d = w, w+4, w+8; lane = output row.
-// Accumulation in FP64 for double2, FP32 for float2.
-template <class MC2, class VC2, bool DAG>
-__global__ __launch_bounds__(256) void k_coarse_apply(const MC2* __restrict__ Dc, const VC2* __restrict__ x,
-                                                      VC2* __restrict__ y, CoarseArgs a) {
+// Adjoint stencil in the same form as D_c: (D_c^+ y)(X) = sum_e DcH[X][e] y(X + delta_e)
+// with DcH[X][e] = Dc[X + delta_e][opposite(e)]^+.  Column-major blocks on both sides.
+__global__ void k_adjoint_blocks(const double2* __restrict__ Dc, double2* __restrict__ DcH, CoarseArgs a) {
+  const int blk = blockIdx.x;  // X * 9 + e
+  const int X = blk / 9, e = blk % 9;
+  const int Y = coarse_neighbour(a, X, e);
+  const int n2 = a.n2;
+  const double2* src = Dc + ((long long)Y * 9 + opposite(e)) * n2 * n2;
+  double2* dst = DcH + (long long)blk * n2 * n2;
+  for (int i = threadIdx.x; i < n2 * n2; i += blockDim.x) {
+    const int r = i % n2, c = i / n2;           // dst element (r, c), column major
+    const double2 v = src[(long long)r * n2 + c]; // src element (c, r)
+    dst[i] = make_double2(v.x, -v.y);
+  }
+}
+
+// y[rhs] = sum_d M[X][d] x[rhs](X + delta_d) for up to NR right-hand sides, each
+// block read once for all of them.  Workgroup = one coarse site, 4 wavefronts;
+// wavefront w takes d = w, w+4, w+8; lane = output row; partial sums of the
+// four wavefronts are added in a fixed order through LDS.
+template <class MC2, class VC2, int NR>
+__global__ __launch_bounds__(256) void k_capply(const MC2* __restrict__ M, const VC2* __restrict__ x,
+                                                VC2* __restrict__ y, CoarseArgs a, int nrhs, int rhs0) {
   using T = typename real_of<VC2>::type;
-  __shared__ T red[4][64][2];
-  const int X = blockIdx.x, rhs = blockIdx.y;
+  __shared__ T red[4][NR][64][2];
+  const int X = blockIdx.x;
   const int n2 = a.n2;
   const int w = threadIdx.x >> 6, row = threadIdx.x & 63;
-  const long long voff = (long long)rhs * a.Vc * n2;
-  VC2 acc = cmk<VC2>(0, 0);
+  const int nr = min(NR, nrhs - rhs0);
+  const long long vs = (long long)a.Vc * n2;  // RHS stride
+  VC2 acc[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) acc[j] = cmk<VC2>(0, 0);
   if (row < n2) {
     for (int d = w; d < 9; d += 4) {
-      if (!DAG) {
-        const int Y = coarse_neighbour(a, X, d);
-        const MC2* M = Dc + ((long long)X * 9 + d) * n2 * n2;
-        const VC2* xv = x + voff + (long long)Y * n2;
-        for (int c = 0; c < n2; ++c) {
-          MC2 m = M[c * n2 + row];
-          cfma(acc, cmk<VC2>((T)m.x, (T)m.y), xv[c]);
-        }
-      } else {
-        // (D_c^+ x)(X) = sum_d Dc[X - delta_d][d]^+ x(X - delta_d)
-        const int dopp = (d == 0) ? 0 : (((d - 1) ^ 1) + 1);
-        const int Y = coarse_neighbour(a, X, dopp);
-        const MC2* M = Dc + ((long long)Y * 9 + d) * n2 * n2;
-        const VC2* xv = x + voff + (long long)Y * n2;
-        for (int c = 0; c < n2; ++c) {
-          MC2 m = M[row * n2 + c];  // element (c, row) of Dc[Y][d]
-          cfmac(acc, cmk<VC2>((T)m.x, (T)m.y), xv[c]);
-        }
+      const int Y = coarse_neighbour(a, X, d);
+      const MC2* Md = M + ((long long)X * 9 + d) * n2 * n2;
+      const VC2* xv = x + (long long)rhs0 * vs + (long long)Y * n2;
+      for (int c = 0; c < n2; ++c) {
+        const MC2 m = Md[c * n2 + row];
+        const VC2 mv = cmk<VC2>((T)m.x, (T)m.y);
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+          if (j < nr) cfma(acc[j], mv, xv[j * vs + c]);
       }
     }
   }
-  red[w][row][0] = acc.x;
-  red[w][row][1] = acc.y;
+#pragma unroll
+  for (int j = 0; j < NR; ++j) { red[w][j][row][0] = acc[j].x; red[w][j][row][1] = acc[j].y; }
   __syncthreads();
-  if (threadIdx.x < n2) {
-    const int r = threadIdx.x;
-    VC2 s = cmk<VC2>(red[0][r][0] + red[1][r][0] + red[2][r][0] + red[3][r][0],
-                     red[0][r][1] + red[1][r][1] + red[2][r][1] + red[3][r][1]);
-    y[voff + (long long)X * n2 + r] = s;
+  for (int i = threadIdx.x; i < nr * n2; i += 256) {
+    const int j = i / n2, r = i % n2;
+    VC2 s = cmk<VC2>(red[0][j][r][0] + red[1][j][r][0] + red[2][j][r][0] + red[3][j][r][0],
+                     red[0][j][r][1] + red[1][j][r][1] + red[2][j][r][1] + red[3][j][r][1]);
+    y[(long long)(rhs0 + j) * vs + (long long)X * n2 + r] = s;
   }
 }
 
 __global__ void k_dc_to_f32(const double2* __restrict__ in, float2* __restrict__ out, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+// ---------------------------------------------------------------- 16-bit storage
+// FP16: the hardware conversion (round to nearest even).  BF16: round to
+// nearest even on the upper half of the IEEE single (NaN kept quiet).
+__device__ __forceinline__ uint16_t to_f16(float v) {
+  _Float16 h = (_Float16)v;
+  return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ uint16_t to_bf16(float v) {
+  uint32_t b = __builtin_bit_cast(uint32_t, v);
+  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return (uint16_t)((b >> 16) | 0x40);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+
+template <bool BF>
+__device__ __forceinline__ uint16_t to16(float v) { return BF ? to_bf16(v) : to_f16(v); }
+
+// One workgroup per block (X, d): scale = max |Re|, |Im| over the block; store
+// Re/scale and Im/scale row major (row r, col c at r * n2 + c).
+template <bool BF>
+__global__ __launch_bounds__(256) void k_pack_blocks(const double2* __restrict__ M, uint16_t* __restrict__ re,
+                                                     uint16_t* __restrict__ im, float* __restrict__ sc, int n2) {
+  __shared__ double wmax[4];
+  const long long blk = blockIdx.x;
+  const double2* src = M + blk * n2 * n2;
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n2 * n2; i += 256) mx = fmax(mx, fmax(fabs(src[i].x), fabs(src[i].y)));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  const double s = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+  const double inv = s > 0.0 ? 1.0 / s : 0.0;
+  if (threadIdx.x == 0) sc[blk] = (float)s;
+  for (int i = threadIdx.x; i < n2 * n2; i += 256) {
+    const int r = i / n2, c = i % n2;
+    const double2 v = src[(long long)c * n2 + r];
+    re[blk * n2 * n2 + i] = to16<BF>((float)(v.x * inv));
+    im[blk * n2 * n2 + i] = to16<BF>((float)(v.y * inv));
+  }
+}
+
+// Coarse vectors -> 16-bit with one scale per (site, RHS):
+// xp[(rhs * Vc + X) * 2 n2 + k] = Re x_k / s, [.. + n2 + k] = Im x_k / s.
+template <bool BF>
+__global__ void k_pack_vec(const float2* __restrict__ x, uint16_t* __restrict__ xp, float* __restrict__ xs,
+                           int Vc, int n2, int nrhs) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)nrhs * Vc) return;
+  const float2* v = x + i * n2;
+  float mx = 0.f;
+  for (int k = 0; k < n2; ++k) mx = fmaxf(mx, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
+  const float inv = mx > 0.f ? 1.f / mx : 0.f;
+  xs[i] = mx;
+  uint16_t* o = xp + i * 2 * n2;
+  for (int k = 0; k < n2; ++k) {
+    o[k] = to16<BF>(v[k].x * inv);
+    o[n2 + k] = to16<BF>(v[k].y * inv);
+  }
+}
+
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <bool BF>
+__device__ __forceinline__ f4v mfma16(uint2 a, uint2 b, f4v c) {
+  if (BF) return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4v, a), __builtin_bit_cast(s4v, b), c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4v, a), __builtin_bit_cast(h4v, b), c, 0, 0, 0);
+}
+
+// 16-bit coarse apply on MFMA, FP32 accumulation.  The complex product is the
+// real product of [[Re, -Im], [Im, Re]] (2 n2 x 2 n2) with [Re x; Im x]
+// (2 n2 x 16 RHS).  16x16x16 tiles: lane l holds A[row l%16][k 4(l/16)..+3],
+// B[k 4(l/16)..+3][col l%16] and C[row 4(l/16)..+3][col l%16].  Each
+// direction's tile sum is rescaled by (block scale) x (input scale of its RHS)
+// before it joins the FP32 accumulator.  Workgroup = one coarse site and a
+// chunk of 16 RHS; wavefront w takes d = w, w+4, w+8.
+template <bool BF>
+__global__ __launch_bounds__(256) void k_capply_mfma(const uint16_t* __restrict__ Are, const uint16_t* __restrict__ Aim,
+                                                     const float* __restrict__ Asc, const uint16_t* __restrict__ xp,
+                                                     const float* __restrict__ xs, float2* __restrict__ y, CoarseArgs a,
+                                                     int nrhs) {
+  constexpr int MTMAX = 8;  // 2 n2 / 16 <= 8
+  __shared__ float red[4][128][17];
+  const int X = blockIdx.x;
+  const int rhs0 = blockIdx.y * 16;
+  const int n2 = a.n2;
+  const int MT = 2 * n2 / 16;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int col = l & 15, kq = l >> 4;
+  const int rhs = rhs0 + col;
+  const bool valid = rhs < nrhs;
+  f4v acc[MTMAX];
+#pragma unroll
+  for (int m = 0; m < MTMAX; ++m) acc[m] = f4v{0.f, 0.f, 0.f, 0.f};
+  for (int d = w; d < 9; d += 4) {
+    const int Y = coarse_neighbour(a, X, d);
+    const long long blk = (long long)X * 9 + d;
+    uint2 bf[MTMAX];
+    const uint16_t* xrow = xp + ((long long)(valid ? rhs : 0) * a.Vc + Y) * 2 * n2;
+#pragma unroll
+    for (int kt = 0; kt < MTMAX; ++kt)
+      bf[kt] = (kt < MT && valid) ? *reinterpret_cast<const uint2*>(xrow + kt * 16 + 4 * kq) : make_uint2(0u, 0u);
+    f4v t[MTMAX];
+#pragma unroll
+    for (int m = 0; m < MTMAX; ++m) t[m] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int mt = 0; mt < MTMAX; ++mt) {
+      if (mt >= MT) continue;
+      const int i = mt * 16 + (l & 15);           // expanded row
+      const bool im_row = i >= n2;
+      const int rr = im_row ? i - n2 : i;
+#pragma unroll
+      for (int kt = 0; kt < MTMAX; ++kt) {
+        if (kt >= MT) continue;
+        const int k = kt * 16 + 4 * kq;             // expanded column of this lane's 4 values
+        const bool im_col = k >= n2;
+        const int kk = im_col ? k - n2 : k;
+        const uint16_t* src = (im_row != im_col) ? Aim : Are;
+        uint2 av = *reinterpret_cast<const uint2*>(src + blk * n2 * n2 + (long long)rr * n2 + kk);
+        if (!im_row && im_col) { av.x ^= 0x80008000u; av.y ^= 0x80008000u; }  // -Im in the upper right
+        t[mt] = mfma16<BF>(av, bf[kt], t[mt]);
+      }
+    }
+    const float s = Asc[blk] * (valid ? xs[(long long)rhs * a.Vc + Y] : 0.f);
+#pragma unroll
+    for (int m = 0; m < MTMAX; ++m) acc[m] += s * t[m];
+  }
+#pragma unroll
+  for (int mt = 0; mt < MTMAX; ++mt)
+    if (mt < MT)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) red[w][mt * 16 + 4 * kq + j][col] = acc[mt][j];
+  __syncthreads();
+  for (int i = threadIdx.x; i < 16 * n2; i += 256) {
+    const int r = i % n2, cl = i / n2;
+    if (rhs0 + cl < nrhs) {
+      const float re = red[0][r][cl] + red[1][r][cl] + red[2][r][cl] + red[3][r][cl];
+      const float im = red[0][n2 + r][cl] + red[1][n2 + r][cl] + red[2][n2 + r][cl] + red[3][n2 + r][cl];
+      y[((long long)(rhs0 + cl) * a.Vc + X) * n2 + r] = make_float2(re, im);
+    }
+  }
 }
 
 }  // namespace
@@ -137,27 +303,74 @@ void build_coarse_op(const double2* Vhat, const double2* gauge, double2* Dc, dou
     }
 }
 
-void coarse_to_f32(const double2* Dc64, float2* Dc32, long long n, hipStream_t st) {
-  hipLaunchKernelGGL(k_dc_to_f32, dim3(std::min(ceil_div(n, 256), 8192)), dim3(256), 0, st, Dc64, Dc32, n);
+static void pack_store(CoarseStore& s, const CoarseGeometry& cg, hipStream_t st) {
+  const long long nblk = 9LL * cg.Vc, n = nblk * cg.n2 * cg.n2;
+  s.m32.alloc(n * sizeof(float2));
+  hipLaunchKernelGGL(k_dc_to_f32, dim3(std::min(ceil_div(n, 256), 8192)), dim3(256), 0, st, s.m64.as<double2>(),
+                     s.m32.as<float2>(), n);
+  MG_LAUNCH_CHECK();
+  s.re16.alloc(n * 2); s.im16.alloc(n * 2); s.sc16.alloc(nblk * sizeof(float));
+  s.reb.alloc(n * 2); s.imb.alloc(n * 2); s.scb.alloc(nblk * sizeof(float));
+  hipLaunchKernelGGL(k_pack_blocks<false>, dim3(nblk), dim3(256), 0, st, s.m64.as<double2>(), s.re16.as<uint16_t>(),
+                     s.im16.as<uint16_t>(), s.sc16.as<float>(), cg.n2);
+  MG_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_pack_blocks<true>, dim3(nblk), dim3(256), 0, st, s.m64.as<double2>(), s.reb.as<uint16_t>(),
+                     s.imb.as<uint16_t>(), s.scb.as<float>(), cg.n2);
   MG_LAUNCH_CHECK();
 }
 
-template <class MC2, class VC2>
-void coarse_apply(const MC2* Dc, const VC2* x, VC2* y, bool dagger, const CoarseGeometry& cg, int nrhs,
-                  hipStream_t st) {
+// From Dc.m64: the adjoint stencil and the FP32 / FP16 / BF16 copies of both.
+void finish_coarse_op(CoarseStore& Dc, CoarseStore& DcH, const CoarseGeometry& cg, hipStream_t st) {
+  const long long nblk = 9LL * cg.Vc, n = nblk * cg.n2 * cg.n2;
+  DcH.m64.alloc(n * sizeof(double2));
+  hipLaunchKernelGGL(k_adjoint_blocks, dim3(nblk), dim3(256), 0, st, Dc.m64.as<double2>(), DcH.m64.as<double2>(),
+                     coarse_args(cg));
+  MG_LAUNCH_CHECK();
+  pack_store(Dc, cg, st);
+  pack_store(DcH, cg, st);
+}
+
+void coarse_apply64(const CoarseStore& s, const double2* x, double2* y, const CoarseGeometry& cg, int nrhs,
+                    hipStream_t st) {
   if (cg.n2 > 64) fail(MGDWF_ERR_INVALID_ARG, "2*nvec above 64 is not supported");
-  CoarseArgs a;
-  for (int m = 0; m < 4; ++m) a.Lc[m] = cg.Lc[m];
-  a.Vc = cg.Vc; a.n2 = cg.n2;
-  dim3 grid(cg.Vc, nrhs);
-  if (dagger) hipLaunchKernelGGL((k_coarse_apply<MC2, VC2, true>), grid, dim3(256), 0, st, Dc, x, y, a);
-  else hipLaunchKernelGGL((k_coarse_apply<MC2, VC2, false>), grid, dim3(256), 0, st, Dc, x, y, a);
-  MG_LAUNCH_CHECK();
+  for (int r0 = 0; r0 < nrhs; r0 += 8) {
+    hipLaunchKernelGGL((k_capply<double2, double2, 8>), dim3(cg.Vc), dim3(256), 0, st, s.m64.as<double2>(), x, y,
+                       coarse_args(cg), nrhs, r0);
+    MG_LAUNCH_CHECK();
+  }
 }
 
-template void coarse_apply<double2, double2>(const double2*, const double2*, double2*, bool,
-                                             const CoarseGeometry&, int, hipStream_t);
-template void coarse_apply<float2, float2>(const float2*, const float2*, float2*, bool, const CoarseGeometry&,
-                                           int, hipStream_t);
+size_t coarse_pack_bytes(const CoarseGeometry& cg, int nrhs) {
+  return (size_t)nrhs * cg.Vc * (2 * cg.n2 * sizeof(uint16_t) + sizeof(float)) + 256;
+}
+
+void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, float2* y, const CoarseGeometry& cg,
+                    int nrhs, void* pack, hipStream_t st) {
+  if (cg.n2 > 64) fail(MGDWF_ERR_INVALID_ARG, "2*nvec above 64 is not supported");
+  if (prec == MGDWF_F32 || prec == MGDWF_F64) {
+    for (int r0 = 0; r0 < nrhs; r0 += 16) {
+      hipLaunchKernelGGL((k_capply<float2, float2, 16>), dim3(cg.Vc), dim3(256), 0, st, s.m32.as<float2>(), x, y,
+                         coarse_args(cg), nrhs, r0);
+      MG_LAUNCH_CHECK();
+    }
+    return;
+  }
+  if (cg.n2 % 16) fail(MGDWF_ERR_INVALID_ARG, "16-bit coarse operator needs nvec divisible by 8");
+  const bool bf = prec == MGDWF_BF16;
+  uint16_t* xp = static_cast<uint16_t*>(pack);
+  float* xs = reinterpret_cast<float*>(xp + (size_t)nrhs * cg.Vc * 2 * cg.n2);
+  const long long nsv = (long long)nrhs * cg.Vc;
+  if (bf) hipLaunchKernelGGL(k_pack_vec<true>, dim3(ceil_div(nsv, 256)), dim3(256), 0, st, x, xp, xs, cg.Vc, cg.n2, nrhs);
+  else hipLaunchKernelGGL(k_pack_vec<false>, dim3(ceil_div(nsv, 256)), dim3(256), 0, st, x, xp, xs, cg.Vc, cg.n2, nrhs);
+  MG_LAUNCH_CHECK();
+  dim3 grid(cg.Vc, ceil_div(nrhs, 16));
+  if (bf)
+    hipLaunchKernelGGL(k_capply_mfma<true>, grid, dim3(256), 0, st, s.reb.as<uint16_t>(), s.imb.as<uint16_t>(),
+                       s.scb.as<float>(), xp, xs, y, coarse_args(cg), nrhs);
+  else
+    hipLaunchKernelGGL(k_capply_mfma<false>, grid, dim3(256), 0, st, s.re16.as<uint16_t>(), s.im16.as<uint16_t>(),
+                       s.sc16.as<float>(), xp, xs, y, coarse_args(cg), nrhs);
+  MG_LAUNCH_CHECK();
+}
 
 }  // namespace mgdwf

@@ -19,7 +19,7 @@ struct mgdwf_ctx {
   mgdwf::CoarseGeometry cg{};
   bool have_basis = false, have_coarse = false;
   mgdwf::DevBuf V64, V32;    // orthonormal basis, Nv fields
-  mgdwf::DevBuf Dc64, Dc32;  // coarse operator (internal column-major blocks)
+  mgdwf::CoarseStore Dc, DcH;  // coarse operator and its adjoint stencil, all precisions
 
   mgdwf_mg_params mp{};
   bool have_params = false;

@@ -343,9 +343,401 @@ __global__ __launch_bounds__(256) void k_dslash_split(const double2* __restrict_
     for (int c = 0; c < 3; ++c) out[(sp * 3 + c) * V5 + i5] = self.v[sp][c];
 }
 
+// ---------------------------------------------------------------- t-march kernel
+// Same operator, organised for reuse in the cache hierarchy.  A workgroup owns
+// a 4 x 2 x 2 tile of (x, y, z) sites times all Ls and walks a chunk of
+// t-slices.  The backward t-hop of slice t, (1 +- g_t) U_t(x, t-1)^+ psi(t-1),
+// is the transported half spinor computed from slice t-1 in the previous step
+// (kept in registers, with the link loaded once for both t-hops), so per slice
+// only psi(t+1) is new to the workgroup; the x, y, z neighbours are the current
+// slice, which every workgroup touches at about the same time, so they come
+// from L2.  Workgroups are ordered tile-fastest then chunk, and remapped so each
+// XCD takes a contiguous range (one chunk of t over a contiguous set of tiles).
+constexpr int TMX = 4, TMY = 2, TMZ = 2, TMS = TMX * TMY * TMZ;
+
+struct TMArgs {
+  DslashArgs d;
+  int ntx, nty, ntz;  // tiles per direction
+  int tc;             // t-slices per chunk
+};
+
+__device__ __forceinline__ double block_sum_dyn(double v) {
+  __shared__ double red[16];
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+template <class C2>
+__device__ __forceinline__ void load_link(const C2* __restrict__ gauge, int mu, long long V4, int x4, C2 U[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) U[a][b] = gauge[(mu * 9 + a * 3 + b) * V4 + x4];
+}
+
+template <bool DAGU, class C2>
+__device__ __forceinline__ void mul_link(const C2 U[3][3], const C2 h[2][3], C2 u[2][3], float ph) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      C2 s = cmk<C2>(0, 0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (DAGU) cfmac(s, U[b][a], h[r][b]);
+        else cfma(s, U[a][b], h[r][b]);
+      }
+      u[r][a] = cscale(s, ph);
+    }
+}
+
+template <class C2, bool DAG, int MODE>
+__global__ __launch_bounds__(256) void k_dslash_tm(const C2* __restrict__ in, C2* __restrict__ out,
+                                                    const C2* __restrict__ b, const C2* __restrict__ gauge, TMArgs ta,
+                                                    double* __restrict__ partial) {
+  using T = typename real_of<C2>::type;
+  const DslashArgs& a = ta.d;
+  const int ntiles = ta.ntx * ta.nty * ta.ntz;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int chunk = bid / ntiles, tile = bid - chunk * ntiles;
+  const int tx = tile % ta.ntx, ty = (tile / ta.ntx) % ta.nty, tz = tile / (ta.ntx * ta.nty);
+  const int Ls = a.Ls;
+  const int site = threadIdx.x / Ls, s = threadIdx.x - site * Ls;
+  const int x = tx * TMX + (site & 3), y = ty * TMY + ((site >> 2) & 1), z = tz * TMZ + (site >> 3);
+  const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2], Lt = a.L[3];
+  const long long V5 = a.V5, V4 = a.V4;
+  const int V3 = Lx * Ly * Lz;
+  const long long roff = (long long)blockIdx.y * 12 * V5;
+  in += roff;
+  out += roff;
+  if (MODE == 1) b += roff;
+  const int x3 = (z * Ly + y) * Lx + x;
+  // x, y, z neighbours inside a slice, with boundary phases
+  int nf3[3], nb3[3];
+  float phf[3], phb[3];
+  {
+    const int co[3] = {x, y, z};
+    const int Lm[3] = {Lx, Ly, Lz};
+    const int st[3] = {1, Lx, Lx * Ly};
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      const bool top = co[mu] == Lm[mu] - 1, bot = co[mu] == 0;
+      nf3[mu] = top ? x3 - (Lm[mu] - 1) * st[mu] : x3 + st[mu];
+      nb3[mu] = bot ? x3 + (Lm[mu] - 1) * st[mu] : x3 - st[mu];
+      phf[mu] = top ? a.ph[mu] : 1.0f;
+      phb[mu] = bot ? a.ph[mu] : 1.0f;
+    }
+  }
+  constexpr int EF = DAG ? 1 : -1;
+  constexpr int EB = DAG ? -1 : 1;
+  const int t0 = chunk * ta.tc;
+  const int t1 = min(t0 + ta.tc, Lt);
+  C2 h[2][3], hb[2][3], U[3][3];
+  Spinor<C2> p;
+  {  // backward t-hop of the first slice, from slice t0 - 1
+    const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+    const int x4m = tm * V3 + x3;
+    load_spinor(p, in, V5, (long long)x4m * Ls + s);
+    project<3, EB>(p, h);
+    load_link(gauge, 3, V4, x4m, U);
+    mul_link<true>(U, h, hb, t0 == 0 ? a.ph[3] : 1.0f);
+  }
+  const int up0 = DAG ? 0 : 2;
+  const int dn0 = DAG ? 2 : 0;
+  const T half = (T)-0.5;
+  const T dg = (T)a.diag;
+  double nrm = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int x4 = t * V3 + x3;
+    const long long i5 = (long long)x4 * Ls + s;
+    Spinor<C2> acc;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc.v[sp][c] = cmk<C2>(0, 0);
+    const int tb = t * V3;
+    hop_dir<0, EF, EB>(acc, in, gauge, V5, V4, Ls, s, x4, tb + nf3[0], tb + nb3[0], phf[0], phb[0]);
+    hop_dir<1, EF, EB>(acc, in, gauge, V5, V4, Ls, s, x4, tb + nf3[1], tb + nb3[1], phf[1], phb[1]);
+    hop_dir<2, EF, EB>(acc, in, gauge, V5, V4, Ls, s, x4, tb + nf3[2], tb + nb3[2], phf[2], phb[2]);
+    // forward t-hop: U_t(x, t) psi(x, t+1)
+    const bool top = t == Lt - 1;
+    const int x4f = (top ? 0 : t + 1) * V3 + x3;
+    load_spinor(p, in, V5, (long long)x4f * Ls + s);
+    project<3, EF>(p, h);
+    load_link(gauge, 3, V4, x4, U);
+    {
+      C2 u[2][3];
+      mul_link<false>(U, h, u, top ? a.ph[3] : 1.0f);
+      accumulate<3, EF>(acc, u);
+    }
+    accumulate<3, EB>(acc, hb);
+    // this slice's own spinor: diagonal, fifth-dimension hop, and the next backward t-hop
+    load_spinor(p, in, V5, i5);
+    const long long base = (long long)x4 * Ls;
+    const int sp1 = (s == Ls - 1) ? 0 : s + 1;
+    const int sm1 = (s == 0) ? Ls - 1 : s - 1;
+    const T cup = (s == Ls - 1) ? (T)a.mf : (T)-1;
+    const T cdn = (s == 0) ? (T)a.mf : (T)-1;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long cc = (long long)(sp * 3 + c) * V5;
+        C2 r = cadd(cscale(p.v[sp][c], dg), cscale(acc.v[sp][c], half));
+        if (sp == up0 || sp == up0 + 1) r = cadd(r, cscale(in[cc + base + sp1], cup));
+        if (sp == dn0 || sp == dn0 + 1) r = cadd(r, cscale(in[cc + base + sm1], cdn));
+        if (MODE == 1) r = csub(b[cc + i5], r);
+        out[cc + i5] = r;
+        nrm += (double)r.x * r.x + (double)r.y * r.y;
+      }
+    project<3, EB>(p, h);
+    mul_link<true>(U, h, hb, 1.0f);  // slice t+1 never crosses the boundary inside a chunk
+  }
+  if (partial) {
+    const double sum = block_sum_dyn(nrm);
+    if (threadIdx.x == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = sum;
+  }
+}
+
+// ---------------------------------------------------------------- t-march, s-pairs (FP32)
+// Each thread computes the two sites (x4, 2j) and (x4, 2j+1): one 16-byte load
+// brings both s-values of a spin-colour component (they are adjacent in the
+// layout), and every link is loaded once for both outputs.  A workgroup owns a
+// 4 x 4 x 2 tile of (x, y, z) sites; the t-march is as in k_dslash_tm.
+constexpr int TPX = 4, TPY = 4, TPZ = 2, TPS = TPX * TPY * TPZ;
+
+__device__ __forceinline__ void load_pair(Spinor<float2>& p0, Spinor<float2>& p1, const float2* __restrict__ f,
+                                          long long stride, long long i5) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float4 v = *reinterpret_cast<const float4*>(f + (sp * 3 + c) * stride + i5);
+      p0.v[sp][c] = make_float2(v.x, v.y);
+      p1.v[sp][c] = make_float2(v.z, v.w);
+    }
+}
+
+template <int MU, int EPS, bool DAGU>
+__device__ __forceinline__ void hop_pair(Spinor<float2>& a0, Spinor<float2>& a1, const float2* __restrict__ in,
+                                         const float2* __restrict__ gauge, long long V5, long long V4, long long j5,
+                                         int xlink, float ph) {
+  Spinor<float2> p0, p1;
+  float2 U[3][3], h[2][3], u[2][3];
+  load_pair(p0, p1, in, V5, j5);
+  load_link(gauge, MU, V4, xlink, U);
+  project<MU, EPS>(p0, h);
+  mul_link<DAGU>(U, h, u, ph);
+  accumulate<MU, EPS>(a0, u);
+  project<MU, EPS>(p1, h);
+  mul_link<DAGU>(U, h, u, ph);
+  accumulate<MU, EPS>(a1, u);
+}
+
+template <bool DAG, int MODE>
+__global__ __launch_bounds__(256) void k_dslash_tp(const float2* __restrict__ in, float2* __restrict__ out,
+                                                   const float2* __restrict__ b, const float2* __restrict__ gauge,
+                                                   TMArgs ta, double* __restrict__ partial) {
+  const DslashArgs& a = ta.d;
+  const int ntiles = ta.ntx * ta.nty * ta.ntz;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int chunk = bid / ntiles, tile = bid - chunk * ntiles;
+  const int tx = tile % ta.ntx, ty = (tile / ta.ntx) % ta.nty, tz = tile / (ta.ntx * ta.nty);
+  const int Ls = a.Ls, np = Ls >> 1;
+  const int site = threadIdx.x / np, jp = threadIdx.x - site * np;
+  const int s0 = 2 * jp;  // this thread's sites: s0 and s0 + 1
+  const int x = tx * TPX + (site & 3), y = ty * TPY + ((site >> 2) & 3), z = tz * TPZ + (site >> 4);
+  const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2], Lt = a.L[3];
+  const long long V5 = a.V5, V4 = a.V4;
+  const int V3 = Lx * Ly * Lz;
+  const long long roff = (long long)blockIdx.y * 12 * V5;
+  in += roff;
+  out += roff;
+  if (MODE == 1) b += roff;
+  const int x3 = (z * Ly + y) * Lx + x;
+  int nf3[3], nb3[3];
+  float phf[3], phb[3];
+  {
+    const int co[3] = {x, y, z};
+    const int Lm[3] = {Lx, Ly, Lz};
+    const int st[3] = {1, Lx, Lx * Ly};
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      const bool top = co[mu] == Lm[mu] - 1, bot = co[mu] == 0;
+      nf3[mu] = top ? x3 - (Lm[mu] - 1) * st[mu] : x3 + st[mu];
+      nb3[mu] = bot ? x3 + (Lm[mu] - 1) * st[mu] : x3 - st[mu];
+      phf[mu] = top ? a.ph[mu] : 1.0f;
+      phb[mu] = bot ? a.ph[mu] : 1.0f;
+    }
+  }
+  constexpr int EF = DAG ? 1 : -1;
+  constexpr int EB = DAG ? -1 : 1;
+  const int t0 = chunk * ta.tc;
+  const int t1 = min(t0 + ta.tc, Lt);
+  float2 hb0[2][3], hb1[2][3], U[3][3], h[2][3];
+  Spinor<float2> p0, p1;
+  {
+    const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+    const int x4m = tm * V3 + x3;
+    load_pair(p0, p1, in, V5, (long long)x4m * Ls + s0);
+    load_link(gauge, 3, V4, x4m, U);
+    const float ph = t0 == 0 ? a.ph[3] : 1.0f;
+    project<3, EB>(p0, h);
+    mul_link<true>(U, h, hb0, ph);
+    project<3, EB>(p1, h);
+    mul_link<true>(U, h, hb1, ph);
+  }
+  const int up0 = DAG ? 0 : 2;   // spins coupled to s+1
+  const int dn0 = DAG ? 2 : 0;   // spins coupled to s-1
+  const float dg = (float)a.diag, mf = (float)a.mf;
+  double nrm = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int x4 = t * V3 + x3;
+    const long long i5 = (long long)x4 * Ls + s0;
+    const int tb = t * V3;
+    Spinor<float2> a0, a1;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) { a0.v[sp][c] = make_float2(0.f, 0.f); a1.v[sp][c] = make_float2(0.f, 0.f); }
+    hop_pair<0, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[0]) * Ls + s0, x4, phf[0]);
+    hop_pair<0, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[0]) * Ls + s0, tb + nb3[0], phb[0]);
+    hop_pair<1, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[1]) * Ls + s0, x4, phf[1]);
+    hop_pair<1, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[1]) * Ls + s0, tb + nb3[1], phb[1]);
+    hop_pair<2, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[2]) * Ls + s0, x4, phf[2]);
+    hop_pair<2, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[2]) * Ls + s0, tb + nb3[2], phb[2]);
+    {  // forward t-hop, then the carried backward t-hop
+      const bool top = t == Lt - 1;
+      const int x4f = (top ? 0 : t + 1) * V3 + x3;
+      load_pair(p0, p1, in, V5, (long long)x4f * Ls + s0);
+      load_link(gauge, 3, V4, x4, U);
+      const float ph = top ? a.ph[3] : 1.0f;
+      float2 u[2][3];
+      project<3, EF>(p0, h);
+      mul_link<false>(U, h, u, ph);
+      accumulate<3, EF>(a0, u);
+      project<3, EF>(p1, h);
+      mul_link<false>(U, h, u, ph);
+      accumulate<3, EF>(a1, u);
+      accumulate<3, EB>(a0, hb0);
+      accumulate<3, EB>(a1, hb1);
+    }
+    load_pair(p0, p1, in, V5, i5);  // psi(x4, s0), psi(x4, s0 + 1)
+    // neighbours in s outside the pair: s0 - 1 (for s0) and s0 + 2 (for s0 + 1)
+    const long long base = (long long)x4 * Ls;
+    const int sm = s0 == 0 ? Ls - 1 : s0 - 1;
+    const int sp2 = s0 + 2 == Ls ? 0 : s0 + 2;
+    const float cdn0 = s0 == 0 ? mf : -1.f;          // s0 - 1 across the wall
+    const float cup1 = s0 + 2 == Ls ? mf : -1.f;     // s0 + 2 across the wall
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long cc = (long long)(sp * 3 + c) * V5;
+        float2 r0 = cadd(cscale(p0.v[sp][c], dg), cscale(a0.v[sp][c], -0.5f));
+        float2 r1 = cadd(cscale(p1.v[sp][c], dg), cscale(a1.v[sp][c], -0.5f));
+        if (sp == up0 || sp == up0 + 1) {
+          r0 = csub(r0, p1.v[sp][c]);                               // s0 <- s0 + 1 (inside the pair)
+          r1 = cadd(r1, cscale(in[cc + base + sp2], cup1));         // s0 + 1 <- s0 + 2
+        }
+        if (sp == dn0 || sp == dn0 + 1) {
+          r0 = cadd(r0, cscale(in[cc + base + sm], cdn0));          // s0 <- s0 - 1
+          r1 = csub(r1, p0.v[sp][c]);                               // s0 + 1 <- s0
+        }
+        if (MODE == 1) {
+          const float4 bb = *reinterpret_cast<const float4*>(b + cc + i5);
+          r0 = make_float2(bb.x - r0.x, bb.y - r0.y);
+          r1 = make_float2(bb.z - r1.x, bb.w - r1.y);
+        }
+        *reinterpret_cast<float4*>(out + cc + i5) = make_float4(r0.x, r0.y, r1.x, r1.y);
+        nrm += (double)r0.x * r0.x + (double)r0.y * r0.y + (double)r1.x * r1.x + (double)r1.y * r1.y;
+      }
+    project<3, EB>(p0, h);
+    mul_link<true>(U, h, hb0, 1.0f);
+    project<3, EB>(p1, h);
+    mul_link<true>(U, h, hb1, 1.0f);
+  }
+  if (partial) {
+    const double sum = block_sum_dyn(nrm);
+    if (threadIdx.x == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = sum;
+  }
+}
+
 }  // namespace
 
-int dslash_nblocks(const Geometry& g) { return ceil_div(g.V5, 256); }
+// s-pair t-march (FP32): x, y, z extents tile by 4, 4, 2 and Ls is even, 4..16.
+static bool use_tpair(const Geometry& g) {
+  return g.L[0] % TPX == 0 && g.L[1] % TPY == 0 && g.L[2] % TPZ == 0 && g.Ls % 2 == 0 && g.Ls >= 4 &&
+         g.Ls <= 16 && (TPS * g.Ls / 2) % 64 == 0;
+}
+
+static int tpair_chunk(const Geometry& g) {
+  const int ntiles = (g.L[0] / TPX) * (g.L[1] / TPY) * (g.L[2] / TPZ);
+  const int want_chunks = std::max(1, std::min(g.L[3], ceil_div(512, ntiles)));
+  return ceil_div(g.L[3], want_chunks);
+}
+
+// The t-march kernel covers lattices whose x, y, z extents tile by 4, 2, 2 and
+// whose Ls is a multiple of 4 (whole wavefronts) up to 16; others use k_dslash.
+static bool use_tmarch(const Geometry& g) {
+  return g.L[0] % TMX == 0 && g.L[1] % TMY == 0 && g.L[2] % TMZ == 0 && g.Ls % 4 == 0 && g.Ls <= 16;
+}
+
+// t-slices per chunk: enough chunks that about four workgroups share each CU.
+static int tmarch_chunk(const Geometry& g) {
+  const int ntiles = (g.L[0] / TMX) * (g.L[1] / TMY) * (g.L[2] / TMZ);
+  const int want_chunks = std::max(1, std::min(g.L[3], ceil_div(1024, ntiles)));
+  return ceil_div(g.L[3], want_chunks);
+}
+
+static void launch_tpair(const float2* in, float2* out, const float2* b, const float2* gauge, const TMArgs& ta,
+                         double* partial, bool dagger, int mode, dim3 grid, dim3 blk, hipStream_t st) {
+#define MG_TP(DAG, MODE) \
+  hipLaunchKernelGGL((k_dslash_tp<DAG, MODE>), grid, blk, 0, st, in, out, b, gauge, ta, partial)
+  if (!dagger && mode == 0) MG_TP(false, 0);
+  else if (!dagger && mode == 1) MG_TP(false, 1);
+  else if (dagger && mode == 0) MG_TP(true, 0);
+  else MG_TP(true, 1);
+#undef MG_TP
+}
+static void launch_tpair(const double2*, double2*, const double2*, const double2*, const TMArgs&, double*, bool, int,
+                         dim3, dim3, hipStream_t) {
+  fail(MGDWF_ERR_INVALID_ARG, "the s-pair kernel is FP32 only");
+}
+
+// Kernel choice: FP32 takes the s-pair t-march where the lattice tiles, else the
+// t-march, else the plain kernel; FP64 takes the plain kernel, whose register
+// budget (about 250) keeps two wavefronts per SIMD where the t-march keeps one.
+enum DslashKind { DS_PLAIN, DS_TMARCH, DS_TPAIR };
+
+template <class C2>
+static DslashKind dslash_kind(const Geometry& g) {
+  if (sizeof(typename real_of<C2>::type) == 8) return DS_PLAIN;
+  if (use_tpair(g)) return DS_TPAIR;
+  if (use_tmarch(g)) return DS_TMARCH;
+  return DS_PLAIN;
+}
+
+template <class C2>
+int dslash_nblocks(const Geometry& g) {
+  switch (dslash_kind<C2>(g)) {
+    case DS_TPAIR:
+      return (g.L[0] / TPX) * (g.L[1] / TPY) * (g.L[2] / TPZ) * ceil_div(g.L[3], tpair_chunk(g));
+    case DS_TMARCH:
+      return (g.L[0] / TMX) * (g.L[1] / TMY) * (g.L[2] / TMZ) * ceil_div(g.L[3], tmarch_chunk(g));
+    default:
+      return ceil_div(g.V5, 256);
+  }
+}
+template int dslash_nblocks<double2>(const Geometry&);
+template int dslash_nblocks<float2>(const Geometry&);
 
 template <class C2>
 void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geometry& g, double M5,
@@ -353,7 +745,34 @@ void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geomet
   DslashArgs a;
   for (int m = 0; m < 4; ++m) { a.L[m] = g.L[m]; a.ph[m] = (float)g.bc[m]; }
   a.Ls = g.Ls; a.V4 = g.V4; a.V5 = g.V5; a.diag = 5.0 - M5; a.mf = mf;
-  dim3 grid(dslash_nblocks(g), nrhs), blk(256);
+  const DslashKind kind = dslash_kind<C2>(g);
+  if (kind == DS_TPAIR) {
+    TMArgs ta;
+    ta.d = a;
+    ta.ntx = g.L[0] / TPX; ta.nty = g.L[1] / TPY; ta.ntz = g.L[2] / TPZ;
+    ta.tc = tpair_chunk(g);
+    launch_tpair(in, out, b, gauge, ta, partial, dagger, mode, dim3(dslash_nblocks<C2>(g), nrhs),
+                 dim3(TPS * g.Ls / 2), st);
+    MG_LAUNCH_CHECK();
+    return;
+  }
+  if (kind == DS_TMARCH) {
+    TMArgs ta;
+    ta.d = a;
+    ta.ntx = g.L[0] / TMX; ta.nty = g.L[1] / TMY; ta.ntz = g.L[2] / TMZ;
+    ta.tc = tmarch_chunk(g);
+    dim3 grid(dslash_nblocks<C2>(g), nrhs), blk(TMS * g.Ls);
+#define MG_TM(DAG, MODE) \
+  hipLaunchKernelGGL((k_dslash_tm<C2, DAG, MODE>), grid, blk, 0, st, in, out, b, gauge, ta, partial)
+    if (!dagger && mode == 0) MG_TM(false, 0);
+    else if (!dagger && mode == 1) MG_TM(false, 1);
+    else if (dagger && mode == 0) MG_TM(true, 0);
+    else MG_TM(true, 1);
+#undef MG_TM
+    MG_LAUNCH_CHECK();
+    return;
+  }
+  dim3 grid(dslash_nblocks<C2>(g), nrhs), blk(256);
 #define MG_DS(DAG, MODE) \
   hipLaunchKernelGGL((k_dslash<C2, DAG, MODE>), grid, blk, 0, st, in, out, b, gauge, a, partial)
   if (!dagger && mode == 0) MG_DS(false, 0);

@@ -86,6 +86,14 @@ struct DevBuf {
 
 inline int ceil_div(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
 
+// One coarse stencil (D_c or its adjoint) in every storage precision.
+//   m64, m32:        complex blocks, column major, block (X, d) at (X * 9 + d) * n2 * n2
+//   re16/im16/sc16:  FP16 real and imaginary parts, row major, one FP32 scale per block
+//   reb/imb/scb:     the same in BF16
+struct CoarseStore {
+  DevBuf m64, m32, re16, im16, sc16, reb, imb, scb;
+};
+
 // Remap a linear workgroup index so that each XCD (workgroups are dealt to
 // the 8 XCDs round robin) processes one contiguous slice of the index range:
 // neighbouring tiles then share that XCD's L2.

@@ -61,7 +61,7 @@ template <> const float2* basis_of<float2>(mgdwf_ctx* c) { return c->V32.as<floa
 template <class F2>
 void fine_op(mgdwf_ctx* c, const F2* in, F2* out, const F2* b, bool dag, int mode, int nrhs, int dst) {
   double* partial = nullptr;
-  const int nb = dslash_nblocks(c->g);
+  const int nb = dslash_nblocks<F2>(c->g);
   if (dst >= 0) partial = c->buf<double>("dpart", (size_t)nb * nrhs);
   dslash_ex<F2>(in, out, b, gauge_of<F2>(c), c->g, c->M5, c->mf, dag, mode, nrhs, partial, c->st);
   if (dst >= 0) finalize_rhs(partial, nb, 1, c->buf<double>("slots", (size_t)nrhs * NSLOT), dst, nrhs, c->st);
@@ -80,20 +80,30 @@ void copy(mgdwf_ctx* c, const C2* in, C2* out, long long n) {
   MG_HIP(hipMemcpyAsync(out, in, n * sizeof(C2), hipMemcpyDeviceToDevice, c->st));
 }
 
+// y = D_c x or D_c^+ x in the precision the parameters select
+inline void coarse_op(mgdwf_ctx* c, const mgdwf_mg_params&, const double2* x, double2* y, bool dag, int nrhs) {
+  coarse_apply64(dag ? c->DcH : c->Dc, x, y, c->cg, nrhs, c->st);
+  c->coarse_applies += 1;
+}
+inline void coarse_op(mgdwf_ctx* c, const mgdwf_mg_params& p, const float2* x, float2* y, bool dag, int nrhs) {
+  coarse_apply32(dag ? c->DcH : c->Dc, p.coarse_prec, x, y, c->cg, nrhs,
+                 c->buf<char>("vc_pack", coarse_pack_bytes(c->cg, nrhs)), c->st);
+  c->coarse_applies += 1;
+}
+
 // ---------------------------------------------------------------- V-cycle
-template <class F2, class M2>
+template <class F2>
 struct TwoLevel {
   mgdwf_ctx* c;
   int nrhs;
   mgdwf_mg_params p;
-  const M2* Dc;
   long long nf, nc;  // per-RHS lengths (complex numbers)
   F2 *r1, *pp, *qq, *b3, *x3, *r3;
   F2 *cb, *cx, *cr, *cp, *cq, *ct;  // coarse vectors (same real type as the fine level)
   double* sl;
   double* vpart;
 
-  TwoLevel(mgdwf_ctx* ctx, int n_rhs, const mgdwf_mg_params& prm, const M2* dc) : c(ctx), nrhs(n_rhs), p(prm), Dc(dc) {
+  TwoLevel(mgdwf_ctx* ctx, int n_rhs, const mgdwf_mg_params& prm) : c(ctx), nrhs(n_rhs), p(prm) {
     nf = c->fine_len();
     nc = c->coarse_len();
     const std::string t = Prec<F2>::tag;
@@ -130,19 +140,17 @@ struct TwoLevel {
     copy(c, b, cr, nc * nrhs);
     norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR0);
     norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR_A);
-    coarse_apply<M2, F2>(Dc, cr, cp, true, c->cg, nrhs, c->st);
-    c->coarse_applies += 1;
+    coarse_op(c, p, cr, cp, true, nrhs);
     norm_into<F2>(c, cp, nullptr, nc, nrhs, S_CPP);
     int cur = S_CRR_A, nxt = S_CRR_B;
     const double tol2 = p.coarse_tol * p.coarse_tol;
     for (int it = 0; it < p.coarse_maxiter; ++it) {
-      coarse_apply<M2, F2>(Dc, cp, cq, false, c->cg, nrhs, c->st);
+      coarse_op(c, p, cp, cq, false, nrhs);
       mr_update<F2>(x, cr, cp, cq, nc, nrhs, sl, cur, S_CPP, it == 0, vpart, c->st);
       finalize_rhs(vpart, VEC_BLOCKS, 1, sl, nxt, nrhs, c->st);
-      coarse_apply<M2, F2>(Dc, cr, ct, true, c->cg, nrhs, c->st);
+      coarse_op(c, p, cr, ct, true, nrhs);
       cg_dir<F2>(cp, ct, nc, nrhs, sl, nxt, cur, vpart, c->st);
       finalize_rhs(vpart, VEC_BLOCKS, 1, sl, S_CPP, nrhs, c->st);
-      c->coarse_applies += 2;
       std::swap(cur, nxt);
       if ((it + 1) % check == 0 && it + 1 < p.coarse_maxiter) {
         std::vector<double> h = read_slots(c, nrhs);
@@ -173,8 +181,8 @@ struct TwoLevel {
 // ---------------------------------------------------------------- FGCR cycle
 // Up to `kmax` flexible GCR steps on D e = r (inner precision F2), e from 0.
 // Stops early when every |r|^2 <= stop2[rhs].  Returns the steps taken.
-template <class F2, class M2>
-int fgcr_cycle(mgdwf_ctx* c, TwoLevel<F2, M2>& M, F2* r, F2* e, int nrhs, int kmax, const std::vector<double>& stop2,
+template <class F2>
+int fgcr_cycle(mgdwf_ctx* c, TwoLevel<F2>& M, F2* r, F2* e, int nrhs, int kmax, const std::vector<double>& stop2,
                std::vector<double>* rin2_out) {
   const long long nf = c->fine_len();
   const std::string t = Prec<F2>::tag;
@@ -218,15 +226,15 @@ int fgcr_cycle(mgdwf_ctx* c, TwoLevel<F2, M2>& M, F2* r, F2* e, int nrhs, int km
 
 // ---------------------------------------------------------------- public (C++) API
 
-template <class F2, class M2>
-static void solve_impl(mgdwf_ctx* c, const M2* Dc, double2* b64, double2* x64, int nrhs, const mgdwf_solve_params& sp,
+template <class F2>
+static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const mgdwf_solve_params& sp,
                        mgdwf_solve_report* rep) {
   const long long nf = c->fine_len();
   double* sl = c->buf<double>("slots", (size_t)nrhs * NSLOT);
   double2* r64 = c->buf<double2>("sol_r64", nf * nrhs);
   F2* rin = c->buf<F2>(std::string("sol_rin") + Prec<F2>::tag, nf * nrhs);
   F2* e = c->buf<F2>(std::string("sol_e") + Prec<F2>::tag, nf * nrhs);
-  TwoLevel<F2, M2> M(c, nrhs, c->mp, Dc);
+  TwoLevel<F2> M(c, nrhs, c->mp);
   const long long fa0 = c->fine_applies, ca0 = c->coarse_applies;
   auto t0 = std::chrono::steady_clock::now();
   norm_into<double2>(c, b64, nullptr, nf, nrhs, S_B);
@@ -262,7 +270,7 @@ static void solve_impl(mgdwf_ctx* c, const M2* Dc, double2* b64, double2* x64, i
     std::vector<double> stop2(nrhs);
     for (int r = 0; r < nrhs; ++r) stop2[r] = 0.25 * sp.tol * sp.tol * b2[r];
     int kmax = std::min(restart, sp.max_outer - outer);
-    int k = fgcr_cycle<F2, M2>(c, M, rin, e, nrhs, kmax, stop2, nullptr);
+    int k = fgcr_cycle<F2>(c, M, rin, e, nrhs, kmax, stop2, nullptr);
     add_to<F2, double2>(x64, e, nf * nrhs, c->st);
     outer += k;
     ++restarts;
@@ -285,12 +293,10 @@ void mg_solve(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const mgdwf_so
               mgdwf_solve_report* rep) {
   if (c->mp.fine_prec == MGDWF_F64) {
     if (c->mp.coarse_prec != MGDWF_F64) fail(MGDWF_ERR_INVALID_ARG, "an FP64 fine level needs an FP64 coarse level");
-    solve_impl<double2, double2>(c, c->Dc64.as<double2>(), b64, x64, nrhs, sp, rep);
+    solve_impl<double2>(c, b64, x64, nrhs, sp, rep);
   } else if (c->mp.fine_prec == MGDWF_F32) {
-    if (c->mp.coarse_prec == MGDWF_F32)
-      solve_impl<float2, float2>(c, c->Dc32.as<float2>(), b64, x64, nrhs, sp, rep);
-    else
-      fail(MGDWF_ERR_INVALID_ARG, "coarse precision not available for the FP32 fine level");
+    if (c->mp.coarse_prec == MGDWF_F64) fail(MGDWF_ERR_INVALID_ARG, "an FP32 fine level takes an F32/F16/BF16 coarse level");
+    solve_impl<float2>(c, b64, x64, nrhs, sp, rep);
   } else {
     fail(MGDWF_ERR_INVALID_ARG, "fine precision must be F64 or F32");
   }
@@ -369,12 +375,12 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
   sweep.coarse_prec = MGDWF_F64;
   for (int s = 1; s < p.sweeps; ++s) {
     // inverse iteration: W <- (approximately) D^{-1} W with the current MG
-    TwoLevel<double2, double2> M(c, nh, sweep, c->Dc64.as<double2>());
+    TwoLevel<double2> M(c, nh, sweep);
     double2* r = c->buf<double2>("setup_r", nf * nh);
     double2* e = c->buf<double2>("setup_e", nf * nh);
     copy(c, W, r, nf * nh);
     std::vector<double> stop2(nh, -1.0);
-    fgcr_cycle<double2, double2>(c, M, r, e, nh, std::max(1, std::min(p.sweep_iters, 16)), stop2, nullptr);
+    fgcr_cycle<double2>(c, M, r, e, nh, std::max(1, std::min(p.sweep_iters, 16)), stop2, nullptr);
     copy(c, e, W, nf * nh);
     normalise(c, W, nh);
     rebuild();
@@ -383,6 +389,13 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
   }
   c->mp = p;
   c->have_params = true;
+  // the setup's work fields are large (several per vector): give them back
+  for (auto it = c->ws.begin(); it != c->ws.end();) {
+    if (it->first.rfind("cg_", 0) == 0 || it->first.rfind("setup_", 0) == 0 || it->first.rfind("dc_", 0) == 0)
+      it = c->ws.erase(it);
+    else
+      ++it;
+  }
   if (rep) {
     rep->sweeps_done = nsw;
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

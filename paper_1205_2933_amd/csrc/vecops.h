@@ -37,6 +37,7 @@ template <class C2>
 void reflect5(const C2* in, C2* out, const Geometry& g, int nf, hipStream_t st);
 
 // dslash.hip
+template <class C2>
 int dslash_nblocks(const Geometry& g);
 template <class C2>
 void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geometry& g, double M5, double mf,
@@ -56,9 +57,11 @@ bool orthonormalise_basis(double2* V, const Geometry& g, const CoarseGeometry& c
 void build_coarse_op(const double2* Vhat, const double2* gauge, double2* Dc, double2* work9, double2* cwork,
                      double* partial, const Geometry& g, const CoarseGeometry& cg, double M5, double mf,
                      hipStream_t st);
-void coarse_to_f32(const double2* Dc64, float2* Dc32, long long n, hipStream_t st);
-template <class MC2, class VC2>
-void coarse_apply(const MC2* Dc, const VC2* x, VC2* y, bool dagger, const CoarseGeometry& cg, int nrhs,
-                  hipStream_t st);
+void finish_coarse_op(CoarseStore& Dc, CoarseStore& DcH, const CoarseGeometry& cg, hipStream_t st);
+void coarse_apply64(const CoarseStore& s, const double2* x, double2* y, const CoarseGeometry& cg, int nrhs,
+                    hipStream_t st);
+size_t coarse_pack_bytes(const CoarseGeometry& cg, int nrhs);
+void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, float2* y, const CoarseGeometry& cg,
+                    int nrhs, void* pack, hipStream_t st);
 
 }  // namespace mgdwf

@@ -18,16 +18,16 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_mg_solve_c1(cuda, prec):
+@pytest.mark.parametrize("prec,cprec", [("f64", "f64"), ("f32", "f32"), ("f32", "f16"), ("f32", "bf16")])
+def test_mg_solve_c1(cuda, prec, cprec):
     import paper_1205_2933_amd as mg
     L, Ls, mf = (4, 4, 4, 4), 8, 0.01
     U = prepare_gauge(L, 0.3, 11)
     h = mg.Handle(L, Ls, 1.8, mf)
     mg.mgdwf_set_gauge(h, dev(U))
     p = mg.make_mg_params((2, 2, 2, 2), 16, sweeps=1, sweep0_iters=100, sweep_iters=4, coarse_tol=0.1,
-                          coarse_maxiter=200, fine_prec=prec, coarse_prec=prec)
-    print(f"setup C1 {prec}", flush=True)
+                          coarse_maxiter=200, fine_prec=prec, coarse_prec=cprec)
+    print(f"setup C1 {prec}/{cprec}", flush=True)
     rep = mg.mgdwf_setup(h, p, dev(random_starts(L, Ls, 8, 21)))
     print("setup report", rep, flush=True)
     b = gaussian_fermion(L, Ls, 31)

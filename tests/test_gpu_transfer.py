@@ -21,8 +21,13 @@ CASES = [
     ((4, 4, 4, 4), 8, (2, 2, 2, 2), 8, 0.01, (1, 1, 1, 1)),     # C1: coarse extent 2 (aliased +-mu)
     ((2, 2, 2, 2), 4, (2, 2, 2, 2), 6, 0.05, (1, 1, 1, 1)),     # a single coarse site: all d alias to self
     ((8, 4, 6, 4), 6, (4, 2, 2, 4), 10, 0.02, (1, -1, 1, -1)),  # ragged, coarse extents 2,2,3,1
-    ((4, 4, 6, 6), 4, (2, 2, 2, 2), 12, 0.001, (1, 1, 1, 1)),   # coarse extent 3: true 9-point stencil
+    ((4, 4, 6, 6), 4, (2, 2, 2, 2), 16, 0.001, (1, 1, 1, 1)),   # coarse extent 3: true 9-point stencil
 ]
+
+# 16-bit storage: per-block scale, FP32 accumulation.  Unit roundoff 2^-11 (FP16)
+# and 2^-8 (BF16, round to nearest even) on every matrix and vector entry; with
+# the per-site vector scale the relative error of y stays within a few units.
+LOWP_TOL = {"f16": 3e-3, "bf16": 2.5e-2}
 
 
 def dev(a):
@@ -111,9 +116,36 @@ def test_coarse_operator_matches_oracle(cuda, case):
     assert rel(Dc.cpu().numpy(), ref) < 1e-13
     # apply, both directions, FP64 and FP32
     c = np.random.default_rng(3).standard_normal(Lc[::-1] + (2, nvec)) + 1j * np.random.default_rng(4).standard_normal(Lc[::-1] + (2, nvec))
+    precs = [("f64", 1e-13), ("f32", 2e-6)]
+    if nvec % 8 == 0:
+        precs += [(p, LOWP_TOL[p]) for p in ("f16", "bf16")]
     for dagger in (False, True):
-        for prec, tol in (("f64", 1e-13), ("f32", 2e-6)):
+        for prec, tol in precs:
             y = torch.empty_like(dev(c))
             mg.mgdwf_apply_coarse(h, dev(c), y, dagger=dagger, prec=prec)
             torch.cuda.synchronize()
             assert rel(y.cpu().numpy(), oc.apply_coarse(c, ref, dagger=dagger)) < tol, (dagger, prec)
+
+
+def test_coarse_apply_many_rhs(cuda):
+    """18 right-hand sides: crosses the 8-RHS (FP64) and 16-RHS (FP32, MFMA) chunks."""
+    import paper_1205_2933_amd as mg
+    case = CASES[3]
+    L, Ls, block, nvec, mf, bc = case
+    h, U, V, Vh = make(case, mg)
+    mg.mgdwf_build_coarse(h)
+    Lc = tuple(L[m] // block[m] for m in range(4))
+    ref = oc.build_coarse_op(Vh, U, 1.8, mf, block, bc)
+    nr = 18
+    rng = np.random.default_rng(9)
+    c = rng.standard_normal((nr,) + Lc[::-1] + (2, nvec)) + 1j * rng.standard_normal((nr,) + Lc[::-1] + (2, nvec))
+    c[5] *= 1e-6   # a small RHS next to O(1) ones: the per-(site, RHS) scale keeps it accurate
+    for dagger in (False, True):
+        want = np.stack([oc.apply_coarse(c[r], ref, dagger=dagger) for r in range(nr)])
+        for prec, tol in (("f64", 1e-13), ("f32", 2e-6), ("f16", LOWP_TOL["f16"]), ("bf16", LOWP_TOL["bf16"])):
+            y = torch.empty_like(dev(c))
+            mg.mgdwf_apply_coarse(h, dev(c), y, dagger=dagger, prec=prec, nrhs=nr)
+            torch.cuda.synchronize()
+            got = y.cpu().numpy()
+            for r in range(nr):
+                assert rel(got[r], want[r]) < tol, (dagger, prec, r)
