@@ -38,7 +38,7 @@ def log(msg):
 
 
 def mg_params(mg, fine, coarse):
-    return mg.make_mg_params(BLOCK, NVEC, sweeps=1, sweep0_iters=400, sweep_iters=4, nu_pre=8, nu_post=8,
+    return mg.make_mg_params(BLOCK, NVEC, sweeps=1, sweep0_iters=400, sweep_iters=4, nu_pre=12, nu_post=12,
                              coarse_tol=0.1, coarse_maxiter=400, fine_prec=fine, coarse_prec=coarse)
 
 
@@ -126,7 +126,7 @@ def main():
     X = torch.zeros_like(B)
 
     # ---- mixed precision, 12 right-hand sides per step
-    mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f32"))
+    mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f16"))
 
     def step():
         X.zero_()

@@ -91,44 +91,47 @@ __global__ void k_adjoint_blocks(const double2* __restrict__ Dc, double2* __rest
 }
 
 // y[rhs] = sum_d M[X][d] x[rhs](X + delta_d) for up to NR right-hand sides, each
-// block read once for all of them.  Workgroup = one coarse site, 4 wavefronts;
-// wavefront w takes d = w, w+4, w+8; lane = output row; partial sums of the
-// four wavefronts are added in a fixed order through LDS.
+// block read once for all of them.  Workgroup = one coarse site, 9 wavefronts,
+// one per stencil direction d; lane = output row; the nine partial sums are
+// added in a fixed order through LDS.
 template <class MC2, class VC2, int NR>
-__global__ __launch_bounds__(256) void k_capply(const MC2* __restrict__ M, const VC2* __restrict__ x,
+__global__ __launch_bounds__(576) void k_capply(const MC2* __restrict__ M, const VC2* __restrict__ x,
                                                 VC2* __restrict__ y, CoarseArgs a, int nrhs, int rhs0) {
   using T = typename real_of<VC2>::type;
-  __shared__ T red[4][NR][64][2];
+  __shared__ T red[NR][64][2];
   const int X = blockIdx.x;
   const int n2 = a.n2;
-  const int w = threadIdx.x >> 6, row = threadIdx.x & 63;
+  const int d = threadIdx.x >> 6, row = threadIdx.x & 63;  // one wavefront per stencil direction
   const int nr = min(NR, nrhs - rhs0);
   const long long vs = (long long)a.Vc * n2;  // RHS stride
   VC2 acc[NR];
 #pragma unroll
   for (int j = 0; j < NR; ++j) acc[j] = cmk<VC2>(0, 0);
   if (row < n2) {
-    for (int d = w; d < 9; d += 4) {
-      const int Y = coarse_neighbour(a, X, d);
-      const MC2* Md = M + ((long long)X * 9 + d) * n2 * n2;
-      const VC2* xv = x + (long long)rhs0 * vs + (long long)Y * n2;
-      for (int c = 0; c < n2; ++c) {
-        const MC2 m = Md[c * n2 + row];
-        const VC2 mv = cmk<VC2>((T)m.x, (T)m.y);
+    const int Y = coarse_neighbour(a, X, d);
+    const MC2* Md = M + ((long long)X * 9 + d) * n2 * n2;
+    const VC2* xv = x + (long long)rhs0 * vs + (long long)Y * n2;
+    for (int c = 0; c < n2; ++c) {
+      const MC2 m = Md[c * n2 + row];
+      const VC2 mv = cmk<VC2>((T)m.x, (T)m.y);
 #pragma unroll
-        for (int j = 0; j < NR; ++j)
-          if (j < nr) cfma(acc[j], mv, xv[j * vs + c]);
-      }
+      for (int j = 0; j < NR; ++j)
+        if (j < nr) cfma(acc[j], mv, xv[j * vs + c]);
     }
   }
+  // add the nine directions in a fixed order (bitwise reproducible)
+  for (int w = 0; w < 9; ++w) {
+    if (d == w)
 #pragma unroll
-  for (int j = 0; j < NR; ++j) { red[w][j][row][0] = acc[j].x; red[w][j][row][1] = acc[j].y; }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nr * n2; i += 256) {
+      for (int j = 0; j < NR; ++j) {
+        if (w == 0) { red[j][row][0] = acc[j].x; red[j][row][1] = acc[j].y; }
+        else { red[j][row][0] += acc[j].x; red[j][row][1] += acc[j].y; }
+      }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < nr * n2; i += blockDim.x) {
     const int j = i / n2, r = i % n2;
-    VC2 s = cmk<VC2>(red[0][j][r][0] + red[1][j][r][0] + red[2][j][r][0] + red[3][j][r][0],
-                     red[0][j][r][1] + red[1][j][r][1] + red[2][j][r][1] + red[3][j][r][1]);
-    y[(long long)(rhs0 + j) * vs + (long long)X * n2 + r] = s;
+    y[(long long)(rhs0 + j) * vs + (long long)X * n2 + r] = cmk<VC2>(red[j][r][0], red[j][r][1]);
   }
 }
 
@@ -214,71 +217,68 @@ __device__ __forceinline__ f4v mfma16(uint2 a, uint2 b, f4v c) {
 // B[k 4(l/16)..+3][col l%16] and C[row 4(l/16)..+3][col l%16].  Each
 // direction's tile sum is rescaled by (block scale) x (input scale of its RHS)
 // before it joins the FP32 accumulator.  Workgroup = one coarse site and a
-// chunk of 16 RHS; wavefront w takes d = w, w+4, w+8.
+// chunk of 16 RHS; one wavefront per stencil direction d, the nine partial
+// results added in LDS in a fixed order.
 template <bool BF>
-__global__ __launch_bounds__(256) void k_capply_mfma(const uint16_t* __restrict__ Are, const uint16_t* __restrict__ Aim,
+__global__ __launch_bounds__(576) void k_capply_mfma(const uint16_t* __restrict__ Are, const uint16_t* __restrict__ Aim,
                                                      const float* __restrict__ Asc, const uint16_t* __restrict__ xp,
                                                      const float* __restrict__ xs, float2* __restrict__ y, CoarseArgs a,
                                                      int nrhs) {
   constexpr int MTMAX = 8;  // 2 n2 / 16 <= 8
-  __shared__ float red[4][128][17];
+  __shared__ float red[128][17];
   const int X = blockIdx.x;
   const int rhs0 = blockIdx.y * 16;
   const int n2 = a.n2;
   const int MT = 2 * n2 / 16;
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int d = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int col = l & 15, kq = l >> 4;
   const int rhs = rhs0 + col;
   const bool valid = rhs < nrhs;
-  f4v acc[MTMAX];
+  const int Y = coarse_neighbour(a, X, d);
+  const long long blk = (long long)X * 9 + d;
+  uint2 bf[MTMAX];
+  const uint16_t* xrow = xp + ((long long)(valid ? rhs : 0) * a.Vc + Y) * 2 * n2;
 #pragma unroll
-  for (int m = 0; m < MTMAX; ++m) acc[m] = f4v{0.f, 0.f, 0.f, 0.f};
-  for (int d = w; d < 9; d += 4) {
-    const int Y = coarse_neighbour(a, X, d);
-    const long long blk = (long long)X * 9 + d;
-    uint2 bf[MTMAX];
-    const uint16_t* xrow = xp + ((long long)(valid ? rhs : 0) * a.Vc + Y) * 2 * n2;
+  for (int kt = 0; kt < MTMAX; ++kt)
+    bf[kt] = (kt < MT && valid) ? *reinterpret_cast<const uint2*>(xrow + kt * 16 + 4 * kq) : make_uint2(0u, 0u);
+  f4v t[MTMAX];
 #pragma unroll
-    for (int kt = 0; kt < MTMAX; ++kt)
-      bf[kt] = (kt < MT && valid) ? *reinterpret_cast<const uint2*>(xrow + kt * 16 + 4 * kq) : make_uint2(0u, 0u);
-    f4v t[MTMAX];
+  for (int m = 0; m < MTMAX; ++m) t[m] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int m = 0; m < MTMAX; ++m) t[m] = f4v{0.f, 0.f, 0.f, 0.f};
+  for (int mt = 0; mt < MTMAX; ++mt) {
+    if (mt >= MT) continue;
+    const int i = mt * 16 + (l & 15);           // expanded row
+    const bool im_row = i >= n2;
+    const int rr = im_row ? i - n2 : i;
 #pragma unroll
-    for (int mt = 0; mt < MTMAX; ++mt) {
-      if (mt >= MT) continue;
-      const int i = mt * 16 + (l & 15);           // expanded row
-      const bool im_row = i >= n2;
-      const int rr = im_row ? i - n2 : i;
-#pragma unroll
-      for (int kt = 0; kt < MTMAX; ++kt) {
-        if (kt >= MT) continue;
-        const int k = kt * 16 + 4 * kq;             // expanded column of this lane's 4 values
-        const bool im_col = k >= n2;
-        const int kk = im_col ? k - n2 : k;
-        const uint16_t* src = (im_row != im_col) ? Aim : Are;
-        uint2 av = *reinterpret_cast<const uint2*>(src + blk * n2 * n2 + (long long)rr * n2 + kk);
-        if (!im_row && im_col) { av.x ^= 0x80008000u; av.y ^= 0x80008000u; }  // -Im in the upper right
-        t[mt] = mfma16<BF>(av, bf[kt], t[mt]);
-      }
+    for (int kt = 0; kt < MTMAX; ++kt) {
+      if (kt >= MT) continue;
+      const int k = kt * 16 + 4 * kq;             // expanded column of this lane's 4 values
+      const bool im_col = k >= n2;
+      const int kk = im_col ? k - n2 : k;
+      const uint16_t* src = (im_row != im_col) ? Aim : Are;
+      uint2 av = *reinterpret_cast<const uint2*>(src + blk * n2 * n2 + (long long)rr * n2 + kk);
+      if (!im_row && im_col) { av.x ^= 0x80008000u; av.y ^= 0x80008000u; }  // -Im in the upper right
+      t[mt] = mfma16<BF>(av, bf[kt], t[mt]);
     }
-    const float s = Asc[blk] * (valid ? xs[(long long)rhs * a.Vc + Y] : 0.f);
-#pragma unroll
-    for (int m = 0; m < MTMAX; ++m) acc[m] += s * t[m];
   }
+  const float s = Asc[blk] * (valid ? xs[(long long)rhs * a.Vc + Y] : 0.f);
+  for (int w = 0; w < 9; ++w) {
+    if (d == w) {
 #pragma unroll
-  for (int mt = 0; mt < MTMAX; ++mt)
-    if (mt < MT)
+      for (int mt = 0; mt < MTMAX; ++mt)
+        if (mt < MT)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) red[w][mt * 16 + 4 * kq + j][col] = acc[mt][j];
-  __syncthreads();
-  for (int i = threadIdx.x; i < 16 * n2; i += 256) {
-    const int r = i % n2, cl = i / n2;
-    if (rhs0 + cl < nrhs) {
-      const float re = red[0][r][cl] + red[1][r][cl] + red[2][r][cl] + red[3][r][cl];
-      const float im = red[0][n2 + r][cl] + red[1][n2 + r][cl] + red[2][n2 + r][cl] + red[3][n2 + r][cl];
-      y[((long long)(rhs0 + cl) * a.Vc + X) * n2 + r] = make_float2(re, im);
+          for (int j = 0; j < 4; ++j) {
+            float& r = red[mt * 16 + 4 * kq + j][col];
+            r = (w == 0 ? 0.f : r) + s * t[mt][j];
+          }
     }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < 16 * n2; i += blockDim.x) {
+    const int r = i % n2, cl = i / n2;
+    if (rhs0 + cl < nrhs) y[((long long)(rhs0 + cl) * a.Vc + X) * n2 + r] = make_float2(red[r][cl], red[n2 + r][cl]);
   }
 }
 
@@ -334,7 +334,7 @@ void coarse_apply64(const CoarseStore& s, const double2* x, double2* y, const Co
                     hipStream_t st) {
   if (cg.n2 > 64) fail(MGDWF_ERR_INVALID_ARG, "2*nvec above 64 is not supported");
   for (int r0 = 0; r0 < nrhs; r0 += 8) {
-    hipLaunchKernelGGL((k_capply<double2, double2, 8>), dim3(cg.Vc), dim3(256), 0, st, s.m64.as<double2>(), x, y,
+    hipLaunchKernelGGL((k_capply<double2, double2, 8>), dim3(cg.Vc), dim3(576), 0, st, s.m64.as<double2>(), x, y,
                        coarse_args(cg), nrhs, r0);
     MG_LAUNCH_CHECK();
   }
@@ -349,7 +349,7 @@ void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, floa
   if (cg.n2 > 64) fail(MGDWF_ERR_INVALID_ARG, "2*nvec above 64 is not supported");
   if (prec == MGDWF_F32 || prec == MGDWF_F64) {
     for (int r0 = 0; r0 < nrhs; r0 += 16) {
-      hipLaunchKernelGGL((k_capply<float2, float2, 16>), dim3(cg.Vc), dim3(256), 0, st, s.m32.as<float2>(), x, y,
+      hipLaunchKernelGGL((k_capply<float2, float2, 16>), dim3(cg.Vc), dim3(576), 0, st, s.m32.as<float2>(), x, y,
                          coarse_args(cg), nrhs, r0);
       MG_LAUNCH_CHECK();
     }
@@ -365,10 +365,10 @@ void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, floa
   MG_LAUNCH_CHECK();
   dim3 grid(cg.Vc, ceil_div(nrhs, 16));
   if (bf)
-    hipLaunchKernelGGL(k_capply_mfma<true>, grid, dim3(256), 0, st, s.reb.as<uint16_t>(), s.imb.as<uint16_t>(),
+    hipLaunchKernelGGL(k_capply_mfma<true>, grid, dim3(576), 0, st, s.reb.as<uint16_t>(), s.imb.as<uint16_t>(),
                        s.scb.as<float>(), xp, xs, y, coarse_args(cg), nrhs);
   else
-    hipLaunchKernelGGL(k_capply_mfma<false>, grid, dim3(256), 0, st, s.re16.as<uint16_t>(), s.im16.as<uint16_t>(),
+    hipLaunchKernelGGL(k_capply_mfma<false>, grid, dim3(576), 0, st, s.re16.as<uint16_t>(), s.im16.as<uint16_t>(),
                        s.sc16.as<float>(), xp, xs, y, coarse_args(cg), nrhs);
   MG_LAUNCH_CHECK();
 }

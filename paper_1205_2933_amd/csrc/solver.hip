@@ -27,6 +27,7 @@ constexpr int S_DOT = 8;                                          // multidot bl
 constexpr int S_QN = 48;                                          // |q_k|^2 at S_QN+k, <q_k, r> after it
 constexpr int S_RIN = 70, S_R64 = 71, S_B = 72, S_TMP = 73;       // FGCR residuals
 constexpr int S_GRR_A = 80, S_GRR_B = 81, S_GPAP = 82, S_G0 = 83; // CG on the normal equations
+constexpr int S_MR = 96;                                          // MR step i: |p_i|^2, |q_i|^2 at S_MR + 2i, +1
 
 template <class C2> struct Prec;
 template <> struct Prec<double2> { static constexpr const char* tag = "64"; };
@@ -123,15 +124,25 @@ struct TwoLevel {
     vpart = c->buf<double>("vpart", (size_t)VEC_BLOCKS * nrhs * (2 * 16 + 3));
   }
 
-  // nu steps of minimal residual along D^+ r on D x = b from x = 0.
+  // nu steps of minimal residual along D^+ r on D x = b from x = 0.  The
+  // directions p_i are kept and x = sum_i alpha_i p_i is formed once at the end,
+  // so a step moves r, q and the new r only; step 0 reads b in place of r.
   void smooth(const F2* b, F2* x, F2* r, int nu) {
-    copy(c, b, r, nf * nrhs);
-    if (nu == 0) { zero<F2>(x, nf * nrhs, c->st); return; }
-    for (int i = 0; i < nu; ++i) {
-      fine_op<F2>(c, r, pp, nullptr, true, 0, nrhs, S_PP);   // p = D^+ r, |p|^2
-      fine_op<F2>(c, pp, qq, nullptr, false, 0, nrhs, S_QQ); // q = D p,   |q|^2
-      mr_update<F2>(x, r, pp, qq, nf, nrhs, sl, S_PP, S_QQ, i == 0, nullptr, c->st);
+    if (nu == 0) {
+      copy(c, b, r, nf * nrhs);
+      zero<F2>(x, nf * nrhs, c->st);
+      return;
     }
+    const std::string t = Prec<F2>::tag;
+    std::vector<F2*> P(nu);
+    for (int i = 0; i < nu; ++i) P[i] = c->buf<F2>("mr_p" + std::to_string(i) + t, nf * nrhs);
+    for (int i = 0; i < nu; ++i) {
+      const F2* rin = i == 0 ? b : r;
+      fine_op<F2>(c, rin, P[i], nullptr, true, 0, nrhs, S_MR + 2 * i);      // p_i = D^+ r, |p_i|^2
+      fine_op<F2>(c, P[i], qq, nullptr, false, 0, nrhs, S_MR + 2 * i + 1);  // q = D p_i, |q|^2
+      res_update<F2>(r, rin, qq, nf, nrhs, sl, S_MR + 2 * i, S_MR + 2 * i + 1, c->st);
+    }
+    lincomb<F2>(x, ptr_table<F2>(c, "ptrP" + t, P), nu, nf, nrhs, sl, S_MR, c->st);
   }
 
   // CGNE on D_c: x = D_c^+ y with D_c D_c^+ y = b, to |r| < tol |b| or maxiter.

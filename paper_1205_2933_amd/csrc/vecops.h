@@ -5,7 +5,7 @@
 
 namespace mgdwf {
 
-constexpr int NSLOT = 96;        // scalar slots per right-hand side
+constexpr int NSLOT = 128;       // scalar slots per right-hand side
 constexpr int VEC_BLOCKS = 1024; // workgroups of the grid-stride vector kernels (partials per RHS)
 
 void finalize_rhs(const double* partial, int nparts, int ncomp, double* sl, int dst, int nrhs, hipStream_t st);
@@ -16,6 +16,11 @@ void mr_update(C2* x, C2* r, const C2* p, const C2* q, long long n, int nrhs, co
 template <class C2>
 void cg_dir(C2* p, const C2* r, long long n, int nrhs, const double* sl, int num, int den, double* partial,
             hipStream_t st);
+template <class C2>
+void res_update(C2* rout, const C2* rin, const C2* q, long long n, int nrhs, const double* sl, int num, int den,
+                hipStream_t st);
+template <class C2>
+void lincomb(C2* x, const C2* const* ps, int nv, long long n, int nrhs, const double* sl, int num, hipStream_t st);
 template <class C2>
 void multidot_rhs(const C2* const* avec, int nv, const C2* b, const C2* c, long long n, int nrhs, double* partial,
                   double* sl, int dst, hipStream_t st);

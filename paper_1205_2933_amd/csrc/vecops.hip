@@ -50,6 +50,43 @@ __global__ __launch_bounds__(256) void k_mr_update(C2* __restrict__ x, C2* __res
   }
 }
 
+// r_out = r_in - alpha q, alpha = sl[num] / sl[den]  (the residual half of an MR step;
+// r_in may equal r_out).
+template <class C2>
+__global__ __launch_bounds__(256) void k_res_update(C2* __restrict__ rout, const C2* rin, const C2* __restrict__ q,
+                                                    long long n, const double* __restrict__ sl, int num, int den) {
+  using T = typename real_of<C2>::type;
+  const int rhs = blockIdx.y;
+  const long long off = rhs * n;
+  const double dd = slot(sl, rhs, den);
+  const T alpha = (T)(dd > 0.0 ? slot(sl, rhs, num) / dd : 0.0);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    rout[off + i] = csub(rin[off + i], cscale(q[off + i], alpha));
+}
+
+// x = sum_m alpha_m p_m, alpha_m = sl[num + 2m] / sl[num + 2m + 1]  (m < nv)
+template <class C2>
+__global__ __launch_bounds__(256) void k_lincomb(C2* __restrict__ x, const C2* const* __restrict__ ps, int nv,
+                                                 long long n, const double* __restrict__ sl, int num) {
+  using T = typename real_of<C2>::type;
+  constexpr int MAXV = 16;
+  const int rhs = blockIdx.y;
+  const long long off = rhs * n;
+  T al[MAXV];
+#pragma unroll
+  for (int m = 0; m < MAXV; ++m) {
+    const double d = m < nv ? slot(sl, rhs, num + 2 * m + 1) : 0.0;
+    al[m] = (T)(d > 0.0 ? slot(sl, rhs, num + 2 * m) / d : 0.0);
+  }
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    C2 acc = cmk<C2>(0, 0);
+#pragma unroll
+    for (int m = 0; m < MAXV; ++m)
+      if (m < nv) acc = cadd(acc, cscale(ps[m][off + i], al[m]));
+    x[off + i] = acc;
+  }
+}
+
 // p = r + beta p, beta = sl[num] / sl[den]  (CG direction update); partial |p|^2
 template <class C2>
 __global__ __launch_bounds__(256) void k_cg_dir(C2* __restrict__ p, const C2* __restrict__ r, long long n,
@@ -244,6 +281,20 @@ void mr_update(C2* x, C2* r, const C2* p, const C2* q, long long n, int nrhs, co
 }
 
 template <class C2>
+void res_update(C2* rout, const C2* rin, const C2* q, long long n, int nrhs, const double* sl, int num, int den,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_res_update<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, rout, rin, q, n, sl, num, den);
+  MG_LAUNCH_CHECK();
+}
+
+template <class C2>
+void lincomb(C2* x, const C2* const* ps, int nv, long long n, int nrhs, const double* sl, int num, hipStream_t st) {
+  if (nv > 16) fail(MGDWF_ERR_INVALID_ARG, "at most 16 smoother steps");
+  hipLaunchKernelGGL(k_lincomb<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, x, ps, nv, n, sl, num);
+  MG_LAUNCH_CHECK();
+}
+
+template <class C2>
 void cg_dir(C2* p, const C2* r, long long n, int nrhs, const double* sl, int num, int den, double* partial,
             hipStream_t st) {
   hipLaunchKernelGGL(k_cg_dir<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, p, r, n, sl, num, den, partial);
@@ -310,6 +361,8 @@ void reflect5(const C2* in, C2* out, const Geometry& g, int nf, hipStream_t st) 
   template void mr_update<C2>(C2*, C2*, const C2*, const C2*, long long, int, const double*, int, int, bool,    \
                               double*, hipStream_t);                                                             \
   template void cg_dir<C2>(C2*, const C2*, long long, int, const double*, int, int, double*, hipStream_t);      \
+  template void res_update<C2>(C2*, const C2*, const C2*, long long, int, const double*, int, int, hipStream_t); \
+  template void lincomb<C2>(C2*, const C2* const*, int, long long, int, const double*, int, hipStream_t);        \
   template void multidot_rhs<C2>(const C2* const*, int, const C2*, const C2*, long long, int, double*, double*, \
                                  int, hipStream_t);                                                              \
   template void orth_update<C2>(C2*, C2*, const C2* const*, const C2* const*, int, long long, int,              \
