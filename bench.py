@@ -33,6 +33,26 @@ NVEC = 24
 HBM_PEAK_GBS = 8000.0
 
 
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "dslash_tp_f32_nrhs12_counters.md")
+DSLASH_SRC = os.path.join(ROOT, "paper_1205_2933_amd", "csrc", "dslash.hip")
+
+
+def counted_traffic():
+    """HBM bytes per launch of the FP32 Dslash at 12 RHS, from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary -- or None when the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = dict(line.split(":", 1) for line in open(COUNTER_SUMMARY) if line.startswith("- ") and ":" in line)
+        fields = {k[2:].strip(): v.strip().strip("`") for k, v in fields.items()}
+        src = hashlib.sha256(open(DSLASH_SRC, "rb").read()).hexdigest()
+        if fields.get("dslash.hip sha256") != src:
+            return None
+        return float(fields["traffic bytes per launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -168,6 +188,10 @@ def main():
     ms32 = mg.mgdwf_time_kernel(h, mg.MGDWF_K_DSLASH, "f32", 1, 50)
     gbs64 = bytes64 / (ms64 * 1e-3) / 1e9
     gbs32 = bytes64 / 2 / (ms32 * 1e-3) / 1e9
+    # the launch the timed step makes: 12 right-hand sides in one FP32 Dslash
+    bytes32_12 = nrhs * 2 * 12 * V4 * LS * 8 + 36 * V4 * 8
+    ms32_12 = mg.mgdwf_time_kernel(h, mg.MGDWF_K_DSLASH, "f32", nrhs, 20)
+    gbs32_12 = bytes32_12 / (ms32_12 * 1e-3) / 1e9
     msR = mg.mgdwf_time_kernel(h, mg.MGDWF_K_RESTRICT, "f32", 1, 10)
     msP = mg.mgdwf_time_kernel(h, mg.MGDWF_K_PROLONG, "f32", 1, 10)
     msC = mg.mgdwf_time_kernel(h, mg.MGDWF_K_COARSE, "f32", 1, 50)
@@ -201,12 +225,14 @@ def main():
         "setup_s": setup_s,
         "null_residual": srep["null_residual"],
         "dslash": {"f64_us": ms64 * 1e3, "f64_GBs": gbs64, "f32_us": ms32 * 1e3, "f32_GBs": gbs32,
-                   "f64_frac_peak": gbs64 / HBM_PEAK_GBS, "f32_frac_peak": gbs32 / HBM_PEAK_GBS},
+                   "f64_frac_peak": gbs64 / HBM_PEAK_GBS, "f32_frac_peak": gbs32 / HBM_PEAK_GBS,
+                   "f32_12rhs_us": ms32_12 * 1e3, "f32_12rhs_GBs": gbs32_12},
         "restrict_f32_GBs": rp_bytes32 / (msR * 1e-3) / 1e9,
         "prolong_f32_GBs": rp_bytes32 / (msP * 1e-3) / 1e9,
         "coarse_apply_f32_us": msC * 1e3,
-        "roofline": {"bound": "hbm", "kernel": "dslash f32", "achieved": gbs32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs32 / HBM_PEAK_GBS, "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": "k_dslash_tp<false,0> (FP32 Dslash, 12 RHS per launch)",
+                     "achieved": gbs32_12, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs32_12 / HBM_PEAK_GBS,
+                     "algorithmic_bytes": bytes32_12, "launch_us": ms32_12 * 1e3, "traffic": counted_traffic()},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

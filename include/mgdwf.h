@@ -190,6 +190,43 @@ mgdwf_status mgdwf_solve(mgdwf_handle h, const double* b, double* x, int32_t nrh
 mgdwf_status mgdwf_cgne(mgdwf_handle h, const double* b, double* x, const mgdwf_solve_params* p,
                         mgdwf_solve_report* report);
 
+/* ---- learned near-null proposals --------------------------------------- */
+
+/* A gauge-covariant network proposes the 4D part of near-null vectors from
+ * the gauge field and seeded noise; the fifth dimension is the free-field
+ * wall profile (every low mode shares it: the paper's Sec. 2, last
+ * paragraph).  Layer: out_o = sum_{d,i} W[d][o][i] T_d in_i with T_0 = 1,
+ * T_{1+2mu} f(x) = U_mu(x) f(x+mu), T_{2+2mu} f(x) = U_mu(x-mu)^+ f(x-mu);
+ * gate f |f|^2/(1+|f|^2) after layers 1..3; output channel 4k+alpha = spin
+ * alpha of proposal k; lift v_k(x,s) = P+ f_k w^(Ls-1-s) + P- f_k w^s,
+ * w = 1 - M5.  FP32 arithmetic, BF16 weights, FP32 Adam master weights. */
+typedef struct mgdwf_net_s* mgdwf_net;
+
+typedef struct {
+  int32_t channels[5]; /* input, three hidden, output (output = 4 x proposals) */
+  double lam;          /* weight of the Gram term of the training loss         */
+} mgdwf_net_config;
+
+mgdwf_status mgdwf_net_create(const mgdwf_net_config* cfg, mgdwf_net* out);
+mgdwf_status mgdwf_net_destroy(mgdwf_net net);
+/* Message of the last failed call on net (of the last failed create if NULL);
+ * calls that also take a handle store their message on the handle too. */
+const char* mgdwf_net_last_error(mgdwf_net net);
+/* Weights, HOST float arrays of mgdwf_net_num_weights entries, layer after
+ * layer, each layer [d = 0..8][out][in].  Setting them resets Adam. */
+int64_t mgdwf_net_num_weights(mgdwf_net net);
+mgdwf_status mgdwf_net_set_weights(mgdwf_net net, const float* w);
+mgdwf_status mgdwf_net_get_weights(mgdwf_net net, float* w);
+/* Lifted proposals V (canonical complex128, channels[4]/4 fine fields) on h's
+ * lattice and gauge field; eta: input channels, complex128 [C][x4][colour]. */
+mgdwf_status mgdwf_net_propose(mgdwf_net net, mgdwf_handle h, const double* eta, double* V);
+/* Training loss against the basis installed on h (set_nullvecs or setup):
+ * mean_k |(1 - P R) v_k|^2/|v_k|^2 + lam mean_{j<k} |<f_j,f_k>|^2/(|f_j|^2 |f_k|^2);
+ * *loss and the weight gradient (HOST float array, may be NULL). */
+mgdwf_status mgdwf_net_grad(mgdwf_net net, mgdwf_handle h, const double* eta, double* loss, float* grad);
+/* One Adam step (lr; beta 0.9 / 0.999) on that loss; *loss before the step. */
+mgdwf_status mgdwf_net_train_step(mgdwf_net net, mgdwf_handle h, const double* eta, double lr, double* loss);
+
 /* ---- measurement ------------------------------------------------------- */
 
 /* Kernel ids for mgdwf_time_kernel. */

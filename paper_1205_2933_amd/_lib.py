@@ -69,6 +69,10 @@ class mgdwf_setup_report(ctypes.Structure):
                 "seconds": self.seconds}
 
 
+class mgdwf_net_config(ctypes.Structure):
+    _fields_ = [("channels", ctypes.c_int32 * 5), ("lam", ctypes.c_double)]
+
+
 class MgdwfError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -103,6 +107,15 @@ def _load() -> ctypes.CDLL:
                        ctypes.c_int),
         "mgdwf_time_kernel": ([H, ctypes.c_int, ctypes.c_int, i32, i32, ctypes.POINTER(ctypes.c_double)],
                               ctypes.c_int),
+        "mgdwf_net_create": ([ctypes.POINTER(mgdwf_net_config), ctypes.POINTER(H)], ctypes.c_int),
+        "mgdwf_net_destroy": ([H], ctypes.c_int),
+        "mgdwf_net_last_error": ([H], ctypes.c_char_p),
+        "mgdwf_net_num_weights": ([H], ctypes.c_int64),
+        "mgdwf_net_set_weights": ([H, P], ctypes.c_int),
+        "mgdwf_net_get_weights": ([H, P], ctypes.c_int),
+        "mgdwf_net_propose": ([H, H, P, P], ctypes.c_int),
+        "mgdwf_net_grad": ([H, H, P, ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
+        "mgdwf_net_train_step": ([H, H, P, ctypes.c_double, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -280,3 +293,95 @@ def mgdwf_time_kernel(h: Handle, kernel: int, prec="f64", nrhs=1, iters=20) -> f
     ms = ctypes.c_double()
     _check(h.h, _lib.mgdwf_time_kernel(h.h, kernel, PREC[prec], nrhs, iters, ctypes.byref(ms)))
     return ms.value
+
+
+# ---- learned near-null proposals --------------------------------------------
+
+class Net:
+    """Owner of one mgdwf_net."""
+
+    def __init__(self, channels, lam=1.0):
+        cfg = mgdwf_net_config()
+        cfg.channels[:] = list(channels)
+        cfg.lam = lam
+        n = ctypes.c_void_p()
+        st = _lib.mgdwf_net_create(ctypes.byref(cfg), ctypes.byref(n))
+        if st != MGDWF_OK:
+            msg = _lib.mgdwf_net_last_error(None)
+            raise MgdwfError(st, msg.decode() if msg else "")
+        self.n = n
+        self.channels, self.lam = tuple(channels), lam
+        self.nweights = int(_lib.mgdwf_net_num_weights(n))
+        self.nh = channels[4] // 4
+
+    def close(self):
+        if self.n:
+            _lib.mgdwf_net_destroy(self.n)
+            self.n = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _net_check(net: Net, status: int):
+    if status != MGDWF_OK:
+        msg = _lib.mgdwf_net_last_error(net.n)
+        raise MgdwfError(status, msg.decode() if msg else "")
+
+
+def _host_f32(t: torch.Tensor, numel: int, name: str):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cpu" or t.dtype != torch.float32:
+        raise TypeError(f"{name} must be a host float32 tensor")
+    if not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name} must be contiguous with {numel} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mgdwf_net_create(channels, lam=1.0) -> Net:
+    return Net(channels, lam)
+
+
+def mgdwf_net_destroy(net: Net):
+    net.close()
+
+
+def mgdwf_net_last_error(net: Net | None) -> str:
+    m = _lib.mgdwf_net_last_error(net.n if net else None)
+    return m.decode() if m else ""
+
+
+def mgdwf_net_num_weights(net: Net) -> int:
+    return int(_lib.mgdwf_net_num_weights(net.n))
+
+
+def mgdwf_net_set_weights(net: Net, w: torch.Tensor):
+    _net_check(net, _lib.mgdwf_net_set_weights(net.n, _host_f32(w, net.nweights, "w")))
+
+
+def mgdwf_net_get_weights(net: Net) -> torch.Tensor:
+    w = torch.empty(net.nweights, dtype=torch.float32)
+    _net_check(net, _lib.mgdwf_net_get_weights(net.n, ctypes.c_void_p(w.data_ptr())))
+    return w
+
+
+def mgdwf_net_propose(net: Net, h: Handle, eta: torch.Tensor, V: torch.Tensor):
+    _net_check(net, _lib.mgdwf_net_propose(net.n, h.h, _dev(eta, net.channels[0] * h.V4 * 3, "eta"),
+                                           _dev(V, h.nfine * net.nh, "V")))
+
+
+def mgdwf_net_grad(net: Net, h: Handle, eta: torch.Tensor, want_grad=True):
+    loss = ctypes.c_double()
+    g = torch.empty(net.nweights, dtype=torch.float32) if want_grad else None
+    _net_check(net, _lib.mgdwf_net_grad(net.n, h.h, _dev(eta, net.channels[0] * h.V4 * 3, "eta"), ctypes.byref(loss),
+                                        ctypes.c_void_p(g.data_ptr()) if g is not None else None))
+    return loss.value, g
+
+
+def mgdwf_net_train_step(net: Net, h: Handle, eta: torch.Tensor, lr: float) -> float:
+    loss = ctypes.c_double()
+    _net_check(net, _lib.mgdwf_net_train_step(net.n, h.h, _dev(eta, net.channels[0] * h.V4 * 3, "eta"), lr,
+                                              ctypes.byref(loss)))
+    return loss.value

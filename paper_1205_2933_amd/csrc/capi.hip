@@ -443,3 +443,106 @@ mgdwf_status mgdwf_time_kernel(mgdwf_handle h, mgdwf_kernel k, mgdwf_prec prec, 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- learned proposals
+#include "nullnet.h"
+
+struct mgdwf_net_s {
+  mgdwf::NullNet net;
+  std::string err;
+};
+
+namespace {
+template <class F>
+mgdwf_status guarded_net(mgdwf_net n, mgdwf_handle h, F&& f) {
+  try {
+    f();
+    return MGDWF_OK;
+  } catch (const Error& e) {
+    if (h) h->err = e.msg;
+    if (n) n->err = e.msg;
+    if (!h && !n) g_create_error = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    if (h) h->err = e.what();
+    if (n) n->err = e.what();
+    return MGDWF_ERR_HIP;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+mgdwf_status mgdwf_net_create(const mgdwf_net_config* cfg, mgdwf_net* out) {
+  return guarded_net(nullptr, nullptr, [&] {
+    need(cfg && out, MGDWF_ERR_INVALID_ARG, "null argument");
+    for (int l = 0; l < 5; ++l) need(cfg->channels[l] >= 1 && cfg->channels[l] <= 64, MGDWF_ERR_INVALID_ARG, "channels must be in 1..64");
+    need(cfg->channels[4] % 4 == 0, MGDWF_ERR_INVALID_ARG, "output channels must be 4 x proposals");
+    need(cfg->lam >= 0.0, MGDWF_ERR_INVALID_ARG, "lam must be >= 0");
+    auto* n = new mgdwf_net_s();
+    for (int l = 0; l < 5; ++l) n->net.ch[l] = cfg->channels[l];
+    n->net.lam = cfg->lam;
+    try {
+      n->net.init();
+    } catch (...) {
+      delete n;
+      throw;
+    }
+    *out = n;
+  });
+}
+
+mgdwf_status mgdwf_net_destroy(mgdwf_net net) {
+  delete net;
+  return MGDWF_OK;
+}
+
+int64_t mgdwf_net_num_weights(mgdwf_net net) { return net ? net->net.nweights() : 0; }
+
+const char* mgdwf_net_last_error(mgdwf_net net) { return net ? net->err.c_str() : g_create_error.c_str(); }
+
+mgdwf_status mgdwf_net_set_weights(mgdwf_net net, const float* w) {
+  if (!net) return MGDWF_ERR_INVALID_ARG;
+  return guarded_net(net, nullptr, [&] {
+    need(w != nullptr, MGDWF_ERR_INVALID_ARG, "null weights");
+    net->net.set_weights(w, nullptr);
+  });
+}
+
+mgdwf_status mgdwf_net_get_weights(mgdwf_net net, float* w) {
+  if (!net) return MGDWF_ERR_INVALID_ARG;
+  return guarded_net(net, nullptr, [&] {
+    need(w != nullptr, MGDWF_ERR_INVALID_ARG, "null output");
+    MG_HIP(hipMemcpy(w, net->net.w.p, net->net.nweights() * sizeof(float), hipMemcpyDeviceToHost));
+  });
+}
+
+mgdwf_status mgdwf_net_propose(mgdwf_net net, mgdwf_handle h, const double* eta, double* V) {
+  if (!net || !h) return MGDWF_ERR_INVALID_ARG;
+  return guarded_net(net, h, [&] {
+    need(eta && V, MGDWF_ERR_INVALID_ARG, "null argument");
+    need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
+    mgdwf::net_propose(net->net, h, reinterpret_cast<const double2*>(eta), reinterpret_cast<double2*>(V));
+  });
+}
+
+mgdwf_status mgdwf_net_grad(mgdwf_net net, mgdwf_handle h, const double* eta, double* loss, float* grad) {
+  if (!net || !h) return MGDWF_ERR_INVALID_ARG;
+  return guarded_net(net, h, [&] {
+    need(eta && loss, MGDWF_ERR_INVALID_ARG, "null argument");
+    need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
+    *loss = mgdwf::net_grad(net->net, h, reinterpret_cast<const double2*>(eta));
+    if (grad) MG_HIP(hipMemcpy(grad, net->net.g.p, net->net.nweights() * sizeof(float), hipMemcpyDeviceToHost));
+  });
+}
+
+mgdwf_status mgdwf_net_train_step(mgdwf_net net, mgdwf_handle h, const double* eta, double lr, double* loss) {
+  if (!net || !h) return MGDWF_ERR_INVALID_ARG;
+  return guarded_net(net, h, [&] {
+    need(eta && loss && lr > 0, MGDWF_ERR_INVALID_ARG, "bad argument");
+    need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
+    *loss = mgdwf::net_train_step(net->net, h, reinterpret_cast<const double2*>(eta), lr);
+  });
+}
+
+}  // extern "C"

@@ -184,20 +184,23 @@ __global__ __launch_bounds__(256) void k_pack_blocks(const double2* __restrict__
 
 // Coarse vectors -> 16-bit with one scale per (site, RHS):
 // xp[(rhs * Vc + X) * 2 n2 + k] = Re x_k / s, [.. + n2 + k] = Im x_k / s.
+// One wavefront per (RHS, site), lane k < n2 <= 64 handles component k.
 template <bool BF>
-__global__ void k_pack_vec(const float2* __restrict__ x, uint16_t* __restrict__ xp, float* __restrict__ xs,
-                           int Vc, int n2, int nrhs) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)nrhs * Vc) return;
-  const float2* v = x + i * n2;
-  float mx = 0.f;
-  for (int k = 0; k < n2; ++k) mx = fmaxf(mx, fmaxf(fabsf(v[k].x), fabsf(v[k].y)));
+__global__ __launch_bounds__(256) void k_pack_vec(const float2* __restrict__ x, uint16_t* __restrict__ xp,
+                                                  float* __restrict__ xs, int Vc, int n2, int nrhs) {
+  const long long i = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int k = threadIdx.x & 63;
+  if (i >= (long long)nrhs * Vc) return;  // whole wavefronts leave together
+  const float2 v = k < n2 ? x[i * n2 + k] : make_float2(0.f, 0.f);
+  float mx = fmaxf(fabsf(v.x), fabsf(v.y));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
   const float inv = mx > 0.f ? 1.f / mx : 0.f;
-  xs[i] = mx;
-  uint16_t* o = xp + i * 2 * n2;
-  for (int k = 0; k < n2; ++k) {
-    o[k] = to16<BF>(v[k].x * inv);
-    o[n2 + k] = to16<BF>(v[k].y * inv);
+  if (k == 0) xs[i] = mx;
+  if (k < n2) {
+    uint16_t* o = xp + i * 2 * n2;
+    o[k] = to16<BF>(v.x * inv);
+    o[n2 + k] = to16<BF>(v.y * inv);
   }
 }
 
@@ -360,8 +363,8 @@ void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, floa
   uint16_t* xp = static_cast<uint16_t*>(pack);
   float* xs = reinterpret_cast<float*>(xp + (size_t)nrhs * cg.Vc * 2 * cg.n2);
   const long long nsv = (long long)nrhs * cg.Vc;
-  if (bf) hipLaunchKernelGGL(k_pack_vec<true>, dim3(ceil_div(nsv, 256)), dim3(256), 0, st, x, xp, xs, cg.Vc, cg.n2, nrhs);
-  else hipLaunchKernelGGL(k_pack_vec<false>, dim3(ceil_div(nsv, 256)), dim3(256), 0, st, x, xp, xs, cg.Vc, cg.n2, nrhs);
+  if (bf) hipLaunchKernelGGL(k_pack_vec<true>, dim3(ceil_div(nsv, 4)), dim3(256), 0, st, x, xp, xs, cg.Vc, cg.n2, nrhs);
+  else hipLaunchKernelGGL(k_pack_vec<false>, dim3(ceil_div(nsv, 4)), dim3(256), 0, st, x, xp, xs, cg.Vc, cg.n2, nrhs);
   MG_LAUNCH_CHECK();
   dim3 grid(cg.Vc, ceil_div(nrhs, 16));
   if (bf)
