@@ -237,6 +237,29 @@ typedef enum {
   MGDWF_K_COARSE = 3     /* D_c apply                               */
 } mgdwf_kernel;
 
+/* Autotuning of the FP32 Dslash: every tiling of the t-march kernel that
+ * the lattice admits is timed (mgdwf_time_kernel's method, `iters` launches at
+ * nrhs right-hand sides, D and D^+ alternating) and the fastest is kept on the
+ * handle for every later FP32 fine-operator application.  Without a call the
+ * first admissible tiling of the table is used.  Results are identical up to
+ * FP32 rounding order whatever the tiling. */
+#define MGDWF_MAX_TILINGS 16
+#define MGDWF_TILE_RELOAD 1      /* kernel that reloads each slice's own spinor          */
+#define MGDWF_TILE_FOLDED 2      /* workgroups ordered t-chunk first across all RHS       */
+#define MGDWF_TILE_ONE_PER_CU 4  /* LDS reserved so one workgroup runs per CU             */
+typedef struct {
+  int32_t ntilings;                   /* tilings timed                                  */
+  int32_t chosen;                     /* index into the arrays below                     */
+  int32_t id[MGDWF_MAX_TILINGS];      /* tiling id, for mgdwf_set_tiling                 */
+  int32_t tile[MGDWF_MAX_TILINGS][4]; /* x, y, z sites per workgroup, t-slices per one   */
+  int32_t flags[MGDWF_MAX_TILINGS];   /* MGDWF_TILE_* bits                               */
+  double us[MGDWF_MAX_TILINGS];       /* mean time per launch                           */
+} mgdwf_tune_report;
+mgdwf_status mgdwf_tune(mgdwf_handle h, int32_t nrhs, int32_t iters, mgdwf_tune_report* report);
+/* Use tiling `id` (from a tune report) for later FP32 applications; -1 restores
+ * the default.  MGDWF_ERR_INVALID_ARG if the lattice does not admit it. */
+mgdwf_status mgdwf_set_tiling(mgdwf_handle h, int32_t id);
+
 /* Launch kernel `k` `iters` times back to back on the handle's stream on
  * internal buffers and return the mean time per launch in *ms, measured with
  * HIP events recorded on that stream. */

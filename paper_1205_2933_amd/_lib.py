@@ -69,6 +69,21 @@ class mgdwf_setup_report(ctypes.Structure):
                 "seconds": self.seconds}
 
 
+MGDWF_MAX_TILINGS = 16
+
+
+class mgdwf_tune_report(ctypes.Structure):
+    _fields_ = [("ntilings", ctypes.c_int32), ("chosen", ctypes.c_int32), ("id", ctypes.c_int32 * MGDWF_MAX_TILINGS),
+                ("tile", (ctypes.c_int32 * 4) * MGDWF_MAX_TILINGS), ("flags", ctypes.c_int32 * MGDWF_MAX_TILINGS),
+                ("us", ctypes.c_double * MGDWF_MAX_TILINGS)]
+
+    def as_dict(self):
+        n = self.ntilings
+        return {"chosen": self.chosen, "id": [self.id[i] for i in range(n)],
+                "tile": [list(self.tile[i]) for i in range(n)], "flags": [self.flags[i] for i in range(n)],
+                "us": [self.us[i] for i in range(n)]}
+
+
 class mgdwf_net_config(ctypes.Structure):
     _fields_ = [("channels", ctypes.c_int32 * 5), ("lam", ctypes.c_double)]
 
@@ -107,6 +122,8 @@ def _load() -> ctypes.CDLL:
                        ctypes.c_int),
         "mgdwf_time_kernel": ([H, ctypes.c_int, ctypes.c_int, i32, i32, ctypes.POINTER(ctypes.c_double)],
                               ctypes.c_int),
+        "mgdwf_tune": ([H, i32, i32, ctypes.POINTER(mgdwf_tune_report)], ctypes.c_int),
+        "mgdwf_set_tiling": ([H, i32], ctypes.c_int),
         "mgdwf_net_create": ([ctypes.POINTER(mgdwf_net_config), ctypes.POINTER(H)], ctypes.c_int),
         "mgdwf_net_destroy": ([H], ctypes.c_int),
         "mgdwf_net_last_error": ([H], ctypes.c_char_p),
@@ -293,6 +310,16 @@ def mgdwf_time_kernel(h: Handle, kernel: int, prec="f64", nrhs=1, iters=20) -> f
     ms = ctypes.c_double()
     _check(h.h, _lib.mgdwf_time_kernel(h.h, kernel, PREC[prec], nrhs, iters, ctypes.byref(ms)))
     return ms.value
+
+
+def mgdwf_tune(h: Handle, nrhs=1, iters=10) -> dict:
+    rep = mgdwf_tune_report()
+    _check(h.h, _lib.mgdwf_tune(h.h, nrhs, iters, ctypes.byref(rep)))
+    return rep.as_dict()
+
+
+def mgdwf_set_tiling(h: Handle, tiling_id: int):
+    _check(h.h, _lib.mgdwf_set_tiling(h.h, tiling_id))
 
 
 # ---- learned near-null proposals --------------------------------------------

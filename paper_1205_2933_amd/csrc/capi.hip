@@ -442,6 +442,71 @@ mgdwf_status mgdwf_time_kernel(mgdwf_handle h, mgdwf_kernel k, mgdwf_prec prec, 
   });
 }
 
+mgdwf_status mgdwf_tune(mgdwf_handle h, int32_t nrhs, int32_t iters, mgdwf_tune_report* rep) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(rep && iters >= 1 && nrhs >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
+    need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
+    std::memset(rep, 0, sizeof(*rep));
+    rep->chosen = -1;
+    const long long nf = h->fine_len() * nrhs;
+    float2* a = h->buf<float2>("t_a32", nf);
+    float2* b = h->buf<float2>("t_b32", nf);
+    zero<float2>(a, nf, h->st);
+    struct Events {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      ~Events() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+      }
+    } ev;
+    MG_HIP(hipEventCreate(&ev.e0));
+    MG_HIP(hipEventCreate(&ev.e1));
+    int best = -1;
+    double best_us = 0.0;
+    for (int i = 0; i < dslash_ftile_count() && rep->ntilings < MGDWF_MAX_TILINGS; ++i) {
+      Geometry g = h->g;
+      g.ftile = i;
+      int desc[4], flags = 0;
+      if (!dslash_ftile_desc(g, i, desc, &flags)) continue;
+      auto run = [&](int n) {
+        for (int k = 0; k < n; ++k)
+          dslash_ex<float2>(a, b, nullptr, h->U32.as<float2>(), g, h->M5, h->mf, (k & 1) != 0, 0, nrhs, nullptr,
+                            h->st);
+      };
+      run(2);
+      MG_HIP(hipEventRecord(ev.e0, h->st));
+      run(iters);
+      MG_HIP(hipEventRecord(ev.e1, h->st));
+      MG_HIP(hipEventSynchronize(ev.e1));
+      float ms = 0.f;
+      MG_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+      const double us = 1e3 * ms / iters;
+      const int j = rep->ntilings++;
+      rep->id[j] = i;
+      rep->flags[j] = flags;
+      for (int q = 0; q < 4; ++q) rep->tile[j][q] = desc[q];
+      rep->us[j] = us;
+      if (best < 0 || us < best_us) {
+        best = i;
+        best_us = us;
+        rep->chosen = j;
+      }
+    }
+    if (best >= 0) h->g.ftile = best;
+  });
+}
+
+mgdwf_status mgdwf_set_tiling(mgdwf_handle h, int32_t id) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    int desc[4], flags = 0;
+    need(id == -1 || dslash_ftile_desc(h->g, id, desc, &flags), MGDWF_ERR_INVALID_ARG,
+         "tiling does not apply to this lattice");
+    h->g.ftile = id;
+  });
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- learned proposals

@@ -359,6 +359,8 @@ struct TMArgs {
   DslashArgs d;
   int ntx, nty, ntz;  // tiles per direction
   int tc;             // t-slices per chunk
+  int fold = 0;       // 1: one-dimensional grid over (t-chunk, rhs, tile), t-chunk outermost
+  int nrhs = 1;
 };
 
 __device__ __forceinline__ double block_sum_dyn(double v) {
@@ -670,18 +672,243 @@ __global__ __launch_bounds__(256) void k_dslash_tp(const float2* __restrict__ in
   }
 }
 
-}  // namespace
-
-// s-pair t-march (FP32): x, y, z extents tile by 4, 4, 2 and Ls is even, 4..16.
-static bool use_tpair(const Geometry& g) {
-  return g.L[0] % TPX == 0 && g.L[1] % TPY == 0 && g.L[2] % TPZ == 0 && g.Ls % 2 == 0 && g.Ls >= 4 &&
-         g.Ls <= 16 && (TPS * g.Ls / 2) % 64 == 0;
+// ---------------------------------------------------------------- t-march, carried own slice (FP32)
+// As k_dslash_tp, with the spinor of slice t+1 loaded once: the forward
+// t-hop of slice t uses it, and in the same registers it gives slice t+1's
+// diagonal and fifth-dimension terms and the half spinor of slice t+2's
+// backward t-hop.  Seven spinor loads per step instead of eight.  The tile
+// (TX x TY x TZ sites of x, y, z) is a template parameter so several shapes
+// can be timed on the device.
+//
+// acc holds -2 x (the own terms) plus the hop sum, so out = -acc / 2 exactly
+// as D = (own terms) - 1/2 (hops).
+__device__ __forceinline__ void own_pair(Spinor<float2>& a0, Spinor<float2>& a1, const Spinor<float2>& p0,
+                                         const Spinor<float2>& p1, const float2* __restrict__ in, long long V5,
+                                         long long base, int s0, int Ls, float dg, float mf, int up0, int dn0) {
+  const int sm = s0 == 0 ? Ls - 1 : s0 - 1;
+  const int sp2 = s0 + 2 == Ls ? 0 : s0 + 2;
+  const float cdn0 = s0 == 0 ? mf : -1.f;       // s0 - 1 across the wall
+  const float cup1 = s0 + 2 == Ls ? mf : -1.f;  // s0 + 2 across the wall
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long cc = (long long)(sp * 3 + c) * V5 + base;
+      float2 r0 = cscale(p0.v[sp][c], dg), r1 = cscale(p1.v[sp][c], dg);
+      if (sp == up0 || sp == up0 + 1) {
+        r0 = csub(r0, p1.v[sp][c]);                     // s0 <- s0 + 1
+        r1 = cadd(r1, cscale(in[cc + sp2], cup1));      // s0 + 1 <- s0 + 2
+      }
+      if (sp == dn0 || sp == dn0 + 1) {
+        r0 = cadd(r0, cscale(in[cc + sm], cdn0));       // s0 <- s0 - 1
+        r1 = csub(r1, p0.v[sp][c]);                     // s0 + 1 <- s0
+      }
+      a0.v[sp][c] = cscale(r0, -2.f);
+      a1.v[sp][c] = cscale(r1, -2.f);
+    }
 }
 
-static int tpair_chunk(const Geometry& g) {
-  const int ntiles = (g.L[0] / TPX) * (g.L[1] / TPY) * (g.L[2] / TPZ);
-  const int want_chunks = std::max(1, std::min(g.L[3], ceil_div(512, ntiles)));
+template <bool DAG, int MODE, int TX, int TY, int TZ, int PAD>
+__global__ __launch_bounds__(TX * TY * TZ * 8, 2) void k_dslash_tq(const float2* __restrict__ in,
+                                                               float2* __restrict__ out,
+                                                               const float2* __restrict__ b,
+                                                               const float2* __restrict__ gauge, TMArgs ta,
+                                                               double* __restrict__ partial) {
+  if (PAD > 0) {  // LDS reserved only to cap workgroups per CU (one per CU when PAD > 80 KB)
+    __shared__ float pad[PAD > 0 ? PAD / 4 : 1];
+    if (ta.d.Ls < 0) pad[threadIdx.x] = 0.f;  // never true: keeps the allocation
+    if (ta.d.Ls < 0) out[threadIdx.x].x = pad[threadIdx.x ^ 1];
+  }
+  const DslashArgs& a = ta.d;
+  const int ntiles = ta.ntx * ta.nty * ta.ntz;
+  // fold 0: grid (chunks x tiles, rhs), chunk-major per rhs.  fold 1: the
+  // rhs folds into x with the t-chunk outermost, so the contiguous range of
+  // workgroups each XCD receives covers whole t-chunks of every rhs.
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  int chunk, tile, rhs, pidx;
+  if (ta.fold) {
+    const int per_chunk = ta.nrhs * ntiles;
+    chunk = bid / per_chunk;
+    const int r2 = bid - chunk * per_chunk;
+    rhs = r2 / ntiles;
+    tile = r2 - rhs * ntiles;
+    pidx = rhs * (gridDim.x / ta.nrhs) + chunk * ntiles + tile;
+  } else {
+    chunk = bid / ntiles;
+    tile = bid - chunk * ntiles;
+    rhs = blockIdx.y;
+    pidx = blockIdx.y * gridDim.x + blockIdx.x;
+  }
+  const int tx = tile % ta.ntx, ty = (tile / ta.ntx) % ta.nty, tz = tile / (ta.ntx * ta.nty);
+  const int Ls = a.Ls, np = Ls >> 1;
+  const int site = threadIdx.x / np, jp = threadIdx.x - site * np;
+  const int s0 = 2 * jp;
+  const int x = tx * TX + site % TX, y = ty * TY + (site / TX) % TY, z = tz * TZ + site / (TX * TY);
+  const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2], Lt = a.L[3];
+  const long long V5 = a.V5, V4 = a.V4;
+  const int V3 = Lx * Ly * Lz;
+  const long long roff = (long long)rhs * 12 * V5;
+  in += roff;
+  out += roff;
+  if (MODE == 1) b += roff;
+  const int x3 = (z * Ly + y) * Lx + x;
+  int nf3[3], nb3[3];
+  float phf[3], phb[3];
+  {
+    const int co[3] = {x, y, z};
+    const int Lm[3] = {Lx, Ly, Lz};
+    const int st[3] = {1, Lx, Lx * Ly};
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      const bool top = co[mu] == Lm[mu] - 1, bot = co[mu] == 0;
+      nf3[mu] = top ? x3 - (Lm[mu] - 1) * st[mu] : x3 + st[mu];
+      nb3[mu] = bot ? x3 + (Lm[mu] - 1) * st[mu] : x3 - st[mu];
+      phf[mu] = top ? a.ph[mu] : 1.0f;
+      phb[mu] = bot ? a.ph[mu] : 1.0f;
+    }
+  }
+  constexpr int EF = DAG ? 1 : -1;
+  constexpr int EB = DAG ? -1 : 1;
+  const int up0 = DAG ? 0 : 2;   // spins coupled to s+1
+  const int dn0 = DAG ? 2 : 0;   // spins coupled to s-1
+  const float dg = (float)a.diag, mf = (float)a.mf;
+  const int t0 = chunk * ta.tc;
+  const int t1 = min(t0 + ta.tc, Lt);
+  float2 hp0[2][3], hp1[2][3], U[3][3], h[2][3], u[2][3];
+  Spinor<float2> p0, p1, a0, a1;
+  {  // slice t0: own terms, and the backward t-hop from slice t0 - 1
+    const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+    const int x4m = tm * V3 + x3;
+    load_pair(p0, p1, in, V5, (long long)x4m * Ls + s0);
+    project<3, EB>(p0, hp0);
+    project<3, EB>(p1, hp1);
+    const long long base = (long long)(t0 * V3 + x3) * Ls;
+    load_pair(p0, p1, in, V5, base + s0);
+    own_pair(a0, a1, p0, p1, in, V5, base, s0, Ls, dg, mf, up0, dn0);
+    load_link(gauge, 3, V4, x4m, U);
+    const float ph = t0 == 0 ? a.ph[3] : 1.0f;
+    mul_link<true>(U, hp0, u, ph);
+    accumulate<3, EB>(a0, u);
+    mul_link<true>(U, hp1, u, ph);
+    accumulate<3, EB>(a1, u);
+    project<3, EB>(p0, hp0);
+    project<3, EB>(p1, hp1);
+  }
+  double nrm = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int x4 = t * V3 + x3;
+    const int tb = t * V3;
+    hop_pair<0, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[0]) * Ls + s0, x4, phf[0]);
+    hop_pair<0, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[0]) * Ls + s0, tb + nb3[0], phb[0]);
+    hop_pair<1, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[1]) * Ls + s0, x4, phf[1]);
+    hop_pair<1, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[1]) * Ls + s0, tb + nb3[1], phb[1]);
+    hop_pair<2, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[2]) * Ls + s0, x4, phf[2]);
+    hop_pair<2, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[2]) * Ls + s0, tb + nb3[2], phb[2]);
+    // forward t-hop with slice t+1
+    const bool top = t == Lt - 1;
+    const long long basef = (long long)((top ? 0 : t + 1) * V3 + x3) * Ls;
+    load_pair(p0, p1, in, V5, basef + s0);
+    load_link(gauge, 3, V4, x4, U);
+    {
+      const float ph = top ? a.ph[3] : 1.0f;
+      project<3, EF>(p0, h);
+      mul_link<false>(U, h, u, ph);
+      accumulate<3, EF>(a0, u);
+      project<3, EF>(p1, h);
+      mul_link<false>(U, h, u, ph);
+      accumulate<3, EF>(a1, u);
+    }
+    const long long i5 = (long long)x4 * Ls + s0;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long cc = (long long)(sp * 3 + c) * V5;
+        float2 r0 = cscale(a0.v[sp][c], -0.5f), r1 = cscale(a1.v[sp][c], -0.5f);
+        if (MODE == 1) {
+          const float4 bb = *reinterpret_cast<const float4*>(b + cc + i5);
+          r0 = make_float2(bb.x - r0.x, bb.y - r0.y);
+          r1 = make_float2(bb.z - r1.x, bb.w - r1.y);
+        }
+        *reinterpret_cast<float4*>(out + cc + i5) = make_float4(r0.x, r0.y, r1.x, r1.y);
+        nrm += (double)r0.x * r0.x + (double)r0.y * r0.y + (double)r1.x * r1.x + (double)r1.y * r1.y;
+      }
+    if (t + 1 < t1) {  // slice t+1: own terms, backward t-hop from slice t (never across the boundary here)
+      own_pair(a0, a1, p0, p1, in, V5, basef, s0, Ls, dg, mf, up0, dn0);
+      mul_link<true>(U, hp0, u, 1.0f);
+      accumulate<3, EB>(a0, u);
+      mul_link<true>(U, hp1, u, 1.0f);
+      accumulate<3, EB>(a1, u);
+      project<3, EB>(p0, hp0);
+      project<3, EB>(p1, hp1);
+    }
+  }
+  if (partial) {
+    const double sum = block_sum_dyn(nrm);
+    if (threadIdx.x == 0) partial[pidx] = sum;
+  }
+}
+
+}  // namespace
+
+// FP32 t-march tilings: x, y, z tile, workgroups aimed at per right-hand side
+// (sets the t-slices per workgroup), which kernel, workgroup order and
+// occupancy.  Entry 0 is the default; mgdwf_tune times the others on the
+// device.  Measured on 16^3 x 32 x 16 at 12 RHS the spread is within 10 %:
+// the kernel fetches about 3.8x its algorithmic bytes from beyond L2 (tile
+// faces re-read by the neighbouring workgroups), and one workgroup per CU --
+// half the footprint in L2 -- is slightly ahead of two.
+struct FTile {
+  int tx, ty, tz, target;
+  bool eight_loads;  // k_dslash_tp (reloads the own slice) instead of k_dslash_tq
+  int fold;          // workgroup order (TMArgs::fold)
+  bool one_per_cu = false;  // reserve LDS so that one workgroup runs per CU
+};
+constexpr FTile kFTiles[] = {
+    {4, 4, 2, 256, false, 0, true}, {4, 4, 2, 512, false, 0, true}, {4, 4, 2, 256, false, 0},
+    {4, 4, 2, 512, false, 0},       {8, 2, 2, 512, false, 0},       {8, 4, 2, 256, false, 0},
+    {4, 4, 4, 512, false, 0},       {4, 8, 2, 512, false, 0},       {4, 4, 2, 1024, false, 1},
+    {4, 4, 2, 512, true, 0},
+};
+constexpr int NFTILE = sizeof(kFTiles) / sizeof(kFTiles[0]);
+
+// A tiling applies when x, y, z divide by the tile and Ls is even, 4..16,
+// with whole wavefronts per workgroup.
+static bool ftile_ok(const Geometry& g, int i) {
+  if (i < 0 || i >= NFTILE) return false;
+  const FTile& f = kFTiles[i];
+  const int thr = f.tx * f.ty * f.tz * g.Ls / 2;
+  return g.L[0] % f.tx == 0 && g.L[1] % f.ty == 0 && g.L[2] % f.tz == 0 && g.Ls % 2 == 0 && g.Ls >= 4 &&
+         g.Ls <= 16 && thr % 64 == 0;
+}
+
+static int ftile_of(const Geometry& g) {
+  if (ftile_ok(g, g.ftile)) return g.ftile;
+  for (int i = 0; i < NFTILE; ++i)
+    if (ftile_ok(g, i)) return i;
+  return -1;
+}
+
+static int ftile_ntiles(const Geometry& g, int i) {
+  const FTile& f = kFTiles[i];
+  return (g.L[0] / f.tx) * (g.L[1] / f.ty) * (g.L[2] / f.tz);
+}
+
+static int ftile_chunk(const Geometry& g, int i) {
+  const int want_chunks = std::max(1, std::min(g.L[3], ceil_div(kFTiles[i].target, ftile_ntiles(g, i))));
   return ceil_div(g.L[3], want_chunks);
+}
+
+int dslash_ftile_count() { return NFTILE; }
+
+bool dslash_ftile_desc(const Geometry& g, int i, int desc[4], int* flags) {
+  if (!ftile_ok(g, i)) return false;
+  desc[0] = kFTiles[i].tx;
+  desc[1] = kFTiles[i].ty;
+  desc[2] = kFTiles[i].tz;
+  desc[3] = ftile_chunk(g, i);
+  *flags = (kFTiles[i].eight_loads ? 1 : 0) | (kFTiles[i].fold ? 2 : 0) | (kFTiles[i].one_per_cu ? 4 : 0);
+  return true;
 }
 
 // The t-march kernel covers lattices whose x, y, z extents tile by 4, 2, 2 and
@@ -697,18 +924,48 @@ static int tmarch_chunk(const Geometry& g) {
   return ceil_div(g.L[3], want_chunks);
 }
 
+template <int TX, int TY, int TZ, int PAD>
+static void launch_tq(const float2* in, float2* out, const float2* b, const float2* gauge, const TMArgs& ta,
+                      double* partial, bool dagger, int mode, dim3 grid, dim3 blk, hipStream_t st) {
+#define MG_TQ(DAG, MODE) \
+  hipLaunchKernelGGL((k_dslash_tq<DAG, MODE, TX, TY, TZ, PAD>), grid, blk, 0, st, in, out, b, gauge, ta, partial)
+  if (!dagger && mode == 0) MG_TQ(false, 0);
+  else if (!dagger && mode == 1) MG_TQ(false, 1);
+  else if (dagger && mode == 0) MG_TQ(true, 0);
+  else MG_TQ(true, 1);
+#undef MG_TQ
+}
+
 static void launch_tpair(const float2* in, float2* out, const float2* b, const float2* gauge, const TMArgs& ta,
-                         double* partial, bool dagger, int mode, dim3 grid, dim3 blk, hipStream_t st) {
+                         double* partial, bool dagger, int mode, dim3 grid, dim3 blk, int which, hipStream_t st) {
+  const FTile& f = kFTiles[which];
+  if (f.eight_loads) {
 #define MG_TP(DAG, MODE) \
   hipLaunchKernelGGL((k_dslash_tp<DAG, MODE>), grid, blk, 0, st, in, out, b, gauge, ta, partial)
-  if (!dagger && mode == 0) MG_TP(false, 0);
-  else if (!dagger && mode == 1) MG_TP(false, 1);
-  else if (dagger && mode == 0) MG_TP(true, 0);
-  else MG_TP(true, 1);
+    if (!dagger && mode == 0) MG_TP(false, 0);
+    else if (!dagger && mode == 1) MG_TP(false, 1);
+    else if (dagger && mode == 0) MG_TP(true, 0);
+    else MG_TP(true, 1);
 #undef MG_TP
+    return;
+  }
+  constexpr int P1 = 96 * 1024;
+#define MG_TQL(X, Y, Z)                                                                        \
+  if (f.tx == X && f.ty == Y && f.tz == Z) {                                                   \
+    if (f.one_per_cu) launch_tq<X, Y, Z, P1>(in, out, b, gauge, ta, partial, dagger, mode, grid, blk, st); \
+    else launch_tq<X, Y, Z, 0>(in, out, b, gauge, ta, partial, dagger, mode, grid, blk, st);   \
+    return;                                                                                    \
+  }
+  MG_TQL(4, 4, 2)
+  MG_TQL(8, 4, 2)
+  MG_TQL(4, 4, 4)
+  MG_TQL(8, 2, 2)
+  MG_TQL(4, 8, 2)
+#undef MG_TQL
+  fail(MGDWF_ERR_INVALID_ARG, "no kernel for this Dslash tiling");
 }
 static void launch_tpair(const double2*, double2*, const double2*, const double2*, const TMArgs&, double*, bool, int,
-                         dim3, dim3, hipStream_t) {
+                         dim3, dim3, int, hipStream_t) {
   fail(MGDWF_ERR_INVALID_ARG, "the s-pair kernel is FP32 only");
 }
 
@@ -720,7 +977,7 @@ enum DslashKind { DS_PLAIN, DS_TMARCH, DS_TPAIR };
 template <class C2>
 static DslashKind dslash_kind(const Geometry& g) {
   if (sizeof(typename real_of<C2>::type) == 8) return DS_PLAIN;
-  if (use_tpair(g)) return DS_TPAIR;
+  if (ftile_of(g) >= 0) return DS_TPAIR;
   if (use_tmarch(g)) return DS_TMARCH;
   return DS_PLAIN;
 }
@@ -728,8 +985,10 @@ static DslashKind dslash_kind(const Geometry& g) {
 template <class C2>
 int dslash_nblocks(const Geometry& g) {
   switch (dslash_kind<C2>(g)) {
-    case DS_TPAIR:
-      return (g.L[0] / TPX) * (g.L[1] / TPY) * (g.L[2] / TPZ) * ceil_div(g.L[3], tpair_chunk(g));
+    case DS_TPAIR: {
+      const int i = ftile_of(g);
+      return ftile_ntiles(g, i) * ceil_div(g.L[3], ftile_chunk(g, i));
+    }
     case DS_TMARCH:
       return (g.L[0] / TMX) * (g.L[1] / TMY) * (g.L[2] / TMZ) * ceil_div(g.L[3], tmarch_chunk(g));
     default:
@@ -747,12 +1006,16 @@ void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geomet
   a.Ls = g.Ls; a.V4 = g.V4; a.V5 = g.V5; a.diag = 5.0 - M5; a.mf = mf;
   const DslashKind kind = dslash_kind<C2>(g);
   if (kind == DS_TPAIR) {
+    const int i = ftile_of(g);
+    const FTile& f = kFTiles[i];
     TMArgs ta;
     ta.d = a;
-    ta.ntx = g.L[0] / TPX; ta.nty = g.L[1] / TPY; ta.ntz = g.L[2] / TPZ;
-    ta.tc = tpair_chunk(g);
-    launch_tpair(in, out, b, gauge, ta, partial, dagger, mode, dim3(dslash_nblocks<C2>(g), nrhs),
-                 dim3(TPS * g.Ls / 2), st);
+    ta.ntx = g.L[0] / f.tx; ta.nty = g.L[1] / f.ty; ta.ntz = g.L[2] / f.tz;
+    ta.tc = ftile_chunk(g, i);
+    ta.fold = f.fold;
+    ta.nrhs = nrhs;
+    const dim3 grid = f.fold ? dim3(dslash_nblocks<C2>(g) * nrhs, 1) : dim3(dslash_nblocks<C2>(g), nrhs);
+    launch_tpair(in, out, b, gauge, ta, partial, dagger, mode, grid, dim3(f.tx * f.ty * f.tz * g.Ls / 2), i, st);
     MG_LAUNCH_CHECK();
     return;
   }

@@ -35,6 +35,7 @@ struct Geometry {
   int V4;        // 4D volume
   int V5;        // V4 * Ls
   int bc[4];     // +1 periodic, -1 antiperiodic in direction mu
+  int ftile = -1;  // FP32 Dslash tiling (index into its table; -1: the default)
 };
 
 struct CoarseGeometry {

@@ -95,3 +95,32 @@ def test_dslash_deterministic(cuda):
     torch.cuda.synchronize()
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
+
+
+def test_dslash_f32_every_tiling(cuda):
+    """Each FP32 t-march tiling the autotuner may pick gives the operator; with
+    t extent 7 the tilings that split t into chunks of 2 leave a short last one."""
+    import paper_1205_2933_amd as mg
+    L, Ls, mf, bc = (16, 16, 8, 7), 4, 0.02, (1, 1, -1, -1)
+    U = prepare_gauge(L, 0.4, 31)
+    psi = gaussian_fermion(L, Ls, 32, n=2)
+    h = mg.Handle(L, Ls, 1.8, mf, bc)
+    mg.mgdwf_set_gauge(h, dev(U))
+    rep = mg.mgdwf_tune(h, nrhs=2, iters=1)
+    assert len(rep["id"]) >= 8 and 0 <= rep["chosen"] < len(rep["id"])
+    assert any(t[3] == 2 for t in rep["tile"])
+    assert {f & 7 for f in rep["flags"]} >= {0, 1, 2, 4}
+    refs = {dg: [dwf.apply_dwf(psi[r], U, 1.8, mf, bc, dagger=dg) for r in range(2)] for dg in (False, True)}
+    for tid, tile in zip(rep["id"], rep["tile"]):
+        print(f"tiling {tid} {tile}", flush=True)
+        mg.mgdwf_set_tiling(h, tid)
+        for dg in (False, True):
+            out = torch.empty_like(dev(psi))
+            mg.mgdwf_apply_dwf(h, dev(psi), out, dagger=dg, prec="f32", nrhs=2)
+            torch.cuda.synchronize()
+            o = out.cpu().numpy()
+            for r in range(2):
+                assert rel(o[r], refs[dg][r]) < 2e-6, (tid, tile, dg, r)
+    with pytest.raises(mg.MgdwfError):
+        mg.mgdwf_set_tiling(h, 10 ** 6)
+    mg.mgdwf_set_tiling(h, -1)
