@@ -186,6 +186,16 @@ mgdwf_status mgdwf_set_mg_params(mgdwf_handle h, const mgdwf_mg_params* p);
 mgdwf_status mgdwf_solve(mgdwf_handle h, const double* b, double* x, int32_t nrhs,
                          const mgdwf_solve_params* p, mgdwf_solve_report* reports);
 
+/* Ragged batch: handle hs[i] solves nrhs[i] right-hand sides b[i] -> x[i]
+ * (device pointers, as mgdwf_solve), every handle on its own stream and host
+ * thread, so solves on lattices of different sizes overlap on the device.
+ * Handles must be distinct and each must have its own stream for the overlap.
+ * reports: sum(nrhs) entries, handle after handle.  Returns MGDWF_OK, or
+ * MGDWF_ERR_NOT_CONVERGED if some solve missed the tolerance (its x holds the
+ * best iterate), or the first other error (message on that handle). */
+mgdwf_status mgdwf_solve_batch(const mgdwf_handle* hs, int32_t n, const double* const* b, double* const* x,
+                               const int32_t* nrhs, const mgdwf_solve_params* p, mgdwf_solve_report* reports);
+
 /* Control solver of Sec. 3: CG on the normal equations (CGNE), FP64. */
 mgdwf_status mgdwf_cgne(mgdwf_handle h, const double* b, double* x, const mgdwf_solve_params* p,
                         mgdwf_solve_report* report);
@@ -205,6 +215,7 @@ typedef struct mgdwf_net_s* mgdwf_net;
 typedef struct {
   int32_t channels[5]; /* input, three hidden, output (output = 4 x proposals) */
   double lam;          /* weight of the Gram term of the training loss         */
+  uint64_t seed;       /* initial weights of layer l ~ N(0, 1/(9 channels[l])) */
 } mgdwf_net_config;
 
 mgdwf_status mgdwf_net_create(const mgdwf_net_config* cfg, mgdwf_net* out);

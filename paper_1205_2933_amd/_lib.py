@@ -85,7 +85,7 @@ class mgdwf_tune_report(ctypes.Structure):
 
 
 class mgdwf_net_config(ctypes.Structure):
-    _fields_ = [("channels", ctypes.c_int32 * 5), ("lam", ctypes.c_double)]
+    _fields_ = [("channels", ctypes.c_int32 * 5), ("lam", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 class MgdwfError(RuntimeError):
@@ -118,6 +118,8 @@ def _load() -> ctypes.CDLL:
         "mgdwf_set_mg_params": ([H, ctypes.POINTER(mgdwf_mg_params)], ctypes.c_int),
         "mgdwf_solve": ([H, P, P, i32, ctypes.POINTER(mgdwf_solve_params), ctypes.POINTER(mgdwf_solve_report)],
                         ctypes.c_int),
+        "mgdwf_solve_batch": ([ctypes.POINTER(H), i32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i32),
+                               ctypes.POINTER(mgdwf_solve_params), ctypes.POINTER(mgdwf_solve_report)], ctypes.c_int),
         "mgdwf_cgne": ([H, P, P, ctypes.POINTER(mgdwf_solve_params), ctypes.POINTER(mgdwf_solve_report)],
                        ctypes.c_int),
         "mgdwf_time_kernel": ([H, ctypes.c_int, ctypes.c_int, i32, i32, ctypes.POINTER(ctypes.c_double)],
@@ -298,6 +300,28 @@ def mgdwf_solve(h: Handle, b: torch.Tensor, x: torch.Tensor, nrhs=1, tol=1e-10, 
     return [r.as_dict() for r in reps]
 
 
+def mgdwf_solve_batch(hs, bs, xs, nrhs, tol=1e-10, max_outer=500, restart=8, allow_not_converged=False):
+    """Ragged batch: handle hs[i] solves nrhs[i] right-hand sides bs[i] -> xs[i]."""
+    n = len(hs)
+    if not (len(bs) == len(xs) == len(nrhs) == n):
+        raise ValueError("hs, bs, xs and nrhs must have the same length")
+    H = (ctypes.c_void_p * n)(*[h.h for h in hs])
+    B = (ctypes.c_void_p * n)(*[_dev(b, h.nfine * k, "b") for h, b, k in zip(hs, bs, nrhs)])
+    X = (ctypes.c_void_p * n)(*[_dev(x, h.nfine * k, "x") for h, x, k in zip(hs, xs, nrhs)])
+    R = (ctypes.c_int32 * n)(*nrhs)
+    sp = mgdwf_solve_params(tol, max_outer, restart)
+    reps = (mgdwf_solve_report * sum(nrhs))()
+    st = _lib.mgdwf_solve_batch(H, n, B, X, R, ctypes.byref(sp), reps)
+    if st != MGDWF_OK and not (allow_not_converged and st == MGDWF_ERR_NOT_CONVERGED):
+        msgs = [mgdwf_last_error(h) for h in hs]
+        raise MgdwfError(st, "; ".join(m for m in msgs if m))
+    out, k = [], 0
+    for m in nrhs:
+        out.append([reps[k + j].as_dict() for j in range(m)])
+        k += m
+    return out
+
+
 def mgdwf_cgne(h: Handle, b: torch.Tensor, x: torch.Tensor, tol=1e-10, max_iter=100000):
     sp = mgdwf_solve_params(tol, max_iter, 1)
     rep = mgdwf_solve_report()
@@ -327,10 +351,11 @@ def mgdwf_set_tiling(h: Handle, tiling_id: int):
 class Net:
     """Owner of one mgdwf_net."""
 
-    def __init__(self, channels, lam=1.0):
+    def __init__(self, channels, lam=1.0, seed=0):
         cfg = mgdwf_net_config()
         cfg.channels[:] = list(channels)
         cfg.lam = lam
+        cfg.seed = seed
         n = ctypes.c_void_p()
         st = _lib.mgdwf_net_create(ctypes.byref(cfg), ctypes.byref(n))
         if st != MGDWF_OK:
@@ -367,8 +392,8 @@ def _host_f32(t: torch.Tensor, numel: int, name: str):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def mgdwf_net_create(channels, lam=1.0) -> Net:
-    return Net(channels, lam)
+def mgdwf_net_create(channels, lam=1.0, seed=0) -> Net:
+    return Net(channels, lam, seed)
 
 
 def mgdwf_net_destroy(net: Net):

@@ -3,6 +3,8 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "ctx.h"
 #include "solver.h"
@@ -340,6 +342,35 @@ mgdwf_status mgdwf_solve(mgdwf_handle h, const double* b, double* x, int32_t nrh
   return st;
 }
 
+mgdwf_status mgdwf_solve_batch(const mgdwf_handle* hs, int32_t n, const double* const* b, double* const* x,
+                               const int32_t* nrhs, const mgdwf_solve_params* p, mgdwf_solve_report* reports) {
+  if (!hs || !b || !x || !nrhs || !p || !reports || n < 1) return MGDWF_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i] || nrhs[i] < 1) return MGDWF_ERR_INVALID_ARG;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return MGDWF_ERR_INVALID_ARG;  // a handle is not thread-safe
+  }
+  std::vector<mgdwf_status> st((size_t)n, MGDWF_OK);
+  std::vector<long long> off((size_t)n, 0);
+  for (int i = 1; i < n; ++i) off[i] = off[i - 1] + nrhs[i - 1];
+  std::vector<std::thread> th;
+  th.reserve((size_t)n);
+  for (int i = 0; i < n; ++i)
+    th.emplace_back([&, i] {
+      if (hipSetDevice(hs[i]->device) != hipSuccess) {
+        st[i] = MGDWF_ERR_HIP;
+        hs[i]->err = "hipSetDevice failed";
+        return;
+      }
+      st[i] = mgdwf_solve(hs[i], b[i], x[i], nrhs[i], p, reports + off[i]);
+    });
+  for (auto& t : th) t.join();
+  mgdwf_status worst = MGDWF_OK;
+  for (int i = 0; i < n; ++i)
+    if (st[i] != MGDWF_OK && (worst == MGDWF_OK || worst == MGDWF_ERR_NOT_CONVERGED)) worst = st[i];
+  return worst;
+}
+
 mgdwf_status mgdwf_cgne(mgdwf_handle h, const double* b, double* x, const mgdwf_solve_params* p,
                         mgdwf_solve_report* report) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
@@ -548,7 +579,7 @@ mgdwf_status mgdwf_net_create(const mgdwf_net_config* cfg, mgdwf_net* out) {
     for (int l = 0; l < 5; ++l) n->net.ch[l] = cfg->channels[l];
     n->net.lam = cfg->lam;
     try {
-      n->net.init();
+      n->net.init(cfg->seed);
     } catch (...) {
       delete n;
       throw;

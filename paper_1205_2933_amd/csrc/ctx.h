@@ -3,6 +3,7 @@
 
 #include <map>
 #include <string>
+#include <vector>
 
 #include "mg_internal.h"
 #include "vecops.h"
@@ -25,6 +26,7 @@ struct mgdwf_ctx {
   bool have_params = false;
 
   std::map<std::string, mgdwf::DevBuf> ws;  // named workspaces, grown on demand
+  std::map<std::string, std::vector<void*>> ptr_cache;  // device pointer tables as last uploaded
   std::string err;
 
   long long fine_applies = 0;    // per right-hand side, since the last reset

@@ -14,7 +14,7 @@ struct NullNet {
   long long step = 0;
   long long nweights() const;
   long long woff(int layer) const;
-  void init();
+  void init(unsigned long long seed);
   void set_weights(const float* host, hipStream_t st);
 };
 

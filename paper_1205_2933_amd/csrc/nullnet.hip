@@ -17,6 +17,7 @@
 // 4D channel fields are stored [channel][colour][x4] (float2), so a
 // wavefront's lanes read consecutive sites.
 #include <cmath>
+#include <random>
 #include <vector>
 
 #include "blas.h"
@@ -328,18 +329,24 @@ long long NullNet::woff(int l) const {
   return n;
 }
 
-void NullNet::init() {
+// Weights of layer l drawn from N(0, 1 / (9 C_in)) (seeded), so that a layer
+// keeps the colour norm of unit-variance inputs and the gate starts near its
+// linear regime.
+void NullNet::init(unsigned long long seed) {
   const long long n = nweights();
   w.alloc(n * sizeof(float));
   wb.alloc(n * sizeof(uint16_t));
   m.alloc(n * sizeof(float));
   v.alloc(n * sizeof(float));
   g.alloc(n * sizeof(float));
-  MG_HIP(hipMemset(w.p, 0, n * sizeof(float)));
-  MG_HIP(hipMemset(wb.p, 0, n * sizeof(uint16_t)));
-  MG_HIP(hipMemset(m.p, 0, n * sizeof(float)));
-  MG_HIP(hipMemset(v.p, 0, n * sizeof(float)));
-  step = 0;
+  std::vector<float> host((size_t)n);
+  std::mt19937_64 rng(seed);
+  std::normal_distribution<float> nd(0.f, 1.f);
+  for (int l = 0; l < 4; ++l) {
+    const float sd = 1.f / std::sqrt(9.f * ch[l]);
+    for (long long i = woff(l); i < woff(l) + 9LL * ch[l] * ch[l + 1]; ++i) host[(size_t)i] = sd * nd(rng);
+  }
+  set_weights(host.data(), nullptr);
 }
 
 void NullNet::set_weights(const float* host, hipStream_t st) {

@@ -44,9 +44,18 @@ std::vector<double> read_slots(mgdwf_ctx* c, int nrhs) {
 // Upload a table of device pointers (kept in a named workspace).
 template <class C2>
 const C2* const* ptr_table(mgdwf_ctx* c, const std::string& name, const std::vector<C2*>& ptrs) {
+  const size_t before = c->ws.count(name) ? c->ws[name].bytes : 0;
   C2** d = c->buf<C2*>(name, std::max<size_t>(ptrs.size(), 1));
+  // upload only when the table changed (or its buffer moved): the workspaces
+  // behind the pointers are stable, so repeated V-cycles skip the copy and
+  // the stream synchronisation it needs
+  std::vector<void*> key(ptrs.begin(), ptrs.end());
+  key.push_back(d);
+  auto it = c->ptr_cache.find(name);
+  if (it != c->ptr_cache.end() && it->second == key && before >= ptrs.size() * sizeof(C2*)) return d;
   MG_HIP(hipMemcpyAsync(d, ptrs.data(), ptrs.size() * sizeof(C2*), hipMemcpyHostToDevice, c->st));
   MG_HIP(hipStreamSynchronize(c->st));
+  c->ptr_cache[name] = std::move(key);
   return d;
 }
 
