@@ -25,6 +25,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 L = (16, 16, 16, 32)
+L_MAIN = L
 LS = 16
 M5 = 1.8
 MF = 0.001
@@ -55,6 +56,14 @@ def counted_traffic():
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def mem(tag):
+    """Device memory in use (driver view) and held by torch's allocator."""
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    log(f"[mem {tag}] used {(total - free) / 2**30:.1f} GiB of {total / 2**30:.1f}, "
+        f"torch reserved {torch.cuda.memory_reserved() / 2**30:.1f} GiB")
 
 
 def mg_params(mg, fine, coarse):
@@ -108,6 +117,152 @@ def cpu_baseline(counts):
     }
 
 
+def ragged_leg(mg, h_main, B_main, log):
+    """44 solves over three lattices of uneven size in one mgdwf_solve_batch
+    call: 8^4 x 8 and 8^3 x 16 x 16 with 16 RHS each (12 point sources + 4
+    Gaussian), and the main 16^3 x 32 x 16 lattice with its 12 point sources;
+    mixed precision, tol 1e-10."""
+    import numpy as np
+    import torch
+
+    from inputs import gaussian_fermion, point_sources, prepare_gauge, random_starts
+
+    hs, bs = [], []
+    for L, Ls, seed in [((8, 8, 8, 8), 8, 14), ((8, 8, 8, 16), 16, 15)]:
+        U = prepare_gauge(L, 0.3, seed, ape_steps=2)
+        h = mg.Handle(L, Ls, M5, MF, stream=torch.cuda.Stream())
+        mg.mgdwf_set_gauge(h, torch.from_numpy(U).cuda())
+        mg.mgdwf_setup(h, mg_params(mg, "f64", "f64"), torch.from_numpy(random_starts(L, Ls, NVEC // 2, 21)).cuda())
+        mg.mgdwf_tune(h, nrhs=16, iters=5)
+        mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f16"))
+        b = np.concatenate([point_sources(L, Ls), gaussian_fermion(L, Ls, 33, n=4)])
+        hs.append(h)
+        bs.append(torch.from_numpy(b).cuda())
+        mem(f"ragged, lattice {L} ready")
+    # the main lattice takes its 12 point sources: its 12-RHS workspaces are
+    # already allocated (16 RHS on it next to the others would need ~220 GiB)
+    mg.mgdwf_set_mg_params(h_main, mg_params(mg, "f32", "f16"))  # the FP64 comparison left FP64 in place
+    hs.append(h_main)
+    bs.append(B_main)
+    xs = [torch.zeros_like(b) for b in bs]
+    nrhs = [16, 16, 12]
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    mem("ragged, before the batch")
+    log("handle bytes " + ", ".join(f"{mg.mgdwf_memory_bytes(h) / 2**30:.1f} GiB" for h in hs))
+    t = time.perf_counter()
+    reps = mg.mgdwf_solve_batch(hs, bs, xs, nrhs, tol=1e-10, max_outer=400, restart=8, allow_not_converged=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    lat = np.array([r["seconds"] for rs in reps for r in rs])
+    res = [max(r["true_relres"] for r in rs) for rs in reps]
+    mem("ragged, after the batch")
+    log("handle bytes " + ", ".join(f"{mg.mgdwf_memory_bytes(h) / 2**30:.1f} GiB" for h in hs))
+    for h in hs[:2]:
+        h.close()
+    del xs, bs
+    mg.mgdwf_trim(h_main)
+    torch.cuda.empty_cache()
+    out = {"solves": int(sum(nrhs)), "wall_s": wall, "solves_per_s": sum(nrhs) / wall,
+           "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+           "outer_iters": [max(r["outer_iters"] for r in rs) for rs in reps], "max_true_relres": res,
+           "lattices": ["8^4x8 (16 RHS)", "8^3x16x16 (16 RHS)", "16^3x32x16 (12 RHS)"]}
+    log(f"ragged batch {out}")
+    assert max(res) < 1e-10, res
+    return out
+
+
+def learned_leg(mg, h_main, B_main, full_setup_s, full_null, log):
+    """Learned near-null proposals: train the gauge-covariant network on the
+    adaptive-setup bases of 24 seeded 8^4 x 8 lattices (eps 0.2..0.6, 2 APE),
+    then on the main lattice compare (a) its full setup (400 CG iterations
+    from random starts), (b) the network's proposals + a 100-iteration
+    refinement, (c) random starts + the same 100 iterations; the full setup
+    is the fallback when (b)'s null residual exceeds twice (c)'s or its solve
+    needs 25 % more outer iterations than (a)'s.  Also times the network's
+    inference on 24^3 x 48 x 16."""
+    import torch
+
+    from inputs import prepare_gauge, random_su3_field
+    from paper_1205_2933_amd import learned as ln
+
+    t0 = time.perf_counter()
+    handles = []
+    for i in range(24):
+        eps = 0.2 + 0.4 * i / 23
+        U = prepare_gauge((8, 8, 8, 8), eps, 1000 + i, ape_steps=2)
+        h = mg.Handle((8, 8, 8, 8), 8, M5, MF)
+        mg.mgdwf_set_gauge(h, torch.from_numpy(U).cuda())
+        ln.targets(h, mg_params(mg, "f64", "f64"), 2000 + i)
+        handles.append(h)
+    torch.cuda.synchronize()
+    targets_s = time.perf_counter() - t0
+    net = mg.Net((8, 32, 32, 32, 2 * NVEC), lam=1.0, seed=3)
+    loss0 = ln.evaluate(net, handles)
+    t = time.perf_counter()
+    ln.train(net, handles, 4000, 5e-3, 2e-4, seed=5)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+    loss1 = ln.evaluate(net, handles)
+    for h in handles:
+        h.close()
+    log(f"trained: loss {loss0:.4f} -> {loss1:.4f} in {train_s:.1f} s (targets {targets_s:.1f} s)")
+
+    def solve_iters():
+        mg.mgdwf_set_mg_params(h_main, mg_params(mg, "f32", "f16"))
+        x = torch.zeros_like(B_main[0])
+        r = mg.mgdwf_solve(h_main, B_main[0].contiguous(), x, nrhs=1, tol=1e-10, max_outer=400, restart=8,
+                           allow_not_converged=True)[0]
+        return r["outer_iters"], r["true_relres"] < 1e-10
+
+    short = mg.make_mg_params(BLOCK, NVEC, sweeps=1, sweep0_iters=100, sweep_iters=4, nu_pre=12, nu_post=12,
+                              coarse_tol=0.1, coarse_maxiter=400, fine_prec="f64", coarse_prec="f64")
+    out = {"train_lattices": "24 x 8^4x8, eps 0.2..0.6", "train_steps": 4000, "train_s": train_s,
+           "targets_s": targets_s, "loss_before": loss0, "loss_after": loss1}
+    it_full, _ = solve_iters()
+    out["full_setup"] = {"sweep0_iters": 400, "setup_s": full_setup_s, "null_residual": full_null,
+                         "mg_iters": it_full}
+    # the same short sweep from random starts: the reference of the fallback check
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rep = mg.mgdwf_setup(h_main, short, ln.random_starts(h_main, NVEC // 2, 21))
+    torch.cuda.synchronize()
+    st = time.perf_counter() - t
+    it, conv = solve_iters()
+    ref_null = rep["null_residual"][-1]
+    out["random_short_setup"] = {"sweep0_iters": 100, "setup_s": st, "null_residual": ref_null,
+                                 "mg_iters": it, "converged": conv}
+    r = ln.learned_setup(net, h_main, short, mg_params(mg, "f64", "f64"), seed=11, reference_null=ref_null)
+    it, conv = solve_iters()
+    fb = r["fallback"]
+    if not fb and ln.needs_fallback(it, it_full):
+        t = time.perf_counter()
+        ln.targets(h_main, mg_params(mg, "f64", "f64"), 12)
+        torch.cuda.synchronize()
+        r["setup_s"] += time.perf_counter() - t
+        fb = True
+        it, conv = solve_iters()
+    out["learned_setup"] = {"sweep0_iters": 100, "setup_s": r["setup_s"], "null_residual": r["null_residual"],
+                            "fallback": fb, "mg_iters": it, "converged": conv,
+                            "setup_speedup_vs_full": full_setup_s / r["setup_s"]}
+    # inference throughput at 24^3 x 48 x 16
+    L = (24, 24, 24, 48)
+    U = random_su3_field(L, 0.3, 77)
+    h = mg.Handle(L, 16, M5, MF)
+    mg.mgdwf_set_gauge(h, torch.from_numpy(U).cuda())
+    del U
+    ln.propose(net, h, 1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    V = ln.propose(net, h, 2)
+    torch.cuda.synchronize()
+    out["inference_24c48_s"] = time.perf_counter() - t
+    del V
+    h.close()
+    log(f"learned {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +270,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-solves", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the 48-solve ragged batch")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -140,6 +297,7 @@ def main():
     setup_s = time.perf_counter() - t
     del V0
     log(f"setup {setup_s:.2f} s, null residual {srep['null_residual']}")
+    mem("after setup")
 
     nrhs = 12
     B = torch.from_numpy(point_sources(L, LS)).to(dev)
@@ -168,6 +326,7 @@ def main():
         log(f"timed step {i} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
+    mem("after the timed steps")
     ms_per_step = 1e3 * elapsed / args.steps
     worst = max(r["true_relres"] for r in reps)
     assert worst < 1e-10, worst
@@ -240,6 +399,15 @@ def main():
                      "achieved": gbs32_12, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs32_12 / HBM_PEAK_GBS,
                      "algorithmic_bytes": bytes32_12, "launch_us": ms32_12 * 1e3, "traffic": counted_traffic()},
     }
+    # the legs below change the main handle's setup, so they come last
+    if not args.no_ragged:
+        try:
+            out["ragged_batch"] = ragged_leg(mg, h, B, log)
+        except (mg.MgdwfError, AssertionError) as e:
+            mem("ragged leg failed")
+            out["ragged_batch"] = {"error": str(e)}
+    if not args.no_learned:
+        out["learned_setup"] = learned_leg(mg, h, B, setup_s, srep["null_residual"][-1], log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(counts)

@@ -186,6 +186,14 @@ mgdwf_status mgdwf_set_mg_params(mgdwf_handle h, const mgdwf_mg_params* p);
 mgdwf_status mgdwf_solve(mgdwf_handle h, const double* b, double* x, int32_t nrhs,
                          const mgdwf_solve_params* p, mgdwf_solve_report* reports);
 
+/* Release every workspace the handle has grown (solver, setup and timing
+ * buffers); later calls allocate what they need again.  The gauge field, the
+ * basis and D_c are kept. */
+mgdwf_status mgdwf_trim(mgdwf_handle h);
+
+/* Device bytes the handle holds (fields, basis, D_c, workspaces); -1 if h is NULL. */
+int64_t mgdwf_memory_bytes(mgdwf_handle h);
+
 /* Ragged batch: handle hs[i] solves nrhs[i] right-hand sides b[i] -> x[i]
  * (device pointers, as mgdwf_solve), every handle on its own stream and host
  * thread, so solves on lattices of different sizes overlap on the device.

@@ -118,6 +118,8 @@ def _load() -> ctypes.CDLL:
         "mgdwf_set_mg_params": ([H, ctypes.POINTER(mgdwf_mg_params)], ctypes.c_int),
         "mgdwf_solve": ([H, P, P, i32, ctypes.POINTER(mgdwf_solve_params), ctypes.POINTER(mgdwf_solve_report)],
                         ctypes.c_int),
+        "mgdwf_trim": ([H], ctypes.c_int),
+        "mgdwf_memory_bytes": ([H], ctypes.c_int64),
         "mgdwf_solve_batch": ([ctypes.POINTER(H), i32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i32),
                                ctypes.POINTER(mgdwf_solve_params), ctypes.POINTER(mgdwf_solve_report)], ctypes.c_int),
         "mgdwf_cgne": ([H, P, P, ctypes.POINTER(mgdwf_solve_params), ctypes.POINTER(mgdwf_solve_report)],
@@ -298,6 +300,14 @@ def mgdwf_solve(h: Handle, b: torch.Tensor, x: torch.Tensor, nrhs=1, tol=1e-10, 
                           reps)
     _check(h.h, st, allow=(MGDWF_ERR_NOT_CONVERGED,) if allow_not_converged else ())
     return [r.as_dict() for r in reps]
+
+
+def mgdwf_trim(h: Handle):
+    _check(h.h, _lib.mgdwf_trim(h.h))
+
+
+def mgdwf_memory_bytes(h: Handle) -> int:
+    return int(_lib.mgdwf_memory_bytes(h.h))
 
 
 def mgdwf_solve_batch(hs, bs, xs, nrhs, tol=1e-10, max_outer=500, restart=8, allow_not_converged=False):

@@ -342,6 +342,25 @@ mgdwf_status mgdwf_solve(mgdwf_handle h, const double* b, double* x, int32_t nrh
   return st;
 }
 
+mgdwf_status mgdwf_trim(mgdwf_handle h) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    MG_HIP(hipStreamSynchronize(h->st));
+    h->ws.clear();
+    h->ptr_cache.clear();
+  });
+}
+
+int64_t mgdwf_memory_bytes(mgdwf_handle h) {
+  if (!h) return -1;
+  long long n = (long long)(h->U64.bytes + h->U32.bytes + h->V64.bytes + h->V32.bytes);
+  for (const mgdwf::CoarseStore* cs : {&h->Dc, &h->DcH})
+    n += (long long)(cs->m64.bytes + cs->m32.bytes + cs->re16.bytes + cs->im16.bytes + cs->sc16.bytes +
+                     cs->reb.bytes + cs->imb.bytes + cs->scb.bytes);
+  for (const auto& kv : h->ws) n += (long long)kv.second.bytes;
+  return n;
+}
+
 mgdwf_status mgdwf_solve_batch(const mgdwf_handle* hs, int32_t n, const double* const* b, double* const* x,
                                const int32_t* nrhs, const mgdwf_solve_params* p, mgdwf_solve_report* reports) {
   if (!hs || !b || !x || !nrhs || !p || !reports || n < 1) return MGDWF_ERR_INVALID_ARG;

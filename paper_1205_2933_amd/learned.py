@@ -14,9 +14,11 @@ fallback):
 3. ``learned_setup``: on a new lattice the network proposes the Nv/2 start
    vectors, one short setup sweep refines them (mgdwf_setup with a small
    sweep-0 iteration count) and the coarse operator is built from the result.
-   If the median null residual |D v|/|v| after the refinement is above
-   ``fallback_ratio`` times a reference value, the full adaptive setup from
-   random starts runs instead.
+   Fallback to the full adaptive setup from random starts: if the median null
+   residual |D v|/|v| after the refinement is above twice that of the same
+   short sweep from random starts (``reference_null``), or, once the first
+   solve has run, if it took more than 25 % more outer iterations than the
+   last full adaptive setup gave (``needs_fallback``).
 """
 
 from __future__ import annotations
@@ -82,10 +84,17 @@ def propose(net: mg.Net, h: mg.Handle, seed: int) -> torch.Tensor:
     return V
 
 
+def needs_fallback(outer_iters: int, reference_iters: int, slack: float = 1.25) -> bool:
+    """True if a solve after the learned setup took more than `slack` times the
+    outer iterations of the last full adaptive setup."""
+    return outer_iters > slack * reference_iters
+
+
 def learned_setup(net: mg.Net, h: mg.Handle, params_short: mg.mgdwf_mg_params, params_full: mg.mgdwf_mg_params,
                   seed: int, reference_null: float | None = None, fallback_ratio: float = 2.0) -> dict:
     """Proposals + one short refinement sweep; the full setup if the refined
-    vectors fail the null-residual check against reference_null."""
+    vectors' null residual exceeds fallback_ratio x reference_null (the same
+    short sweep from random starts)."""
     if params_short.nvec != 2 * net.nh:
         raise ValueError("the network proposes nvec/2 start vectors")
     torch.cuda.synchronize()
