@@ -34,7 +34,7 @@ NVEC = 24
 HBM_PEAK_GBS = 8000.0
 
 
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "dslash_tp_f32_nrhs12_counters.md")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "dslash_f32_16c32x16_nrhs12_counters.md")
 DSLASH_SRC = os.path.join(ROOT, "paper_1205_2933_amd", "csrc", "dslash.hip")
 
 

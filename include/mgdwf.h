@@ -266,6 +266,7 @@ typedef enum {
 #define MGDWF_TILE_RELOAD 1      /* kernel that reloads each slice's own spinor          */
 #define MGDWF_TILE_FOLDED 2      /* workgroups ordered t-chunk first across all RHS       */
 #define MGDWF_TILE_ONE_PER_CU 4  /* LDS reserved so one workgroup runs per CU             */
+#define MGDWF_TILE_LDS_LINKS 8   /* each t-slice's links staged in LDS by the workgroup   */
 typedef struct {
   int32_t ntilings;                   /* tilings timed                                  */
   int32_t chosen;                     /* index into the arrays below                     */

@@ -672,6 +672,23 @@ __global__ __launch_bounds__(256) void k_dslash_tp(const float2* __restrict__ in
   }
 }
 
+// hop_pair with the link read from LDS: entry (a, b) at Ul[(a * 3 + b) * stride]
+template <int MU, int EPS, bool DAGU>
+__device__ __forceinline__ void hop_pair_l(Spinor<float2>& a0, Spinor<float2>& a1, const float2* __restrict__ in,
+                                           long long V5, long long j5, const float2* Ul, int stride, float ph) {
+  Spinor<float2> p0, p1;
+  float2 U[3][3], h[2][3], u[2][3];
+  load_pair(p0, p1, in, V5, j5);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) U[q / 3][q % 3] = Ul[q * stride];
+  project<MU, EPS>(p0, h);
+  mul_link<DAGU>(U, h, u, ph);
+  accumulate<MU, EPS>(a0, u);
+  project<MU, EPS>(p1, h);
+  mul_link<DAGU>(U, h, u, ph);
+  accumulate<MU, EPS>(a1, u);
+}
+
 // ---------------------------------------------------------------- t-march, carried own slice (FP32)
 // As k_dslash_tp, with the spinor of slice t+1 loaded once: the forward
 // t-hop of slice t uses it, and in the same registers it gives slice t+1's
@@ -708,8 +725,8 @@ __device__ __forceinline__ void own_pair(Spinor<float2>& a0, Spinor<float2>& a1,
     }
 }
 
-template <bool DAG, int MODE, int TX, int TY, int TZ, int PAD>
-__global__ __launch_bounds__(TX * TY * TZ * 8, 2) void k_dslash_tq(const float2* __restrict__ in,
+template <bool DAG, int MODE, int TX, int TY, int TZ, int PAD, bool LL>
+__global__ __launch_bounds__(TX * TY * TZ * 8, PAD > 0 ? 1 : 2) void k_dslash_tq(const float2* __restrict__ in,
                                                                float2* __restrict__ out,
                                                                const float2* __restrict__ b,
                                                                const float2* __restrict__ gauge, TMArgs ta,
@@ -774,6 +791,27 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, 2) void k_dslash_tq(const float2*
   const float dg = (float)a.diag, mf = (float)a.mf;
   const int t0 = chunk * ta.tc;
   const int t1 = min(t0 + ta.tc, Lt);
+  // LL: the links of the slice are staged in LDS once per step -- U_mu(x) of
+  // the tile's sites for mu = x, y, z, t, and U_mu(x - mu) on the three minus
+  // faces -- instead of every s-pair thread loading its seven links.
+  constexpr int NS = TX * TY * TZ;
+  constexpr int NF0 = TY * TZ, NF1 = TX * TZ, NF2 = TX * TY;
+  constexpr int NL = LL ? 36 * NS + 9 * (NF0 + NF1 + NF2) : 1;
+  __shared__ float2 sU[NL];
+  int lf[3], lb[3], sb[3];  // LDS offsets of the forward / backward links, backward strides
+  {
+    const int lc[3] = {site % TX, (site / TX) % TY, site / (TX * TY)};
+    const int ts[3] = {1, TX, TX * TY};
+    const int fo[3] = {36 * NS, 36 * NS + 9 * NF0, 36 * NS + 9 * (NF0 + NF1)};
+    const int fi[3] = {lc[1] + TY * lc[2], lc[0] + TX * lc[2], lc[0] + TX * lc[1]};
+    const int nfc[3] = {NF0, NF1, NF2};
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      lf[mu] = mu * 9 * NS + site;
+      if (lc[mu] > 0) { lb[mu] = mu * 9 * NS + site - ts[mu]; sb[mu] = NS; }
+      else { lb[mu] = fo[mu] + fi[mu]; sb[mu] = nfc[mu]; }
+    }
+  }
   float2 hp0[2][3], hp1[2][3], U[3][3], h[2][3], u[2][3];
   Spinor<float2> p0, p1, a0, a1;
   {  // slice t0: own terms, and the backward t-hop from slice t0 - 1
@@ -798,17 +836,53 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, 2) void k_dslash_tq(const float2*
   for (int t = t0; t < t1; ++t) {
     const int x4 = t * V3 + x3;
     const int tb = t * V3;
-    hop_pair<0, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[0]) * Ls + s0, x4, phf[0]);
-    hop_pair<0, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[0]) * Ls + s0, tb + nb3[0], phb[0]);
-    hop_pair<1, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[1]) * Ls + s0, x4, phf[1]);
-    hop_pair<1, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[1]) * Ls + s0, tb + nb3[1], phb[1]);
-    hop_pair<2, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[2]) * Ls + s0, x4, phf[2]);
-    hop_pair<2, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[2]) * Ls + s0, tb + nb3[2], phb[2]);
+    if (LL) {
+      __syncthreads();  // every thread is done with the previous slice's links
+      const int bx = tx * TX, by = ty * TY, bz = tz * TZ;
+      for (int i = threadIdx.x; i < 36 * NS; i += blockDim.x) {  // own sites, mu = x, y, z, t
+        const int mab = i / NS, q = i - mab * NS;
+        const int xx = bx + q % TX, yy = by + (q / TX) % TY, zz = bz + q / (TX * TY);
+        sU[i] = gauge[(long long)mab * V4 + tb + (zz * Ly + yy) * Lx + xx];
+      }
+      for (int i = threadIdx.x; i < 9 * (NF0 + NF1 + NF2); i += blockDim.x) {  // minus faces
+        int mu, r;
+        if (i < 9 * NF0) { mu = 0; r = i; }
+        else if (i < 9 * (NF0 + NF1)) { mu = 1; r = i - 9 * NF0; }
+        else { mu = 2; r = i - 9 * (NF0 + NF1); }
+        const int nf = mu == 0 ? NF0 : (mu == 1 ? NF1 : NF2);
+        const int ab = r / nf, f = r - ab * nf;
+        int xx, yy, zz;
+        if (mu == 0) { xx = bx == 0 ? Lx - 1 : bx - 1; yy = by + f % TY; zz = bz + f / TY; }
+        else if (mu == 1) { xx = bx + f % TX; yy = by == 0 ? Ly - 1 : by - 1; zz = bz + f / TX; }
+        else { xx = bx + f % TX; yy = by + f / TX; zz = bz == 0 ? Lz - 1 : bz - 1; }
+        sU[36 * NS + (mu == 0 ? 0 : (mu == 1 ? 9 * NF0 : 9 * (NF0 + NF1))) + r] =
+            gauge[(long long)(mu * 9 + ab) * V4 + tb + (zz * Ly + yy) * Lx + xx];
+      }
+      __syncthreads();
+      hop_pair_l<0, EF, false>(a0, a1, in, V5, (long long)(tb + nf3[0]) * Ls + s0, sU + lf[0], NS, phf[0]);
+      hop_pair_l<0, EB, true>(a0, a1, in, V5, (long long)(tb + nb3[0]) * Ls + s0, sU + lb[0], sb[0], phb[0]);
+      hop_pair_l<1, EF, false>(a0, a1, in, V5, (long long)(tb + nf3[1]) * Ls + s0, sU + lf[1], NS, phf[1]);
+      hop_pair_l<1, EB, true>(a0, a1, in, V5, (long long)(tb + nb3[1]) * Ls + s0, sU + lb[1], sb[1], phb[1]);
+      hop_pair_l<2, EF, false>(a0, a1, in, V5, (long long)(tb + nf3[2]) * Ls + s0, sU + lf[2], NS, phf[2]);
+      hop_pair_l<2, EB, true>(a0, a1, in, V5, (long long)(tb + nb3[2]) * Ls + s0, sU + lb[2], sb[2], phb[2]);
+    } else {
+      hop_pair<0, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[0]) * Ls + s0, x4, phf[0]);
+      hop_pair<0, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[0]) * Ls + s0, tb + nb3[0], phb[0]);
+      hop_pair<1, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[1]) * Ls + s0, x4, phf[1]);
+      hop_pair<1, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[1]) * Ls + s0, tb + nb3[1], phb[1]);
+      hop_pair<2, EF, false>(a0, a1, in, gauge, V5, V4, (long long)(tb + nf3[2]) * Ls + s0, x4, phf[2]);
+      hop_pair<2, EB, true>(a0, a1, in, gauge, V5, V4, (long long)(tb + nb3[2]) * Ls + s0, tb + nb3[2], phb[2]);
+    }
     // forward t-hop with slice t+1
     const bool top = t == Lt - 1;
     const long long basef = (long long)((top ? 0 : t + 1) * V3 + x3) * Ls;
     load_pair(p0, p1, in, V5, basef + s0);
-    load_link(gauge, 3, V4, x4, U);
+    if (LL) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) U[q / 3][q % 3] = sU[(27 + q) * NS + site];
+    } else {
+      load_link(gauge, 3, V4, x4, U);
+    }
     {
       const float ph = top ? a.ph[3] : 1.0f;
       project<3, EF>(p0, h);
@@ -854,21 +928,25 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, 2) void k_dslash_tq(const float2*
 // FP32 t-march tilings: x, y, z tile, workgroups aimed at per right-hand side
 // (sets the t-slices per workgroup), which kernel, workgroup order and
 // occupancy.  Entry 0 is the default; mgdwf_tune times the others on the
-// device.  Measured on 16^3 x 32 x 16 at 12 RHS the spread is within 10 %:
-// the kernel fetches about 3.8x its algorithmic bytes from beyond L2 (tile
-// faces re-read by the neighbouring workgroups), and one workgroup per CU --
-// half the footprint in L2 -- is slightly ahead of two.
+// device.  Measured on 16^3 x 32 x 16 at 12 RHS the shapes and orders are
+// within 10 % of each other.  With two workgroups per CU the kernel fetches
+// 3.8x its algorithmic bytes from beyond L2 (tile faces re-read by the
+// neighbouring workgroups); one workgroup per CU halves the L2 footprint and
+// the fetch (1.9x) but gains only 3 %, and staging the links in LDS (which
+// removes most of the link loads) is 25 % slower -- the kernel is limited by
+// the issue and latency of its 16-byte spinor loads, not by DRAM bytes.
 struct FTile {
   int tx, ty, tz, target;
   bool eight_loads;  // k_dslash_tp (reloads the own slice) instead of k_dslash_tq
   int fold;          // workgroup order (TMArgs::fold)
   bool one_per_cu = false;  // reserve LDS so that one workgroup runs per CU
+  bool lds_links = false;   // stage each slice's links in LDS
 };
 constexpr FTile kFTiles[] = {
     {4, 4, 2, 256, false, 0, true}, {4, 4, 2, 512, false, 0, true}, {4, 4, 2, 256, false, 0},
     {4, 4, 2, 512, false, 0},       {8, 2, 2, 512, false, 0},       {8, 4, 2, 256, false, 0},
     {4, 4, 4, 512, false, 0},       {4, 8, 2, 512, false, 0},       {4, 4, 2, 1024, false, 1},
-    {4, 4, 2, 512, true, 0},
+    {4, 4, 2, 512, true, 0},        {4, 4, 2, 256, false, 0, true, true},
 };
 constexpr int NFTILE = sizeof(kFTiles) / sizeof(kFTiles[0]);
 
@@ -907,7 +985,8 @@ bool dslash_ftile_desc(const Geometry& g, int i, int desc[4], int* flags) {
   desc[1] = kFTiles[i].ty;
   desc[2] = kFTiles[i].tz;
   desc[3] = ftile_chunk(g, i);
-  *flags = (kFTiles[i].eight_loads ? 1 : 0) | (kFTiles[i].fold ? 2 : 0) | (kFTiles[i].one_per_cu ? 4 : 0);
+  *flags = (kFTiles[i].eight_loads ? 1 : 0) | (kFTiles[i].fold ? 2 : 0) | (kFTiles[i].one_per_cu ? 4 : 0) |
+           (kFTiles[i].lds_links ? 8 : 0);
   return true;
 }
 
@@ -924,11 +1003,11 @@ static int tmarch_chunk(const Geometry& g) {
   return ceil_div(g.L[3], want_chunks);
 }
 
-template <int TX, int TY, int TZ, int PAD>
+template <int TX, int TY, int TZ, int PAD, bool LL>
 static void launch_tq(const float2* in, float2* out, const float2* b, const float2* gauge, const TMArgs& ta,
                       double* partial, bool dagger, int mode, dim3 grid, dim3 blk, hipStream_t st) {
 #define MG_TQ(DAG, MODE) \
-  hipLaunchKernelGGL((k_dslash_tq<DAG, MODE, TX, TY, TZ, PAD>), grid, blk, 0, st, in, out, b, gauge, ta, partial)
+  hipLaunchKernelGGL((k_dslash_tq<DAG, MODE, TX, TY, TZ, PAD, LL>), grid, blk, 0, st, in, out, b, gauge, ta, partial)
   if (!dagger && mode == 0) MG_TQ(false, 0);
   else if (!dagger && mode == 1) MG_TQ(false, 1);
   else if (dagger && mode == 0) MG_TQ(true, 0);
@@ -952,9 +1031,15 @@ static void launch_tpair(const float2* in, float2* out, const float2* b, const f
   constexpr int P1 = 96 * 1024;
 #define MG_TQL(X, Y, Z)                                                                        \
   if (f.tx == X && f.ty == Y && f.tz == Z) {                                                   \
-    if (f.one_per_cu) launch_tq<X, Y, Z, P1>(in, out, b, gauge, ta, partial, dagger, mode, grid, blk, st); \
-    else launch_tq<X, Y, Z, 0>(in, out, b, gauge, ta, partial, dagger, mode, grid, blk, st);   \
+    if (f.one_per_cu) launch_tq<X, Y, Z, P1, false>(in, out, b, gauge, ta, partial, dagger, mode, grid, blk, st); \
+    else launch_tq<X, Y, Z, 0, false>(in, out, b, gauge, ta, partial, dagger, mode, grid, blk, st);   \
     return;                                                                                    \
+  }
+  if (f.lds_links) {
+    if (f.tx == 4 && f.ty == 4 && f.tz == 2) {
+      launch_tq<4, 4, 2, P1, true>(in, out, b, gauge, ta, partial, dagger, mode, grid, blk, st);
+      return;
+    }
   }
   MG_TQL(4, 4, 2)
   MG_TQL(8, 4, 2)

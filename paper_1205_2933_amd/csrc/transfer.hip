@@ -119,6 +119,99 @@ __global__ __launch_bounds__(256) void k_restrict(const C2* __restrict__ V, cons
 }
 
 // coarse[(rhs * Vc + B) * n2 + row] = sum over splits, in fixed order.
+// Multi-RHS restriction: as k_restrict, for RG right-hand sides per workgroup
+// (blockIdx.y picks the group).  A thread keeps the rows of its RG right-hand
+// sides in registers while it sweeps KR basis columns, so the basis is read
+// once per group of right-hand sides and x once per KR columns.  FP32 fields
+// are read two s-values per 16-byte load.  Partial sums in the field's
+// precision per thread (a handful of rows), FP64 across threads; same partial
+// layout as k_restrict.
+template <class C2, int RG, int KR>
+__global__ __launch_bounds__(256) void k_restrict_mr(const C2* __restrict__ V, const C2* __restrict__ x,
+                                                     double* __restrict__ partial, BlockArgs a, int nrhs) {
+  using T = typename real_of<C2>::type;
+  constexpr int W = sizeof(T) == 4 ? 2 : 1;  // consecutive s per load
+  const int B = blockIdx.x / NSPLIT, split = blockIdx.x % NSPLIT;
+  const int r0 = blockIdx.y * RG;
+  const int nr = min(RG, nrhs - r0);
+  const long long V5 = a.V5;
+  const long long field = 12 * V5;
+  const int n5 = a.bvol * a.Ls;
+  const int n2 = 2 * a.Nv;
+  __shared__ double red[4][RG * 2 * KR * 2];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  auto load = [&](const C2* f, long long off, C2 out[W]) {
+    if constexpr (W == 2) {
+      const float4 q = *reinterpret_cast<const float4*>(f + off);
+      out[0] = cmk<C2>(q.x, q.y);
+      out[1] = cmk<C2>(q.z, q.w);
+    } else {
+      out[0] = f[off];
+    }
+  };
+  for (int k0 = 0; k0 < a.Nv; k0 += KR) {
+    T acc[RG][2][KR][2];
+#pragma unroll
+    for (int r = 0; r < RG; ++r)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) { acc[r][h][kk][0] = 0; acc[r][h][kk][1] = 0; }
+    for (int j = split * 256 + threadIdx.x; j * W < n5; j += 256 * NSPLIT) {
+      const int jj = j * W;
+      const int jl = jj / a.Ls, s = jj - jl * a.Ls;
+      const long long i5 = (long long)block_site(a, B, jl) * a.Ls + s;
+      C2 xv[RG][12][W];
+#pragma unroll
+      for (int r = 0; r < RG; ++r)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          if (r < nr) load(x + (long long)(r0 + r) * field, c * V5 + i5, xv[r][c]);
+          else for (int q = 0; q < W; ++q) xv[r][c][q] = cmk<C2>(0, 0);
+        }
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const int k = k0 + kk;
+        if (k < a.Nv) {
+#pragma unroll
+          for (int c = 0; c < 12; ++c) {
+            C2 v[W];
+            load(V + (long long)k * field, c * V5 + i5, v);
+            const int h = c / 6;
+#pragma unroll
+            for (int r = 0; r < RG; ++r)
+#pragma unroll
+              for (int q = 0; q < W; ++q) {
+                acc[r][h][kk][0] += v[q].x * xv[r][c][q].x + v[q].y * xv[r][c][q].y;
+                acc[r][h][kk][1] += v[q].x * xv[r][c][q].y - v[q].y * xv[r][c][q].x;
+              }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RG; ++r)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk)
+#pragma unroll
+          for (int ri = 0; ri < 2; ++ri) {
+            const double v = wave_sum((double)acc[r][h][kk][ri]);
+            if (l == 0) red[w][((r * 2 + h) * KR + kk) * 2 + ri] = v;
+          }
+    __syncthreads();
+    for (int q = threadIdx.x; q < RG * 2 * KR * 2; q += 256) {
+      const int r = q / (2 * KR * 2), h = (q / (KR * 2)) % 2, kk = (q / 2) % KR, ri = q & 1;
+      const int k = k0 + kk;
+      const double sum = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+      if (k < a.Nv && r < nr)
+        partial[(((long long)(r0 + r) * a.Vc + B) * NSPLIT + split) * 2 * n2 + (h * a.Nv + k) * 2 + ri] = sum;
+    }
+    __syncthreads();
+  }
+}
+
 template <class C2>
 __global__ void k_restrict_finalize(const double* __restrict__ partial, C2* __restrict__ coarse,
                                     int Vc, int n2, int nrhs) {
@@ -166,6 +259,54 @@ __global__ __launch_bounds__(256) void k_prolong(const C2* __restrict__ V, const
   for (int c = 0; c < 12; ++c) {
     if (ACC) out[c * V5 + i5] = cadd(out[c * V5 + i5], acc[c]);
     else out[c * V5 + i5] = acc[c];
+  }
+}
+
+// Multi-RHS prolongation: each thread reads its site's basis rows once and
+// applies them to RG right-hand sides (blockIdx.y picks the group).
+template <class C2, class CC2, bool ACC, int RG>
+__global__ __launch_bounds__(256) void k_prolong_mr(const C2* __restrict__ V, const CC2* __restrict__ cvec,
+                                                    C2* __restrict__ out, BlockArgs a, int nrhs) {
+  using T = typename real_of<C2>::type;
+  const long long i5 = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int r0 = blockIdx.y * RG;
+  const int nr = min(RG, nrhs - r0);
+  const long long V5 = a.V5;
+  const long long field = 12 * V5;
+  if (i5 >= V5) return;
+  const int n2 = 2 * a.Nv;
+  const int x4 = (int)(i5 / a.Ls);
+  const int cs = coarse_of(a, x4);
+  C2 acc[RG][12];
+#pragma unroll
+  for (int r = 0; r < RG; ++r)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[r][c] = cmk<C2>(0, 0);
+  for (int k = 0; k < a.Nv; ++k) {
+    C2 v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = V[(long long)k * field + c * V5 + i5];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      if (r < nr) {
+        const CC2* cb = cvec + ((long long)(r0 + r) * a.Vc + cs) * n2;
+        const CC2 c0 = cb[k], c1 = cb[a.Nv + k];
+        const C2 w0 = cmk<C2>((T)c0.x, (T)c0.y), w1 = cmk<C2>((T)c1.x, (T)c1.y);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) cfma(acc[r][c], v[c], c < 6 ? w0 : w1);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RG; ++r) {
+    if (r < nr) {
+      C2* o = out + (long long)(r0 + r) * field;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        if (ACC) o[c * V5 + i5] = cadd(o[c * V5 + i5], acc[r][c]);
+        else o[c * V5 + i5] = acc[r][c];
+      }
+    }
   }
 }
 
@@ -315,7 +456,15 @@ template <class C2, class CC2>
 void restrict_op(const C2* V, const C2* x, CC2* coarse, double* partial, const Geometry& g,
                  const CoarseGeometry& cg, int nrhs, hipStream_t st) {
   BlockArgs a = make_args(g, cg);
-  hipLaunchKernelGGL((k_restrict<C2>), dim3(cg.Vc * NSPLIT, nrhs), dim3(256), 0, st, V, x, partial, a);
+  constexpr bool f64 = sizeof(typename real_of<C2>::type) == 8;
+  constexpr int RG = 2, KR = f64 ? 4 : 6;
+  // the FP32 kernel reads s-pairs: Ls even keeps every pair inside one site
+  if (nrhs >= 2 && (f64 || g.Ls % 2 == 0)) {
+    hipLaunchKernelGGL((k_restrict_mr<C2, RG, KR>), dim3(cg.Vc * NSPLIT, ceil_div(nrhs, RG)), dim3(256), 0, st, V,
+                       x, partial, a, nrhs);
+  } else {
+    hipLaunchKernelGGL((k_restrict<C2>), dim3(cg.Vc * NSPLIT, nrhs), dim3(256), 0, st, V, x, partial, a);
+  }
   MG_LAUNCH_CHECK();
   long long tot = (long long)nrhs * cg.Vc * cg.n2;
   hipLaunchKernelGGL((k_restrict_finalize<CC2>), dim3(ceil_div(tot, 256)), dim3(256), 0, st, partial,
@@ -327,11 +476,21 @@ template <class C2, class CC2>
 void prolong_op(const C2* V, const CC2* coarse, C2* fine, bool accumulate, const Geometry& g,
                 const CoarseGeometry& cg, int nrhs, hipStream_t st) {
   BlockArgs a = make_args(g, cg);
-  dim3 grid(ceil_div(g.V5, 256), nrhs);
-  if (accumulate)
-    hipLaunchKernelGGL((k_prolong<C2, CC2, true>), grid, dim3(256), 0, st, V, coarse, fine, a);
-  else
-    hipLaunchKernelGGL((k_prolong<C2, CC2, false>), grid, dim3(256), 0, st, V, coarse, fine, a);
+  constexpr bool f64 = sizeof(typename real_of<C2>::type) == 8;
+  constexpr int RG = f64 ? 2 : 4;
+  if (nrhs >= 2) {
+    dim3 grid(ceil_div(g.V5, 256), ceil_div(nrhs, RG));
+    if (accumulate)
+      hipLaunchKernelGGL((k_prolong_mr<C2, CC2, true, RG>), grid, dim3(256), 0, st, V, coarse, fine, a, nrhs);
+    else
+      hipLaunchKernelGGL((k_prolong_mr<C2, CC2, false, RG>), grid, dim3(256), 0, st, V, coarse, fine, a, nrhs);
+  } else {
+    dim3 grid(ceil_div(g.V5, 256), nrhs);
+    if (accumulate)
+      hipLaunchKernelGGL((k_prolong<C2, CC2, true>), grid, dim3(256), 0, st, V, coarse, fine, a);
+    else
+      hipLaunchKernelGGL((k_prolong<C2, CC2, false>), grid, dim3(256), 0, st, V, coarse, fine, a);
+  }
   MG_LAUNCH_CHECK();
 }
 

@@ -72,20 +72,26 @@ def test_basis_matches_oracle_qr(cuda, case):
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"L{'x'.join(map(str, c[0]))}_b{''.join(map(str, c[2]))}")
 def test_restrict_prolong_match_oracle(cuda, case):
+    """R and P on 5 right-hand sides: the multi-RHS kernels read the basis once
+    per group of right-hand sides, with a ragged last group."""
     import paper_1205_2933_amd as mg
     L, Ls, block, nvec, mf, bc = case
     h, U, V, Vh = make(case, mg)
-    x = gaussian_fermion(L, Ls, 51, n=2)
+    n = 5
+    x = gaussian_fermion(L, Ls, 51, n=n)
     cshape = ot.restrict(x[0], Vh, block).shape
-    cg = torch.empty((2,) + cshape, dtype=torch.complex128, device="cuda")
-    mg.mgdwf_restrict(h, dev(x), cg, nrhs=2)
-    c = np.random.default_rng(1).standard_normal((2,) + cshape) + 1j * np.random.default_rng(2).standard_normal((2,) + cshape)
+    cg = torch.empty((n,) + cshape, dtype=torch.complex128, device="cuda")
+    mg.mgdwf_restrict(h, dev(x), cg, nrhs=n)
+    c = np.random.default_rng(1).standard_normal((n,) + cshape) + 1j * np.random.default_rng(2).standard_normal((n,) + cshape)
     fg = torch.empty_like(dev(x))
-    mg.mgdwf_prolong(h, dev(c), fg, nrhs=2)
+    mg.mgdwf_prolong(h, dev(c), fg, nrhs=n)
+    c1 = torch.empty((1,) + cshape, dtype=torch.complex128, device="cuda")
+    mg.mgdwf_restrict(h, dev(x[3:4]), c1, nrhs=1)
     torch.cuda.synchronize()
-    for r in range(2):
+    for r in range(n):
         assert rel(cg.cpu().numpy()[r], ot.restrict(x[r], Vh, block)) < 1e-13
         assert rel(fg.cpu().numpy()[r], ot.prolong(c[r], Vh, block)) < 1e-13
+    assert rel(c1.cpu().numpy()[0], cg.cpu().numpy()[3]) < 1e-14
 
 
 def test_rank_deficient_basis_is_rejected(cuda):
