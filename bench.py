@@ -81,7 +81,7 @@ def cpu_baseline(counts):
     from oracle import dwf
     from oracle import transfer as ot
 
-    threads = os.environ.get("OMP_NUM_THREADS")
+    cpu0, wall0 = time.process_time(), time.perf_counter()
     U = random_su3_field(L, 0.3, 12)
     psi = gaussian_fermion(L, LS, 1)
     t = time.perf_counter()
@@ -108,8 +108,10 @@ def cpu_baseline(counts):
     oc.apply_coarse(cv, Dc)
     t_c = time.perf_counter() - t
     per_rhs = (counts["fine"] * t_dslash + counts["vcycles"] * (t_r + t_p) + counts["coarse"] * t_c)
+    # threads actually used: process CPU time over wall time of the sample
+    cores = max(1, round((time.process_time() - cpu0) / (time.perf_counter() - wall0)))
     return {
-        "value": per_rhs, "unit": "s per RHS to 1e-10 (extrapolated)", "cores": int(threads) if threads else os.cpu_count(),
+        "value": per_rhs, "unit": "s per RHS to 1e-10 (extrapolated)", "cores": cores,
         "kind": "oracle",
         "sample": (f"oracle Dslash at full size ({t_dslash:.2f} s), R/P on a 16^3x4x16 slab x8 ({t_r:.2f}/{t_p:.2f} s), "
                    f"coarse apply ({t_c:.3f} s), times the GPU per-RHS counts: {counts['fine']} D applications, "
@@ -169,6 +171,50 @@ def ragged_leg(mg, h_main, B_main, log):
            "lattices": ["8^4x8 (16 RHS)", "8^3x16x16 (16 RHS)", "16^3x32x16 (12 RHS)"]}
     log(f"ragged batch {out}")
     assert max(res) < 1e-10, res
+    return out
+
+
+def mass_leg(mg, U_dev, B_main, log):
+    """Iteration count versus quark mass (m_f = 0.01, 0.003, 0.001) on the main
+    gauge field (eps = 0.3) and on a rougher one (eps = 0.6, seed 13), both with
+    two APE steps: a fresh adaptive setup per mass, one point source,
+    mixed-precision MG and, for the paper's comparison, CG on the normal
+    equations (FP64), each to |b - D x| / |b| < 1e-10."""
+    import torch
+
+    from inputs import prepare_gauge, random_starts
+
+    out = []
+    U06 = None
+    for eps in (0.3, 0.6):
+        if eps == 0.6:
+            U06 = torch.from_numpy(prepare_gauge(L_MAIN, 0.6, 13, ape_steps=2)).cuda()
+        for mf in (0.01, 0.003, 0.001):
+            h = mg.Handle(L_MAIN, LS, M5, mf)
+            mg.mgdwf_set_gauge(h, U_dev if eps == 0.3 else U06)
+            srep = mg.mgdwf_setup(h, mg_params(mg, "f64", "f64"),
+                                  torch.from_numpy(random_starts(L_MAIN, LS, NVEC // 2, 21)).cuda())
+            mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f16"))
+            b = B_main[0].contiguous()
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = mg.mgdwf_solve(h, b, x, nrhs=1, tol=1e-10, max_outer=400, restart=8, allow_not_converged=True)[0]
+            torch.cuda.synchronize()
+            mg_s = time.perf_counter() - t
+            x.zero_()
+            t = time.perf_counter()
+            c = mg.mgdwf_cgne(h, b, x, tol=1e-10, max_iter=200000)
+            torch.cuda.synchronize()
+            cg_s = time.perf_counter() - t
+            row = {"eps": eps, "m_f": mf, "null_residual": srep["null_residual"][-1],
+                   "mg_outer_iters": r["outer_iters"], "mg_true_relres": r["true_relres"],
+                   "mg_fine_applies": r["fine_applies"], "mg_s": mg_s, "cgne_iters": c["outer_iters"],
+                   "cgne_fine_applies": c["fine_applies"], "cgne_s": cg_s}
+            log(f"mass scan {row}")
+            out.append(row)
+            h.close()
+            del x
     return out
 
 
@@ -272,6 +318,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ragged", action="store_true", help="skip the 48-solve ragged batch")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup comparison")
+    ap.add_argument("--no-mass-scan", action="store_true", help="skip the iteration count versus m_f")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -288,7 +335,8 @@ def main():
     U = prepare_gauge(L, 0.3, 12, ape_steps=2)
     log(f"inputs ready ({time.perf_counter() - t0:.1f} s)")
     h = mg.Handle(L, LS, M5, MF)
-    mg.mgdwf_set_gauge(h, torch.from_numpy(U).to(dev))
+    U_dev = torch.from_numpy(U).to(dev)
+    mg.mgdwf_set_gauge(h, U_dev)
     V0 = torch.from_numpy(random_starts(L, LS, NVEC // 2, 21)).to(dev)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -400,6 +448,10 @@ def main():
                      "algorithmic_bytes": bytes32_12, "launch_us": ms32_12 * 1e3, "traffic": counted_traffic()},
     }
     # the legs below change the main handle's setup, so they come last
+    if not args.no_mass_scan:
+        mg.mgdwf_trim(h)
+        torch.cuda.empty_cache()
+        out["mass_scan"] = mass_leg(mg, U_dev, B, log)
     if not args.no_ragged:
         try:
             out["ragged_batch"] = ragged_leg(mg, h, B, log)
