@@ -89,6 +89,9 @@ typedef struct {
   int32_t coarse_maxiter; /* iteration cap of the coarse solve                    */
   mgdwf_prec fine_prec;   /* F64 or F32: precision of the V-cycle's fine level    */
   mgdwf_prec coarse_prec; /* F64, F32, F16 or BF16: storage of D_c in the V-cycle */
+  int32_t coarse_graph;   /* 1: after the first 8 coarse iterations, replay each
+                             block of 8 as one captured HIP graph; 0: launch
+                             every kernel.  Results are bitwise the same.        */
 } mgdwf_mg_params;
 
 /* Outer flexible GCR (Sec. 3).  Every restart recomputes the true residual

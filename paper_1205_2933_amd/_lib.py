@@ -42,7 +42,7 @@ class mgdwf_mg_params(ctypes.Structure):
                 ("sweep0_iters", ctypes.c_int32), ("sweep_iters", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("coarse_tol", ctypes.c_double), ("coarse_maxiter", ctypes.c_int32),
-                ("fine_prec", ctypes.c_int), ("coarse_prec", ctypes.c_int)]
+                ("fine_prec", ctypes.c_int), ("coarse_prec", ctypes.c_int), ("coarse_graph", ctypes.c_int32)]
 
 
 class mgdwf_solve_params(ctypes.Structure):
@@ -271,12 +271,14 @@ def mgdwf_apply_coarse(h: Handle, inp: torch.Tensor, out: torch.Tensor, dagger=F
 
 
 def make_mg_params(block, nvec, sweeps=3, sweep0_iters=100, sweep_iters=4, nu_pre=4, nu_post=4,
-                   coarse_tol=0.1, coarse_maxiter=100, fine_prec="f64", coarse_prec="f64") -> mgdwf_mg_params:
+                   coarse_tol=0.1, coarse_maxiter=100, fine_prec="f64", coarse_prec="f64",
+                   coarse_graph=True) -> mgdwf_mg_params:
     p = mgdwf_mg_params()
     p.block[:] = list(block)
     p.nvec, p.sweeps, p.sweep0_iters, p.sweep_iters = nvec, sweeps, sweep0_iters, sweep_iters
     p.nu_pre, p.nu_post, p.coarse_tol, p.coarse_maxiter = nu_pre, nu_post, coarse_tol, coarse_maxiter
     p.fine_prec, p.coarse_prec = PREC[fine_prec], PREC[coarse_prec]
+    p.coarse_graph = 1 if coarse_graph else 0
     return p
 
 

@@ -68,6 +68,7 @@ void check_params(const mgdwf_ctx* c, const mgdwf_mg_params* p) {
        "bad coarse solver settings");
   check_prec_fine(p->fine_prec);
   need(p->coarse_prec >= MGDWF_F64 && p->coarse_prec <= MGDWF_BF16, MGDWF_ERR_INVALID_ARG, "bad coarse precision");
+  need(p->coarse_graph == 0 || p->coarse_graph == 1, MGDWF_ERR_INVALID_ARG, "coarse_graph must be 0 or 1");
   (void)make_coarse(c->g, p->block, p->nvec);
 }
 
@@ -204,6 +205,7 @@ mgdwf_status mgdwf_apply_dwf(mgdwf_handle h, const double* in, double* out, int3
 mgdwf_status mgdwf_set_nullvecs(mgdwf_handle h, const int32_t block[4], const double* V, int32_t nvec) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
+    h->clear_graphs();
     need(block && V, MGDWF_ERR_INVALID_ARG, "null argument");
     need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
     (void)make_coarse(h->g, block, nvec);
@@ -253,7 +255,8 @@ mgdwf_status mgdwf_prolong(mgdwf_handle h, const double* coarse, double* fine, i
 
 mgdwf_status mgdwf_build_coarse(mgdwf_handle h) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
-  return guarded(h, [&] { build_coarse(h); });
+  return guarded(h, [&] {
+    h->clear_graphs(); build_coarse(h); });
 }
 
 mgdwf_status mgdwf_get_coarse_op(mgdwf_handle h, double* Dc) {
@@ -294,6 +297,7 @@ mgdwf_status mgdwf_apply_coarse(mgdwf_handle h, const double* in, double* out, i
 mgdwf_status mgdwf_setup(mgdwf_handle h, const mgdwf_mg_params* p, const double* V0, mgdwf_setup_report* report) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
+    h->clear_graphs();
     check_params(h, p);
     need(V0 != nullptr, MGDWF_ERR_INVALID_ARG, "null starting vectors");
     need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
@@ -308,6 +312,7 @@ mgdwf_status mgdwf_setup(mgdwf_handle h, const mgdwf_mg_params* p, const double*
 mgdwf_status mgdwf_set_mg_params(mgdwf_handle h, const mgdwf_mg_params* p) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
+    h->clear_graphs();
     check_params(h, p);
     need(h->have_coarse, MGDWF_ERR_STATE, "no basis / coarse operator installed");
     need(p->nvec == h->cg.Nv, MGDWF_ERR_INVALID_ARG, "nvec differs from the installed basis");
@@ -346,6 +351,7 @@ mgdwf_status mgdwf_trim(mgdwf_handle h) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     MG_HIP(hipStreamSynchronize(h->st));
+    h->clear_graphs();
     h->ws.clear();
     h->ptr_cache.clear();
   });

@@ -27,6 +27,17 @@ struct mgdwf_ctx {
 
   std::map<std::string, mgdwf::DevBuf> ws;  // named workspaces, grown on demand
   std::map<std::string, std::vector<void*>> ptr_cache;  // device pointer tables as last uploaded
+  std::map<std::string, hipGraphExec_t> graphs;  // captured coarse iteration blocks, keyed by their buffers
+  hipStream_t cap_st = nullptr;                  // private stream the graphs are captured on
+
+  void clear_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
+  ~mgdwf_ctx() {
+    clear_graphs();
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+  }
   std::string err;
 
   long long fine_applies = 0;    // per right-hand side, since the last reset

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <vector>
 
 #include "ctx.h"
@@ -155,8 +156,62 @@ struct TwoLevel {
   }
 
   // CGNE on D_c: x = D_c^+ y with D_c D_c^+ y = b, to |r| < tol |b| or maxiter.
+  // Convergence is tested on the host every `check` iterations.  With
+  // p.coarse_graph, every block of `check` iterations after the first is one
+  // replay of a HIP graph captured from the same launches (their arguments
+  // are the same in every block: the slot pair swaps an even number of times).
+  static constexpr int check = 8;
+
+  void cg_iteration(F2* x, int it, int cur, int nxt) {
+    coarse_op(c, p, cp, cq, false, nrhs);
+    mr_update<F2>(x, cr, cp, cq, nc, nrhs, sl, cur, S_CPP, it == 0, vpart, c->st);
+    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, nxt, nrhs, c->st);
+    coarse_op(c, p, cr, ct, true, nrhs);
+    cg_dir<F2>(cp, ct, nc, nrhs, sl, nxt, cur, vpart, c->st);
+    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, S_CPP, nrhs, c->st);
+  }
+
+  hipGraphExec_t block_graph(F2* x) {
+    const CoarseStore& s1 = c->Dc;
+    const CoarseStore& s2 = c->DcH;
+    char key[512];
+    snprintf(key, sizeof key, "cg%s:%d:%d:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p", Prec<F2>::tag, nrhs,
+             (int)p.coarse_prec, (void*)x, (void*)cr, (void*)cp, (void*)cq, (void*)ct, (void*)sl, (void*)vpart,
+             s1.m64.p, s1.m32.p, s1.re16.p, s1.reb.p, s2.m64.p, s2.m32.p, s2.re16.p, s2.reb.p);
+    auto found = c->graphs.find(key);
+    if (found != c->graphs.end()) return found->second;
+    if (!c->cap_st) MG_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
+    // capture on the private stream: nothing runs now; replays go to c->st
+    hipStream_t saved = c->st;
+    const long long applies = c->coarse_applies;
+    c->st = c->cap_st;
+    hipGraph_t graph = nullptr;
+    MG_HIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+    try {
+      int cur = S_CRR_A, nxt = S_CRR_B;
+      for (int k = 0; k < check; ++k) {
+        cg_iteration(x, 1, cur, nxt);
+        std::swap(cur, nxt);
+      }
+    } catch (...) {
+      (void)hipStreamEndCapture(c->st, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      c->st = saved;
+      c->coarse_applies = applies;
+      throw;
+    }
+    MG_HIP(hipStreamEndCapture(c->st, &graph));
+    c->st = saved;
+    c->coarse_applies = applies;
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    MG_HIP(e);
+    c->graphs[key] = exec;
+    return exec;
+  }
+
   void coarse_solve(const F2* b, F2* x) {
-    const int check = 8;
     copy(c, b, cr, nc * nrhs);
     norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR0);
     norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR_A);
@@ -164,15 +219,18 @@ struct TwoLevel {
     norm_into<F2>(c, cp, nullptr, nc, nrhs, S_CPP);
     int cur = S_CRR_A, nxt = S_CRR_B;
     const double tol2 = p.coarse_tol * p.coarse_tol;
-    for (int it = 0; it < p.coarse_maxiter; ++it) {
-      coarse_op(c, p, cp, cq, false, nrhs);
-      mr_update<F2>(x, cr, cp, cq, nc, nrhs, sl, cur, S_CPP, it == 0, vpart, c->st);
-      finalize_rhs(vpart, VEC_BLOCKS, 1, sl, nxt, nrhs, c->st);
-      coarse_op(c, p, cr, ct, true, nrhs);
-      cg_dir<F2>(cp, ct, nc, nrhs, sl, nxt, cur, vpart, c->st);
-      finalize_rhs(vpart, VEC_BLOCKS, 1, sl, S_CPP, nrhs, c->st);
-      std::swap(cur, nxt);
-      if ((it + 1) % check == 0 && it + 1 < p.coarse_maxiter) {
+    int it = 0;
+    while (it < p.coarse_maxiter) {
+      if (p.coarse_graph && it > 0 && it % check == 0 && it + check <= p.coarse_maxiter) {
+        MG_HIP(hipGraphLaunch(block_graph(x), c->st));
+        c->coarse_applies += 2 * check;
+        it += check;  // cur and nxt are back where they were
+      } else {
+        cg_iteration(x, it, cur, nxt);
+        std::swap(cur, nxt);
+        ++it;
+      }
+      if (it % check == 0 && it < p.coarse_maxiter) {
         std::vector<double> h = read_slots(c, nrhs);
         bool done = true;
         for (int r = 0; r < nrhs; ++r)
