@@ -68,6 +68,28 @@ def train(net: mg.Net, handles, steps: int, lr: float, lr_final: float | None = 
     return losses
 
 
+def train_stream(net: mg.Net, make_handle, n_lattices: int, params: mg.mgdwf_mg_params, steps_per_lattice: int,
+                 lr: float, lr_final: float | None = None, seed: int = 0, log=None) -> list:
+    """Training that streams over lattices: for lattice i, make_handle(i)
+    returns a handle with its gauge field set, a full adaptive setup installs
+    the target basis, steps_per_lattice Adam steps run on it and the handle is
+    released.  The learning rate decays geometrically over all steps."""
+    losses = []
+    total = n_lattices * steps_per_lattice
+    lr_final = lr if lr_final is None else lr_final
+    for i in range(n_lattices):
+        h = make_handle(i)
+        targets(h, params, seed + 7919 * i + 1)
+        for k in range(steps_per_lattice):
+            step = i * steps_per_lattice + k
+            a = lr * (lr_final / lr) ** (step / max(1, total - 1))
+            losses.append(mg.mgdwf_net_train_step(net, h, noise(net.channels[0], h.V4, seed + step), a))
+        h.close()
+        if log and (i % 25 == 0 or i == n_lattices - 1):
+            log(f"lattice {i}: loss {sum(losses[-steps_per_lattice:]) / steps_per_lattice:.4f}")
+    return losses
+
+
 def evaluate(net: mg.Net, handles, seed: int = 10 ** 6) -> float:
     """Mean training loss over the handles on fresh input draws."""
     tot = 0.0
