@@ -153,10 +153,12 @@ mgdwf_status mgdwf_set_nullvecs(mgdwf_handle h, const int32_t block[4], const do
 /* The orthonormal basis, canonical [Nv][fermion] (both chirality columns of
  * vector k in field k). */
 mgdwf_status mgdwf_get_basis(mgdwf_handle h, double* Vhat);
-/* coarse = R fine  (R = P^+), nrhs canonical fine fields -> coarse vectors. */
-mgdwf_status mgdwf_restrict(mgdwf_handle h, const double* fine, double* coarse, int32_t nrhs);
-/* fine = P coarse. */
-mgdwf_status mgdwf_prolong(mgdwf_handle h, const double* coarse, double* fine, int32_t nrhs);
+/* coarse = R fine  (R = P^+), nrhs canonical fine fields -> coarse vectors.
+ * prec F64, or F32: the V-cycle's kernels on FP32 copies of the basis and
+ * the fields (inputs rounded to FP32, results returned as complex128). */
+mgdwf_status mgdwf_restrict(mgdwf_handle h, const double* fine, double* coarse, int32_t nrhs, mgdwf_prec prec);
+/* fine = P coarse, same precisions. */
+mgdwf_status mgdwf_prolong(mgdwf_handle h, const double* coarse, double* fine, int32_t nrhs, mgdwf_prec prec);
 
 /* ---- coarse operator (steps a6, a7): Sec. 2 step 3, Sec. 4 ------------ */
 

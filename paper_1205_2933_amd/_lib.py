@@ -109,8 +109,8 @@ def _load() -> ctypes.CDLL:
         "mgdwf_apply_dwf": ([H, P, P, i32, ctypes.c_int, i32], ctypes.c_int),
         "mgdwf_set_nullvecs": ([H, ctypes.POINTER(i32), P, i32], ctypes.c_int),
         "mgdwf_get_basis": ([H, P], ctypes.c_int),
-        "mgdwf_restrict": ([H, P, P, i32], ctypes.c_int),
-        "mgdwf_prolong": ([H, P, P, i32], ctypes.c_int),
+        "mgdwf_restrict": ([H, P, P, i32, ctypes.c_int], ctypes.c_int),
+        "mgdwf_prolong": ([H, P, P, i32, ctypes.c_int], ctypes.c_int),
         "mgdwf_build_coarse": ([H], ctypes.c_int),
         "mgdwf_get_coarse_op": ([H, P], ctypes.c_int),
         "mgdwf_apply_coarse": ([H, P, P, i32, ctypes.c_int, i32], ctypes.c_int),
@@ -246,14 +246,14 @@ def mgdwf_get_basis(h: Handle, Vhat: torch.Tensor):
     _check(h.h, _lib.mgdwf_get_basis(h.h, _dev(Vhat, h.nfine * h.nvec, "Vhat")))
 
 
-def mgdwf_restrict(h: Handle, fine: torch.Tensor, coarse: torch.Tensor, nrhs=1):
+def mgdwf_restrict(h: Handle, fine: torch.Tensor, coarse: torch.Tensor, nrhs=1, prec="f64"):
     _check(h.h, _lib.mgdwf_restrict(h.h, _dev(fine, h.nfine * nrhs, "fine"), _dev(coarse, h.ncoarse * nrhs, "coarse"),
-                                    nrhs))
+                                    nrhs, PREC[prec]))
 
 
-def mgdwf_prolong(h: Handle, coarse: torch.Tensor, fine: torch.Tensor, nrhs=1):
+def mgdwf_prolong(h: Handle, coarse: torch.Tensor, fine: torch.Tensor, nrhs=1, prec="f64"):
     _check(h.h, _lib.mgdwf_prolong(h.h, _dev(coarse, h.ncoarse * nrhs, "coarse"), _dev(fine, h.nfine * nrhs, "fine"),
-                                   nrhs))
+                                   nrhs, PREC[prec]))
 
 
 def mgdwf_build_coarse(h: Handle):

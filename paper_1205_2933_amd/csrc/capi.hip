@@ -226,33 +226,51 @@ mgdwf_status mgdwf_get_basis(mgdwf_handle h, double* Vhat) {
   });
 }
 
-mgdwf_status mgdwf_restrict(mgdwf_handle h, const double* fine, double* coarse, int32_t nrhs) {
+mgdwf_status mgdwf_restrict(mgdwf_handle h, const double* fine, double* coarse, int32_t nrhs, mgdwf_prec prec) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     need(fine && coarse && nrhs >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
+    check_prec_fine(prec);
     need(h->have_basis, MGDWF_ERR_STATE, "no basis installed");
     const long long n = h->fine_len() * nrhs;
     double2* a = h->buf<double2>("io_a", n);
+    double* part = h->buf<double>("rpart", restrict_partial_doubles(h->cg, nrhs));
     pack_fermion_f64(reinterpret_cast<const double2*>(fine), a, h->g, nrhs, h->st);
-    restrict_op<double2, double2>(h->V64.as<double2>(), a, reinterpret_cast<double2*>(coarse),
-                                  h->buf<double>("rpart", restrict_partial_doubles(h->cg, nrhs)), h->g, h->cg, nrhs,
-                                  h->st);
+    if (prec == MGDWF_F64) {
+      restrict_op<double2, double2>(h->V64.as<double2>(), a, reinterpret_cast<double2*>(coarse), part, h->g, h->cg,
+                                    nrhs, h->st);
+    } else {
+      const long long nc = h->coarse_len() * nrhs;
+      float2* a32 = h->buf<float2>("io_a32", n);
+      float2* c32 = h->buf<float2>("io_c32", nc);
+      convert<double2, float2>(a, a32, n, h->st);
+      restrict_op<float2, float2>(h->V32.as<float2>(), a32, c32, part, h->g, h->cg, nrhs, h->st);
+      convert<float2, double2>(c32, reinterpret_cast<double2*>(coarse), nc, h->st);
+    }
   });
 }
-
-mgdwf_status mgdwf_prolong(mgdwf_handle h, const double* coarse, double* fine, int32_t nrhs) {
+mgdwf_status mgdwf_prolong(mgdwf_handle h, const double* coarse, double* fine, int32_t nrhs, mgdwf_prec prec) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     need(fine && coarse && nrhs >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
+    check_prec_fine(prec);
     need(h->have_basis, MGDWF_ERR_STATE, "no basis installed");
     const long long n = h->fine_len() * nrhs;
     double2* a = h->buf<double2>("io_a", n);
-    prolong_op<double2, double2>(h->V64.as<double2>(), reinterpret_cast<const double2*>(coarse), a, false, h->g, h->cg,
-                                 nrhs, h->st);
+    if (prec == MGDWF_F64) {
+      prolong_op<double2, double2>(h->V64.as<double2>(), reinterpret_cast<const double2*>(coarse), a, false, h->g,
+                                   h->cg, nrhs, h->st);
+    } else {
+      const long long nc = h->coarse_len() * nrhs;
+      float2* a32 = h->buf<float2>("io_a32", n);
+      float2* c32 = h->buf<float2>("io_c32", nc);
+      convert<double2, float2>(reinterpret_cast<const double2*>(coarse), c32, nc, h->st);
+      prolong_op<float2, float2>(h->V32.as<float2>(), c32, a32, false, h->g, h->cg, nrhs, h->st);
+      convert<float2, double2>(a32, a, n, h->st);
+    }
     unpack_fermion_f64(a, reinterpret_cast<double2*>(fine), h->g, nrhs, h->st);
   });
 }
-
 mgdwf_status mgdwf_build_coarse(mgdwf_handle h) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {

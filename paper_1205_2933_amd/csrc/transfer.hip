@@ -212,6 +212,87 @@ __global__ __launch_bounds__(256) void k_restrict_mr(const C2* __restrict__ V, c
   }
 }
 
+// Multi-RHS restriction, FP32, basis and fields each read once: a 768-thread
+// workgroup owns a quarter of block B's rows.  Per chunk of 64 rows the
+// workgroup stages the rows of up to RX right-hand sides in LDS (layout
+// [rhs][component][row], so a wavefront reads 64 consecutive rows); wave w
+// then accumulates basis columns w and w + 12 against every staged
+// right-hand side, lane = row.  Sums in FP32 within the workgroup (16 chunks
+// x 6 components per lane, then 64 lanes), FP64 across workgroups; same
+// partial layout as k_restrict.
+constexpr int RX = 12, RW = 12, RT = 64 * RW;
+__global__ __launch_bounds__(RT) void k_restrict_lds(const float2* __restrict__ V, const float2* __restrict__ x,
+                                                     double* __restrict__ partial, BlockArgs a, int nrhs) {
+  constexpr int KW = 2;  // columns per wave: 12 waves x 2 = 24 >= Nv
+  __shared__ float2 xs[RX * 12 * 64];
+  const int B = blockIdx.x / NSPLIT, split = blockIdx.x % NSPLIT;
+  const int r0 = blockIdx.y * RX;
+  const int nr = min(RX, nrhs - r0);
+  const long long V5 = a.V5;
+  const long long field = 12 * V5;
+  const int n5 = a.bvol * a.Ls;
+  const int n2 = 2 * a.Nv;
+  const int per = n5 / NSPLIT;  // rows of this workgroup (n5 divides by 256)
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  float acc[KW][RX][2][2];
+#pragma unroll
+  for (int j = 0; j < KW; ++j)
+#pragma unroll
+    for (int r = 0; r < RX; ++r)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) { acc[j][r][h][0] = 0.f; acc[j][r][h][1] = 0.f; }
+  for (int c0 = 0; c0 < per; c0 += 64) {
+    __syncthreads();  // the previous chunk's rows are consumed
+    for (int q = threadIdx.x; q < nr * 12 * 64; q += RT) {
+      const int row = q & 63, rc = q >> 6;  // rc = r * 12 + component
+      const int jj = split * per + c0 + row;
+      const int jl = jj / a.Ls, s = jj - jl * a.Ls;
+      const long long i5 = (long long)block_site(a, B, jl) * a.Ls + s;
+      const int r = rc / 12, c = rc - r * 12;
+      xs[q] = x[(long long)(r0 + r) * field + c * V5 + i5];
+    }
+    __syncthreads();
+    const int jj = split * per + c0 + l;
+    const int jl = jj / a.Ls, s = jj - jl * a.Ls;
+    const long long i5 = (long long)block_site(a, B, jl) * a.Ls + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const int h = c / 6;
+      float2 v[KW];
+#pragma unroll
+      for (int j = 0; j < KW; ++j) {
+        const int k = w + RW * j;
+        v[j] = k < a.Nv ? V[(long long)k * field + c * V5 + i5] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int r = 0; r < RX; ++r) {
+        if (r < nr) {
+          const float2 xv = xs[(r * 12 + c) * 64 + l];
+#pragma unroll
+          for (int j = 0; j < KW; ++j) {
+            acc[j][r][h][0] += v[j].x * xv.x + v[j].y * xv.y;
+            acc[j][r][h][1] += v[j].x * xv.y - v[j].y * xv.x;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < KW; ++j) {
+    const int k = w + RW * j;
+#pragma unroll
+    for (int r = 0; r < RX; ++r)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ri = 0; ri < 2; ++ri) {
+          const float sum = wave_sum(acc[j][r][h][ri]);
+          if (l == 0 && k < a.Nv && r < nr)
+            partial[(((long long)(r0 + r) * a.Vc + B) * NSPLIT + split) * 2 * n2 + (h * a.Nv + k) * 2 + ri] = sum;
+        }
+  }
+}
+
 template <class C2>
 __global__ void k_restrict_finalize(const double* __restrict__ partial, C2* __restrict__ coarse,
                                     int Vc, int n2, int nrhs) {
@@ -458,6 +539,19 @@ void restrict_op(const C2* V, const C2* x, CC2* coarse, double* partial, const G
   BlockArgs a = make_args(g, cg);
   constexpr bool f64 = sizeof(typename real_of<C2>::type) == 8;
   constexpr int RG = 2, KR = f64 ? 4 : 6;
+  if constexpr (!f64) {
+    // basis and fields read once; rows per workgroup a multiple of 64
+    if (nrhs >= 2 && cg.Nv <= 24 && (cg.bvol * g.Ls) % (64 * NSPLIT) == 0) {
+      hipLaunchKernelGGL(k_restrict_lds, dim3(cg.Vc * NSPLIT, ceil_div(nrhs, RX)), dim3(RT), 0, st,
+                         reinterpret_cast<const float2*>(V), reinterpret_cast<const float2*>(x), partial, a, nrhs);
+      MG_LAUNCH_CHECK();
+      long long tot = (long long)nrhs * cg.Vc * cg.n2;
+      hipLaunchKernelGGL((k_restrict_finalize<CC2>), dim3(ceil_div(tot, 256)), dim3(256), 0, st, partial,
+                         coarse, cg.Vc, cg.n2, nrhs);
+      MG_LAUNCH_CHECK();
+      return;
+    }
+  }
   // the FP32 kernel reads s-pairs: Ls even keeps every pair inside one site
   if (nrhs >= 2 && (f64 || g.Ls % 2 == 0)) {
     hipLaunchKernelGGL((k_restrict_mr<C2, RG, KR>), dim3(cg.Vc * NSPLIT, ceil_div(nrhs, RG)), dim3(256), 0, st, V,

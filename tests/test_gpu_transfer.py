@@ -94,6 +94,30 @@ def test_restrict_prolong_match_oracle(cuda, case):
     assert rel(c1.cpu().numpy()[0], cg.cpu().numpy()[3]) < 1e-14
 
 
+@pytest.mark.parametrize("n", [2, 13])
+def test_restrict_prolong_fp32_kernels(cuda, n):
+    """The V-cycle's FP32 R and P: 4^4 blocks put 1024 rows in each quarter
+    block, so R takes the LDS-staged kernel (12 right-hand sides per group,
+    13 leaves a group of one); FP32 rounding of basis and fields bounds the
+    error at a few 1e-7 relative."""
+    import paper_1205_2933_amd as mg
+    case = ((8, 8, 8, 8), 4, (4, 4, 4, 4), 24, 0.01, (1, 1, 1, 1))
+    L, Ls, block, nvec, mf, bc = case
+    h, U, V, Vh = make(case, mg)
+    x = gaussian_fermion(L, Ls, 61, n=n)
+    cshape = ot.restrict(x[0], Vh, block).shape
+    cg = torch.empty((n,) + cshape, dtype=torch.complex128, device="cuda")
+    mg.mgdwf_restrict(h, dev(x), cg, nrhs=n, prec="f32")
+    rng = np.random.default_rng(3)
+    c = rng.standard_normal((n,) + cshape) + 1j * rng.standard_normal((n,) + cshape)
+    fg = torch.empty_like(dev(x))
+    mg.mgdwf_prolong(h, dev(c), fg, nrhs=n, prec="f32")
+    torch.cuda.synchronize()
+    for r in range(n):
+        assert rel(cg.cpu().numpy()[r], ot.restrict(x[r], Vh, block)) < 1e-5
+        assert rel(fg.cpu().numpy()[r], ot.prolong(c[r], Vh, block)) < 1e-5
+
+
 def test_rank_deficient_basis_is_rejected(cuda):
     import paper_1205_2933_amd as mg
     L, Ls = (4, 4, 4, 4), 4
