@@ -54,15 +54,21 @@ template <class C2> __device__ __forceinline__ C2 cmul(C2 a, C2 b) {
 template <class C2> __device__ __forceinline__ C2 cmulc(C2 a, C2 b) {
   return cmk<C2>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
-// acc += a * b
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc += a * b, as four fused multiply-adds into the accumulator
 template <class C2> __device__ __forceinline__ void cfma(C2& acc, C2 a, C2 b) {
-  acc.x += a.x * b.x - a.y * b.y;
-  acc.y += a.x * b.y + a.y * b.x;
+  acc.x = fmadd(a.x, b.x, acc.x);
+  acc.x = fmadd(-a.y, b.y, acc.x);
+  acc.y = fmadd(a.x, b.y, acc.y);
+  acc.y = fmadd(a.y, b.x, acc.y);
 }
 // acc += conj(a) * b
 template <class C2> __device__ __forceinline__ void cfmac(C2& acc, C2 a, C2 b) {
-  acc.x += a.x * b.x + a.y * b.y;
-  acc.y += a.x * b.y - a.y * b.x;
+  acc.x = fmadd(a.x, b.x, acc.x);
+  acc.x = fmadd(a.y, b.y, acc.x);
+  acc.y = fmadd(a.x, b.y, acc.y);
+  acc.y = fmadd(-a.y, b.x, acc.y);
 }
 // i * a
 template <class C2> __device__ __forceinline__ C2 ci(C2 a) { return cmk<C2>(-a.y, a.x); }

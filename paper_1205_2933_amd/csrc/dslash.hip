@@ -832,7 +832,7 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, PAD > 0 ? 1 : 2) void k_dslash_tq
     project<3, EB>(p0, hp0);
     project<3, EB>(p1, hp1);
   }
-  double nrm = 0.0;
+  float nrmf = 0.f;  // per-thread |out|^2 in FP32 (a few hundred terms), FP64 across the workgroup
   for (int t = t0; t < t1; ++t) {
     const int x4 = t * V3 + x3;
     const int tb = t * V3;
@@ -905,7 +905,7 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, PAD > 0 ? 1 : 2) void k_dslash_tq
           r1 = make_float2(bb.z - r1.x, bb.w - r1.y);
         }
         *reinterpret_cast<float4*>(out + cc + i5) = make_float4(r0.x, r0.y, r1.x, r1.y);
-        nrm += (double)r0.x * r0.x + (double)r0.y * r0.y + (double)r1.x * r1.x + (double)r1.y * r1.y;
+        if (partial) nrmf += r0.x * r0.x + r0.y * r0.y + r1.x * r1.x + r1.y * r1.y;
       }
     if (t + 1 < t1) {  // slice t+1: own terms, backward t-hop from slice t (never across the boundary here)
       own_pair(a0, a1, p0, p1, in, V5, basef, s0, Ls, dg, mf, up0, dn0);
@@ -918,7 +918,7 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, PAD > 0 ? 1 : 2) void k_dslash_tq
     }
   }
   if (partial) {
-    const double sum = block_sum_dyn(nrm);
+    const double sum = block_sum_dyn((double)nrmf);
     if (threadIdx.x == 0) partial[pidx] = sum;
   }
 }
