@@ -38,11 +38,14 @@ COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "dslash_f32_16c32x16_nrhs12_cou
 DSLASH_SRC = os.path.join(ROOT, "paper_1205_2933_amd", "csrc", "dslash.hip")
 
 
-def counted_traffic():
+def counted_traffic(tiling_id):
     """HBM bytes per launch of the FP32 Dslash at 12 RHS, from the committed
     FETCH_SIZE / WRITE_SIZE counter summary -- or None when the kernel source
-    has changed since the counters were taken."""
+    has changed since the counters were taken, or when the autotuner picked
+    another tiling than the default one the counters were taken on."""
     import hashlib
+    if tiling_id != 0:
+        return None
     try:
         fields = dict(line.split(":", 1) for line in open(COUNTER_SUMMARY) if line.startswith("- ") and ":" in line)
         fields = {k[2:].strip(): v.strip().strip("`") for k, v in fields.items()}
@@ -357,6 +360,7 @@ def main():
 
     import paper_1205_2933_amd as mg
     from inputs import point_sources, prepare_gauge, random_starts
+    log("imports done")
 
     fields_future = None
     if not args.no_learned:
@@ -388,7 +392,8 @@ def main():
     # ---- mixed precision, 12 right-hand sides per step; the FP32 Dslash
     # tiling is autotuned for 12 RHS first (part of the setup, not timed)
     tune = mg.mgdwf_tune(h, nrhs=nrhs, iters=10)
-    tiling = {"tile": tune["tile"][tune["chosen"]], "flags": tune["flags"][tune["chosen"]],
+    tiling = {"id": tune["id"][tune["chosen"]], "tile": tune["tile"][tune["chosen"]],
+              "flags": tune["flags"][tune["chosen"]],
               "us": tune["us"][tune["chosen"]], "tilings_timed": len(tune["id"])}
     log(f"dslash tiling {tiling}")
     mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f16"))
@@ -479,7 +484,7 @@ def main():
         "dslash_tiling": tiling,
         "roofline": {"bound": "hbm", "kernel": "k_dslash_tq (FP32 Dslash, 12 RHS per launch, autotuned tiling)",
                      "achieved": gbs32_12, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs32_12 / HBM_PEAK_GBS,
-                     "algorithmic_bytes": bytes32_12, "launch_us": ms32_12 * 1e3, "traffic": counted_traffic()},
+                     "algorithmic_bytes": bytes32_12, "launch_us": ms32_12 * 1e3, "traffic": counted_traffic(tiling["id"])},
     }
     # the legs below change the main handle's setup, so they come last
     if not args.no_mass_scan:

@@ -264,14 +264,17 @@ typedef enum {
 /* Autotuning of the FP32 Dslash: every tiling of the t-march kernel that
  * the lattice admits is timed (mgdwf_time_kernel's method, `iters` launches at
  * nrhs right-hand sides, D and D^+ alternating) and the fastest is kept on the
- * handle for every later FP32 fine-operator application.  Without a call the
- * first admissible tiling of the table is used.  Results are identical up to
- * FP32 rounding order whatever the tiling. */
+ * handle for every later FP32 fine-operator application, unless it is less
+ * than 3 % faster than the first admissible tiling (the default), which is
+ * then kept, so timing noise does not flip the choice between runs.  Without
+ * a call the default is used.  Results are identical up to FP32 rounding
+ * order whatever the tiling. */
 #define MGDWF_MAX_TILINGS 16
 #define MGDWF_TILE_RELOAD 1      /* kernel that reloads each slice's own spinor          */
 #define MGDWF_TILE_FOLDED 2      /* workgroups ordered t-chunk first across all RHS       */
 #define MGDWF_TILE_ONE_PER_CU 4  /* LDS reserved so one workgroup runs per CU             */
 #define MGDWF_TILE_LDS_LINKS 8   /* each t-slice's links staged in LDS by the workgroup   */
+#define MGDWF_TILE_PIPELINED 16  /* next hop's loads issued before this hop's SU(3) work  */
 typedef struct {
   int32_t ntilings;                   /* tilings timed                                  */
   int32_t chosen;                     /* index into the arrays below                     */

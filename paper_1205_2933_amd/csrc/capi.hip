@@ -536,8 +536,8 @@ mgdwf_status mgdwf_tune(mgdwf_handle h, int32_t nrhs, int32_t iters, mgdwf_tune_
     } ev;
     MG_HIP(hipEventCreate(&ev.e0));
     MG_HIP(hipEventCreate(&ev.e1));
-    int best = -1;
-    double best_us = 0.0;
+    int best = -1, dflt = -1, dflt_j = -1;
+    double best_us = 0.0, dflt_us = 0.0;
     for (int i = 0; i < dslash_ftile_count() && rep->ntilings < MGDWF_MAX_TILINGS; ++i) {
       Geometry g = h->g;
       g.ftile = i;
@@ -561,11 +561,20 @@ mgdwf_status mgdwf_tune(mgdwf_handle h, int32_t nrhs, int32_t iters, mgdwf_tune_
       rep->flags[j] = flags;
       for (int q = 0; q < 4; ++q) rep->tile[j][q] = desc[q];
       rep->us[j] = us;
+      if (dflt < 0) {
+        dflt = i;
+        dflt_j = j;
+        dflt_us = us;
+      }
       if (best < 0 || us < best_us) {
         best = i;
         best_us = us;
         rep->chosen = j;
       }
+    }
+    if (best >= 0 && best_us > 0.97 * dflt_us) {  // within noise of the default: keep it
+      best = dflt;
+      rep->chosen = dflt_j;
     }
     if (best >= 0) h->g.ftile = best;
   });

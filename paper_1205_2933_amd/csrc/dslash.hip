@@ -923,6 +923,245 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, PAD > 0 ? 1 : 2) void k_dslash_tq
   }
 }
 
+// ---------------------------------------------------------------- t-march, software-pipelined (FP32)
+// k_dslash_tq computes each hop right after loading it, so every hop waits
+// out a full memory round trip: with one wavefront per SIMD nothing else hides
+// it.  Here the loads of hop k+1 are issued as soon as hop k's spinor is
+// projected to half spinors (the raw registers are free again), and the SU(3)
+// products of hop k run while they are in flight.  Hop order per t-slice:
+// +x, -x, +y, -y, +z, -z, then +t, whose spinor (slice t+1) also gives slice
+// t+1's own terms and backward t-hop as in k_dslash_tq; the first hop of slice
+// t+1 is issued once slice t is stored.  Scheduling barriers keep the
+// compiler from sinking the early loads back to their uses.
+struct HopRaw {
+  float4 q[12];  // spin-colour component k of the pair (s0, s0 + 1)
+  float2 U[9];   // link entries (a, b) at 3a + b
+};
+
+__device__ __forceinline__ void issue_hop(HopRaw& r, const float2* __restrict__ in, const float2* __restrict__ gauge,
+                                          long long V5, long long V4, long long j5, int mu, int xlink) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) r.q[k] = *reinterpret_cast<const float4*>(in + k * V5 + j5);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) r.U[q] = gauge[(mu * 9 + q) * V4 + xlink];
+}
+
+__device__ __forceinline__ void unpack_pair(const HopRaw& r, Spinor<float2>& p0, Spinor<float2>& p1) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float4 v = r.q[sp * 3 + c];
+      p0.v[sp][c] = make_float2(v.x, v.y);
+      p1.v[sp][c] = make_float2(v.z, v.w);
+    }
+}
+
+// half spinors of both s-values and the link, copied out of the raw buffer
+template <int MU, int EPS>
+__device__ __forceinline__ void take_hop(const HopRaw& r, float2 h0[2][3], float2 h1[2][3], float2 U[3][3]) {
+  Spinor<float2> p0, p1;
+  unpack_pair(r, p0, p1);
+  project<MU, EPS>(p0, h0);
+  project<MU, EPS>(p1, h1);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) U[q / 3][q % 3] = r.U[q];
+}
+
+template <int MU, int EPS, bool DAGU>
+__device__ __forceinline__ void finish_hop(Spinor<float2>& a0, Spinor<float2>& a1, const float2 U[3][3],
+                                           const float2 h0[2][3], const float2 h1[2][3], float ph) {
+  float2 u[2][3];
+  mul_link<DAGU>(U, h0, u, ph);
+  accumulate<MU, EPS>(a0, u);
+  mul_link<DAGU>(U, h1, u, ph);
+  accumulate<MU, EPS>(a1, u);
+}
+
+// The fifth-dimension neighbours of the pair outside it (s0 - 1 for the spins
+// coupled to s-1, s0 + 2 for those coupled to s+1), six components each.
+__device__ __forceinline__ void issue_own(float2 ex[12], const float2* __restrict__ in, long long V5, long long base,
+                                          int s0, int Ls, int up0, int dn0) {
+  const int sm = s0 == 0 ? Ls - 1 : s0 - 1;
+  const int sp2 = s0 + 2 == Ls ? 0 : s0 + 2;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    ex[k] = in[(long long)((up0 + k / 3) * 3 + k % 3) * V5 + base + sp2];
+    ex[6 + k] = in[(long long)((dn0 + k / 3) * 3 + k % 3) * V5 + base + sm];
+  }
+}
+
+// own_pair with the out-of-pair neighbours already loaded by issue_own
+__device__ __forceinline__ void own_pair_pre(Spinor<float2>& a0, Spinor<float2>& a1, const Spinor<float2>& p0,
+                                             const Spinor<float2>& p1, const float2 ex[12], int s0, int Ls,
+                                             float dg, float mf, int up0, int dn0) {
+  const float cdn0 = s0 == 0 ? mf : -1.f;       // s0 - 1 across the wall
+  const float cup1 = s0 + 2 == Ls ? mf : -1.f;  // s0 + 2 across the wall
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float2 r0 = cscale(p0.v[sp][c], dg), r1 = cscale(p1.v[sp][c], dg);
+      if (sp == up0 || sp == up0 + 1) {
+        r0 = csub(r0, p1.v[sp][c]);                                 // s0 <- s0 + 1
+        r1 = cadd(r1, cscale(ex[(sp - up0) * 3 + c], cup1));        // s0 + 1 <- s0 + 2
+      }
+      if (sp == dn0 || sp == dn0 + 1) {
+        r0 = cadd(r0, cscale(ex[6 + (sp - dn0) * 3 + c], cdn0));    // s0 <- s0 - 1
+        r1 = csub(r1, p0.v[sp][c]);                                 // s0 + 1 <- s0
+      }
+      a0.v[sp][c] = cscale(r0, -2.f);
+      a1.v[sp][c] = cscale(r1, -2.f);
+    }
+}
+
+#define MG_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
+
+template <bool DAG, int MODE, int TX, int TY, int TZ, int PAD>
+__global__ __launch_bounds__(TX * TY * TZ * 8, 1) void k_dslash_tw(const float2* __restrict__ in,
+                                                                   float2* __restrict__ out,
+                                                                   const float2* __restrict__ b,
+                                                                   const float2* __restrict__ gauge, TMArgs ta,
+                                                                   double* __restrict__ partial) {
+  if (PAD > 0) {  // LDS reserved only to cap workgroups per CU (one per CU when PAD > 80 KB)
+    __shared__ float pad[PAD > 0 ? PAD / 4 : 1];
+    if (ta.d.Ls < 0) pad[threadIdx.x] = 0.f;  // never true: keeps the allocation
+    if (ta.d.Ls < 0) out[threadIdx.x].x = pad[threadIdx.x ^ 1];
+  }
+  const DslashArgs& a = ta.d;
+  const int ntiles = ta.ntx * ta.nty * ta.ntz;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  int chunk, tile, rhs, pidx;
+  if (ta.fold) {
+    const int per_chunk = ta.nrhs * ntiles;
+    chunk = bid / per_chunk;
+    const int r2 = bid - chunk * per_chunk;
+    rhs = r2 / ntiles;
+    tile = r2 - rhs * ntiles;
+    pidx = rhs * (gridDim.x / ta.nrhs) + chunk * ntiles + tile;
+  } else {
+    chunk = bid / ntiles;
+    tile = bid - chunk * ntiles;
+    rhs = blockIdx.y;
+    pidx = blockIdx.y * gridDim.x + blockIdx.x;
+  }
+  const int tx = tile % ta.ntx, ty = (tile / ta.ntx) % ta.nty, tz = tile / (ta.ntx * ta.nty);
+  const int Ls = a.Ls, np = Ls >> 1;
+  const int site = threadIdx.x / np, jp = threadIdx.x - site * np;
+  const int s0 = 2 * jp;
+  const int x = tx * TX + site % TX, y = ty * TY + (site / TX) % TY, z = tz * TZ + site / (TX * TY);
+  const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2], Lt = a.L[3];
+  const long long V5 = a.V5, V4 = a.V4;
+  const int V3 = Lx * Ly * Lz;
+  const long long roff = (long long)rhs * 12 * V5;
+  in += roff;
+  out += roff;
+  if (MODE == 1) b += roff;
+  const int x3 = (z * Ly + y) * Lx + x;
+  int nf3[3], nb3[3];
+  float phf[3], phb[3];
+  {
+    const int co[3] = {x, y, z};
+    const int Lm[3] = {Lx, Ly, Lz};
+    const int st[3] = {1, Lx, Lx * Ly};
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      const bool top = co[mu] == Lm[mu] - 1, bot = co[mu] == 0;
+      nf3[mu] = top ? x3 - (Lm[mu] - 1) * st[mu] : x3 + st[mu];
+      nb3[mu] = bot ? x3 + (Lm[mu] - 1) * st[mu] : x3 - st[mu];
+      phf[mu] = top ? a.ph[mu] : 1.0f;
+      phb[mu] = bot ? a.ph[mu] : 1.0f;
+    }
+  }
+  constexpr int EF = DAG ? 1 : -1;
+  constexpr int EB = DAG ? -1 : 1;
+  const int up0 = DAG ? 0 : 2;   // spins coupled to s+1
+  const int dn0 = DAG ? 2 : 0;   // spins coupled to s-1
+  const float dg = (float)a.diag, mf = (float)a.mf;
+  const int t0 = chunk * ta.tc;
+  const int t1 = min(t0 + ta.tc, Lt);
+  float2 hp0[2][3], hp1[2][3], U[3][3], h0[2][3], h1[2][3];
+  Spinor<float2> p0, p1, a0, a1;
+  HopRaw r;
+  float2 ex[12];
+  {  // slice t0: own terms, and the backward t-hop from slice t0 - 1
+    const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+    const int x4m = tm * V3 + x3;
+    load_pair(p0, p1, in, V5, (long long)x4m * Ls + s0);
+    project<3, EB>(p0, hp0);
+    project<3, EB>(p1, hp1);
+    const long long base = (long long)(t0 * V3 + x3) * Ls;
+    load_pair(p0, p1, in, V5, base + s0);
+    own_pair(a0, a1, p0, p1, in, V5, base, s0, Ls, dg, mf, up0, dn0);
+    load_link(gauge, 3, V4, x4m, U);
+    const float ph = t0 == 0 ? a.ph[3] : 1.0f;
+    finish_hop<3, EB, true>(a0, a1, U, hp0, hp1, ph);
+    project<3, EB>(p0, hp0);
+    project<3, EB>(p1, hp1);
+    const int tb = t0 * V3;
+    issue_hop(r, in, gauge, V5, V4, (long long)(tb + nf3[0]) * Ls + s0, 0, tb + x3);
+  }
+  float nrmf = 0.f;  // per-thread |out|^2 in FP32, FP64 across the workgroup
+  for (int t = t0; t < t1; ++t) {
+    const int x4 = t * V3 + x3;
+    const int tb = t * V3;
+    const bool top = t == Lt - 1;
+    const long long basef = (long long)((top ? 0 : t + 1) * V3 + x3) * Ls;
+    // hops +x .. -z: project hop k, issue hop k+1, finish hop k
+#define MG_TW_STAGE(MU, E, DAGU, PH, NEXT)  \
+    take_hop<MU, E>(r, h0, h1, U);          \
+    MG_SCHED_FENCE();                       \
+    NEXT;                                   \
+    MG_SCHED_FENCE();                       \
+    finish_hop<MU, E, DAGU>(a0, a1, U, h0, h1, PH);
+    MG_TW_STAGE(0, EF, false, phf[0], issue_hop(r, in, gauge, V5, V4, (long long)(tb + nb3[0]) * Ls + s0, 0, tb + nb3[0]))
+    MG_TW_STAGE(0, EB, true, phb[0], issue_hop(r, in, gauge, V5, V4, (long long)(tb + nf3[1]) * Ls + s0, 1, x4))
+    MG_TW_STAGE(1, EF, false, phf[1], issue_hop(r, in, gauge, V5, V4, (long long)(tb + nb3[1]) * Ls + s0, 1, tb + nb3[1]))
+    MG_TW_STAGE(1, EB, true, phb[1], issue_hop(r, in, gauge, V5, V4, (long long)(tb + nf3[2]) * Ls + s0, 2, x4))
+    MG_TW_STAGE(2, EF, false, phf[2], issue_hop(r, in, gauge, V5, V4, (long long)(tb + nb3[2]) * Ls + s0, 2, tb + nb3[2]))
+    MG_TW_STAGE(2, EB, true, phb[2], issue_hop(r, in, gauge, V5, V4, basef + s0, 3, x4);
+                issue_own(ex, in, V5, basef, s0, Ls, up0, dn0))
+#undef MG_TW_STAGE
+    // +t: slice t+1's spinor stays in p0, p1 for its own terms
+    unpack_pair(r, p0, p1);
+    project<3, EF>(p0, h0);
+    project<3, EF>(p1, h1);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) U[q / 3][q % 3] = r.U[q];
+    finish_hop<3, EF, false>(a0, a1, U, h0, h1, top ? a.ph[3] : 1.0f);
+    const long long i5 = (long long)x4 * Ls + s0;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const long long cc = (long long)(sp * 3 + c) * V5;
+        float2 r0 = cscale(a0.v[sp][c], -0.5f), r1 = cscale(a1.v[sp][c], -0.5f);
+        if (MODE == 1) {
+          const float4 bb = *reinterpret_cast<const float4*>(b + cc + i5);
+          r0 = make_float2(bb.x - r0.x, bb.y - r0.y);
+          r1 = make_float2(bb.z - r1.x, bb.w - r1.y);
+        }
+        *reinterpret_cast<float4*>(out + cc + i5) = make_float4(r0.x, r0.y, r1.x, r1.y);
+        if (partial) nrmf += r0.x * r0.x + r0.y * r0.y + r1.x * r1.x + r1.y * r1.y;
+      }
+    if (t + 1 < t1) {  // slice t+1: first hop in flight, then own terms and backward t-hop
+      const int tb1 = tb + V3;
+      MG_SCHED_FENCE();
+      issue_hop(r, in, gauge, V5, V4, (long long)(tb1 + nf3[0]) * Ls + s0, 0, tb1 + x3);
+      MG_SCHED_FENCE();
+      own_pair_pre(a0, a1, p0, p1, ex, s0, Ls, dg, mf, up0, dn0);
+      finish_hop<3, EB, true>(a0, a1, U, hp0, hp1, 1.0f);
+      project<3, EB>(p0, hp0);
+      project<3, EB>(p1, hp1);
+    }
+  }
+  if (partial) {
+    const double sum = block_sum_dyn((double)nrmf);
+    if (threadIdx.x == 0) partial[pidx] = sum;
+  }
+}
+#undef MG_SCHED_FENCE
+
 }  // namespace
 
 // FP32 t-march tilings: x, y, z tile, workgroups aimed at per right-hand side
@@ -934,19 +1173,24 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, PAD > 0 ? 1 : 2) void k_dslash_tq
 // neighbouring workgroups); one workgroup per CU halves the L2 footprint and
 // the fetch (1.9x) but gains only 3 %, and staging the links in LDS (which
 // removes most of the link loads) is 25 % slower -- the kernel is limited by
-// the issue and latency of its 16-byte spinor loads, not by DRAM bytes.
+// the issue and latency of its 16-byte spinor loads, not by DRAM bytes.  The
+// software-pipelined k_dslash_tw keeps a hop's loads in flight under the
+// previous hop's arithmetic and is within 1-6 % of k_dslash_tq.
 struct FTile {
   int tx, ty, tz, target;
   bool eight_loads;  // k_dslash_tp (reloads the own slice) instead of k_dslash_tq
   int fold;          // workgroup order (TMArgs::fold)
   bool one_per_cu = false;  // reserve LDS so that one workgroup runs per CU
   bool lds_links = false;   // stage each slice's links in LDS
+  bool pipelined = false;   // k_dslash_tw (loads one hop ahead)
 };
 constexpr FTile kFTiles[] = {
     {4, 4, 2, 256, false, 0, true}, {4, 4, 2, 512, false, 0, true}, {4, 4, 2, 256, false, 0},
     {4, 4, 2, 512, false, 0},       {8, 2, 2, 512, false, 0},       {8, 4, 2, 256, false, 0},
     {4, 4, 4, 512, false, 0},       {4, 8, 2, 512, false, 0},       {4, 4, 2, 1024, false, 1},
     {4, 4, 2, 512, true, 0},        {4, 4, 2, 256, false, 0, true, true},
+    {4, 4, 2, 256, false, 0, true, false, true}, {4, 4, 2, 256, false, 0, false, false, true},
+    {4, 4, 2, 512, false, 0, true, false, true},
 };
 constexpr int NFTILE = sizeof(kFTiles) / sizeof(kFTiles[0]);
 
@@ -986,7 +1230,7 @@ bool dslash_ftile_desc(const Geometry& g, int i, int desc[4], int* flags) {
   desc[2] = kFTiles[i].tz;
   desc[3] = ftile_chunk(g, i);
   *flags = (kFTiles[i].eight_loads ? 1 : 0) | (kFTiles[i].fold ? 2 : 0) | (kFTiles[i].one_per_cu ? 4 : 0) |
-           (kFTiles[i].lds_links ? 8 : 0);
+           (kFTiles[i].lds_links ? 8 : 0) | (kFTiles[i].pipelined ? 16 : 0);
   return true;
 }
 
@@ -1029,6 +1273,23 @@ static void launch_tpair(const float2* in, float2* out, const float2* b, const f
     return;
   }
   constexpr int P1 = 96 * 1024;
+  if (f.pipelined && f.tx == 4 && f.ty == 4 && f.tz == 2) {
+#define MG_TW(DAG, MODE, PAD) \
+  hipLaunchKernelGGL((k_dslash_tw<DAG, MODE, 4, 4, 2, PAD>), grid, blk, 0, st, in, out, b, gauge, ta, partial)
+    if (f.one_per_cu) {
+      if (!dagger && mode == 0) MG_TW(false, 0, P1);
+      else if (!dagger && mode == 1) MG_TW(false, 1, P1);
+      else if (dagger && mode == 0) MG_TW(true, 0, P1);
+      else MG_TW(true, 1, P1);
+    } else {
+      if (!dagger && mode == 0) MG_TW(false, 0, 0);
+      else if (!dagger && mode == 1) MG_TW(false, 1, 0);
+      else if (dagger && mode == 0) MG_TW(true, 0, 0);
+      else MG_TW(true, 1, 0);
+    }
+#undef MG_TW
+    return;
+  }
 #define MG_TQL(X, Y, Z)                                                                        \
   if (f.tx == X && f.ty == Y && f.tz == Z) {                                                   \
     if (f.one_per_cu) launch_tq<X, Y, Z, P1, false>(in, out, b, gauge, ta, partial, dagger, mode, grid, blk, st); \
