@@ -109,7 +109,8 @@ typedef struct {
   int64_t coarse_applies; /* applications of D_c or D_c^+                          */
   double true_relres;     /* |b - D x| / |b| in FP64 at return                    */
   double seconds;         /* wall time of the call                                */
-  uint32_t flags;         /* bit 0: NaN/Inf met; bit 1: stagnation              */
+  uint32_t flags;         /* bit 0: NaN/Inf met; bit 1: stagnation; bit 2: a   */
+                          /* second Gram-Schmidt pass was needed in the FGCR    */
 } mgdwf_solve_report;
 
 /* Setup report: median |D v|/|v| over the adaptive vectors after each sweep. */

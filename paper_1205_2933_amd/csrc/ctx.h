@@ -42,6 +42,7 @@ struct mgdwf_ctx {
 
   long long fine_applies = 0;    // per right-hand side, since the last reset
   long long coarse_applies = 0;
+  long long gs_repeats = 0;      // flexible-GCR steps that needed a second Gram-Schmidt pass
 
   // Workspace `name` with room for `count` elements of T (contents undefined).
   template <class T>

@@ -109,7 +109,7 @@ struct TwoLevel {
   int nrhs;
   mgdwf_mg_params p;
   long long nf, nc;  // per-RHS lengths (complex numbers)
-  F2 *r1, *pp, *qq, *b3, *x3, *r3;
+  F2 *r1, *qq, *b3, *r3;
   F2 *cb, *cx, *cr, *cp, *cq, *ct;  // coarse vectors (same real type as the fine level)
   double* sl;
   double* vpart;
@@ -119,10 +119,8 @@ struct TwoLevel {
     nc = c->coarse_len();
     const std::string t = Prec<F2>::tag;
     r1 = c->buf<F2>("vc_r1" + t, nf * nrhs);
-    pp = c->buf<F2>("vc_p" + t, nf * nrhs);
     qq = c->buf<F2>("vc_q" + t, nf * nrhs);
     b3 = c->buf<F2>("vc_b3" + t, nf * nrhs);
-    x3 = c->buf<F2>("vc_x3" + t, nf * nrhs);
     r3 = c->buf<F2>("vc_r3" + t, nf * nrhs);
     cb = c->buf<F2>("vc_cb" + t, nc * nrhs);
     cx = c->buf<F2>("vc_cx" + t, nc * nrhs);
@@ -137,10 +135,12 @@ struct TwoLevel {
   // nu steps of minimal residual along D^+ r on D x = b from x = 0.  The
   // directions p_i are kept and x = sum_i alpha_i p_i is formed once at the end,
   // so a step moves r, q and the new r only; step 0 reads b in place of r.
-  void smooth(const F2* b, F2* x, F2* r, int nu) {
+  // Without need_r the last step skips the residual update nobody reads;
+  // with add_x the step sum is added to x instead of replacing it.
+  void smooth(const F2* b, F2* x, F2* r, int nu, bool need_r = true, bool add_x = false) {
     if (nu == 0) {
       copy(c, b, r, nf * nrhs);
-      zero<F2>(x, nf * nrhs, c->st);
+      if (!add_x) zero<F2>(x, nf * nrhs, c->st);
       return;
     }
     const std::string t = Prec<F2>::tag;
@@ -150,9 +150,9 @@ struct TwoLevel {
       const F2* rin = i == 0 ? b : r;
       fine_op<F2>(c, rin, P[i], nullptr, true, 0, nrhs, S_MR + 2 * i);      // p_i = D^+ r, |p_i|^2
       fine_op<F2>(c, P[i], qq, nullptr, false, 0, nrhs, S_MR + 2 * i + 1);  // q = D p_i, |q|^2
-      res_update<F2>(r, rin, qq, nf, nrhs, sl, S_MR + 2 * i, S_MR + 2 * i + 1, c->st);
+      if (need_r || i + 1 < nu) res_update<F2>(r, rin, qq, nf, nrhs, sl, S_MR + 2 * i, S_MR + 2 * i + 1, c->st);
     }
-    lincomb<F2>(x, ptr_table<F2>(c, "ptrP" + t, P), nu, nf, nrhs, sl, S_MR, c->st);
+    lincomb<F2>(x, ptr_table<F2>(c, "ptrP" + t, P), nu, nf, nrhs, sl, S_MR, add_x, c->st);
   }
 
   // CGNE on D_c: x = D_c^+ y with D_c D_c^+ y = b, to |r| < tol |b| or maxiter.
@@ -250,8 +250,7 @@ struct TwoLevel {
     prolong_op<F2, F2>(V, cx, z, true, c->g, c->cg, nrhs, c->st);       // x1 + P x2
     if (p.nu_post > 0) {
       fine_op<F2>(c, z, b3, b, false, 1, nrhs, -1);                      // b3 = b - A(P x2 + x1)
-      smooth(b3, x3, r3, p.nu_post);                                     // S3^nu3(A, b3)
-      add_to<F2, F2>(z, x3, nf * nrhs, c->st);
+      smooth(b3, z, r3, p.nu_post, false, true);                         // z += S3^nu3(A, b3)
     }
   }
 };
@@ -277,11 +276,22 @@ int fgcr_cycle(mgdwf_ctx* c, TwoLevel<F2>& M, F2* r, F2* e, int nrhs, int kmax, 
   for (; k < kmax; ++k) {
     M.apply(r, Z[k]);                                           // z = M r
     fine_op<F2>(c, Z[k], Q[k], nullptr, false, 0, nrhs, -1);    // q = D z
-    for (int pass = 0; pass < 2 && k > 0; ++pass) {             // classical Gram-Schmidt, twice
-      multidot_rhs<F2>(Qd, k, Q[k], nullptr, nf, nrhs, vpart, sl, S_DOT, c->st);
+    // classical Gram-Schmidt against q_0..q_{k-1} (z follows q); a second pass
+    // only where the first cancelled most of q (|q| fell below 1/sqrt 2 of
+    // its norm before the pass), the usual twice-is-enough criterion
+    for (int pass = 0; pass < 2 && k > 0; ++pass) {
+      multidot_rhs<F2>(Qd, k, Q[k], nullptr, nf, nrhs, vpart, sl, S_DOT, c->st);  // |q|^2 before at S_DOT + 2k
       orth_update<F2>(Q[k], Z[k], Qd, Zd, k, nf, nrhs, sl, S_DOT, S_QN, c->st);
+      norm_into<F2>(c, Q[k], r, nf, nrhs, S_QN + k);            // |q_k|^2, <q_k, r>
+      if (pass == 1) break;
+      std::vector<double> g = read_slots(c, nrhs);
+      bool again = false;
+      for (int rr = 0; rr < nrhs; ++rr)
+        if (!(g[rr * NSLOT + S_QN + k] >= 0.5 * g[rr * NSLOT + S_DOT + 2 * k])) again = true;
+      if (!again) break;
+      ++c->gs_repeats;
     }
-    norm_into<F2>(c, Q[k], r, nf, nrhs, S_QN + k);              // |q_k|^2, <q_k, r>
+    if (k == 0) norm_into<F2>(c, Q[k], r, nf, nrhs, S_QN + k);  // |q_0|^2, <q_0, r>
     gcr_update<F2>(e, r, Z[k], Q[k], nf, nrhs, sl, S_QN + k + 1, S_QN + k, k == 0, vpart, c->st);
     finalize_rhs(vpart, VEC_BLOCKS, 1, sl, S_RIN, nrhs, c->st);
     std::vector<double> h = read_slots(c, nrhs);
@@ -313,7 +323,7 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
   F2* rin = c->buf<F2>(std::string("sol_rin") + Prec<F2>::tag, nf * nrhs);
   F2* e = c->buf<F2>(std::string("sol_e") + Prec<F2>::tag, nf * nrhs);
   TwoLevel<F2> M(c, nrhs, c->mp);
-  const long long fa0 = c->fine_applies, ca0 = c->coarse_applies;
+  const long long fa0 = c->fine_applies, ca0 = c->coarse_applies, gs0 = c->gs_repeats;
   auto t0 = std::chrono::steady_clock::now();
   norm_into<double2>(c, b64, nullptr, nf, nrhs, S_B);
   std::vector<double> h = read_slots(c, nrhs);
@@ -354,6 +364,7 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
     ++restarts;
   }
   double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (c->gs_repeats > gs0) flags |= 4u;
   if (rep)
     for (int r = 0; r < nrhs; ++r) {
       rep[r].outer_iters = outer;

@@ -20,7 +20,8 @@ template <class C2>
 void res_update(C2* rout, const C2* rin, const C2* q, long long n, int nrhs, const double* sl, int num, int den,
                 hipStream_t st);
 template <class C2>
-void lincomb(C2* x, const C2* const* ps, int nv, long long n, int nrhs, const double* sl, int num, hipStream_t st);
+void lincomb(C2* x, const C2* const* ps, int nv, long long n, int nrhs, const double* sl, int num, bool acc,
+             hipStream_t st);
 template <class C2>
 void multidot_rhs(const C2* const* avec, int nv, const C2* b, const C2* c, long long n, int nrhs, double* partial,
                   double* sl, int dst, hipStream_t st);

@@ -64,10 +64,10 @@ __global__ __launch_bounds__(256) void k_res_update(C2* __restrict__ rout, const
     rout[off + i] = csub(rin[off + i], cscale(q[off + i], alpha));
 }
 
-// x = sum_m alpha_m p_m, alpha_m = sl[num + 2m] / sl[num + 2m + 1]  (m < nv)
+// x = sum_m alpha_m p_m (acc: x += ...), alpha_m = sl[num + 2m] / sl[num + 2m + 1]  (m < nv)
 template <class C2>
 __global__ __launch_bounds__(256) void k_lincomb(C2* __restrict__ x, const C2* const* __restrict__ ps, int nv,
-                                                 long long n, const double* __restrict__ sl, int num) {
+                                                 long long n, const double* __restrict__ sl, int num, int acc0) {
   using T = typename real_of<C2>::type;
   constexpr int MAXV = 16;
   const int rhs = blockIdx.y;
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_lincomb(C2* __restrict__ x, const C2* c
     al[m] = (T)(d > 0.0 ? slot(sl, rhs, num + 2 * m) / d : 0.0);
   }
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    C2 acc = cmk<C2>(0, 0);
+    C2 acc = acc0 ? x[off + i] : cmk<C2>(0, 0);
 #pragma unroll
     for (int m = 0; m < MAXV; ++m)
       if (m < nv) acc = cadd(acc, cscale(ps[m][off + i], al[m]));
@@ -288,9 +288,10 @@ void res_update(C2* rout, const C2* rin, const C2* q, long long n, int nrhs, con
 }
 
 template <class C2>
-void lincomb(C2* x, const C2* const* ps, int nv, long long n, int nrhs, const double* sl, int num, hipStream_t st) {
+void lincomb(C2* x, const C2* const* ps, int nv, long long n, int nrhs, const double* sl, int num, bool acc,
+             hipStream_t st) {
   if (nv > 16) fail(MGDWF_ERR_INVALID_ARG, "at most 16 smoother steps");
-  hipLaunchKernelGGL(k_lincomb<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, x, ps, nv, n, sl, num);
+  hipLaunchKernelGGL(k_lincomb<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, x, ps, nv, n, sl, num, acc ? 1 : 0);
   MG_LAUNCH_CHECK();
 }
 
@@ -362,7 +363,7 @@ void reflect5(const C2* in, C2* out, const Geometry& g, int nf, hipStream_t st) 
                               double*, hipStream_t);                                                             \
   template void cg_dir<C2>(C2*, const C2*, long long, int, const double*, int, int, double*, hipStream_t);      \
   template void res_update<C2>(C2*, const C2*, const C2*, long long, int, const double*, int, int, hipStream_t); \
-  template void lincomb<C2>(C2*, const C2* const*, int, long long, int, const double*, int, hipStream_t);        \
+  template void lincomb<C2>(C2*, const C2* const*, int, long long, int, const double*, int, bool, hipStream_t);        \
   template void multidot_rhs<C2>(const C2* const*, int, const C2*, const C2*, long long, int, double*, double*, \
                                  int, hipStream_t);                                                              \
   template void orth_update<C2>(C2*, C2*, const C2* const*, const C2* const*, int, long long, int,              \
