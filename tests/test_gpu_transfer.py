@@ -22,6 +22,7 @@ CASES = [
     ((2, 2, 2, 2), 4, (2, 2, 2, 2), 6, 0.05, (1, 1, 1, 1)),     # a single coarse site: all d alias to self
     ((8, 4, 6, 4), 6, (4, 2, 2, 4), 10, 0.02, (1, -1, 1, -1)),  # ragged, coarse extents 2,2,3,1
     ((4, 4, 6, 6), 4, (2, 2, 2, 2), 16, 0.001, (1, 1, 1, 1)),   # coarse extent 3: true 9-point stencil
+    ((4, 2, 6, 6), 4, (2, 2, 2, 3), 32, 0.01, (1, 1, -1, 1)),   # the largest coarse block (2 Nv = 64)
 ]
 
 # 16-bit storage: per-block scale, FP32 accumulation.  Unit roundoff 2^-11 (FP16)
