@@ -393,6 +393,8 @@ def main():
     # tiling is autotuned for 12 RHS first (part of the setup, not timed)
     tune = mg.mgdwf_tune(h, nrhs=nrhs, iters=10)
     tiling = {"id": tune["id"][tune["chosen"]], "tile": tune["tile"][tune["chosen"]],
+              "coarse_mfma": {0: "16x16x16", 1: "16x16x32"}.get(tune["coarse_chosen"]),
+              "coarse_us": tune["coarse_us"],
               "flags": tune["flags"][tune["chosen"]],
               "us": tune["us"][tune["chosen"]], "tilings_timed": len(tune["id"])}
     log(f"dslash tiling {tiling}")

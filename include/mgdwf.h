@@ -283,8 +283,18 @@ typedef struct {
   int32_t tile[MGDWF_MAX_TILINGS][4]; /* x, y, z sites per workgroup, t-slices per one   */
   int32_t flags[MGDWF_MAX_TILINGS];   /* MGDWF_TILE_* bits                               */
   double us[MGDWF_MAX_TILINGS];       /* mean time per launch                           */
+  int32_t coarse_chosen;              /* 16-bit D_c apply shape kept: 0 = 16x16x16 MFMA,  */
+                                      /* 1 = 16x16x32 MFMA; -1 if no D_c was built        */
+  double coarse_us[2];                /* mean time per D_c apply for each shape (FP16)  */
 } mgdwf_tune_report;
 mgdwf_status mgdwf_tune(mgdwf_handle h, int32_t nrhs, int32_t iters, mgdwf_tune_report* report);
+
+/* MFMA shape of the FP16/BF16 coarse apply: 0 = 16x16x16 tiles, 1 = 16x16x32
+ * tiles (gfx950), -1 = the default (0).  mgdwf_tune also times both (4 iters
+ * launches each at its nrhs, after the Dslash tilings, when the coarse
+ * operator is built) and keeps shape 1 only when it is at least 3 % faster.
+ * The two differ only in FP32 summation order. */
+mgdwf_status mgdwf_set_coarse_tiling(mgdwf_handle h, int32_t id);
 /* Use tiling `id` (from a tune report) for later FP32 applications; -1 restores
  * the default.  MGDWF_ERR_INVALID_ARG if the lattice does not admit it. */
 mgdwf_status mgdwf_set_tiling(mgdwf_handle h, int32_t id);

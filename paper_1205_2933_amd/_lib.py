@@ -75,13 +75,15 @@ MGDWF_MAX_TILINGS = 16
 class mgdwf_tune_report(ctypes.Structure):
     _fields_ = [("ntilings", ctypes.c_int32), ("chosen", ctypes.c_int32), ("id", ctypes.c_int32 * MGDWF_MAX_TILINGS),
                 ("tile", (ctypes.c_int32 * 4) * MGDWF_MAX_TILINGS), ("flags", ctypes.c_int32 * MGDWF_MAX_TILINGS),
-                ("us", ctypes.c_double * MGDWF_MAX_TILINGS)]
+                ("us", ctypes.c_double * MGDWF_MAX_TILINGS), ("coarse_chosen", ctypes.c_int32),
+                ("coarse_us", ctypes.c_double * 2)]
 
     def as_dict(self):
         n = self.ntilings
         return {"chosen": self.chosen, "id": [self.id[i] for i in range(n)],
                 "tile": [list(self.tile[i]) for i in range(n)], "flags": [self.flags[i] for i in range(n)],
-                "us": [self.us[i] for i in range(n)]}
+                "us": [self.us[i] for i in range(n)], "coarse_chosen": self.coarse_chosen,
+                "coarse_us": [self.coarse_us[0], self.coarse_us[1]] if self.coarse_chosen >= 0 else []}
 
 
 class mgdwf_net_config(ctypes.Structure):
@@ -128,6 +130,7 @@ def _load() -> ctypes.CDLL:
                               ctypes.c_int),
         "mgdwf_tune": ([H, i32, i32, ctypes.POINTER(mgdwf_tune_report)], ctypes.c_int),
         "mgdwf_set_tiling": ([H, i32], ctypes.c_int),
+        "mgdwf_set_coarse_tiling": ([H, i32], ctypes.c_int),
         "mgdwf_net_create": ([ctypes.POINTER(mgdwf_net_config), ctypes.POINTER(H)], ctypes.c_int),
         "mgdwf_net_destroy": ([H], ctypes.c_int),
         "mgdwf_net_last_error": ([H], ctypes.c_char_p),
@@ -356,6 +359,11 @@ def mgdwf_tune(h: Handle, nrhs=1, iters=10) -> dict:
 
 def mgdwf_set_tiling(h: Handle, tiling_id: int):
     _check(h.h, _lib.mgdwf_set_tiling(h.h, tiling_id))
+
+
+def mgdwf_set_coarse_tiling(h: Handle, tiling_id: int):
+    """MFMA shape of the 16-bit coarse apply: 0 = 16x16x16, 1 = 16x16x32, -1 = default."""
+    _check(h.h, _lib.mgdwf_set_coarse_tiling(h.h, tiling_id))
 
 
 # ---- learned near-null proposals --------------------------------------------

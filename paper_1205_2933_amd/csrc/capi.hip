@@ -306,7 +306,8 @@ mgdwf_status mgdwf_apply_coarse(mgdwf_handle h, const double* in, double* out, i
       float2* a = h->buf<float2>("cio_a32", n);
       float2* b = h->buf<float2>("cio_b32", n);
       convert<double2, float2>(reinterpret_cast<const double2*>(in), a, n, h->st);
-      coarse_apply32(s, prec, a, b, h->cg, nrhs, h->buf<char>("cio_pack", coarse_pack_bytes(h->cg, nrhs)), h->st);
+      coarse_apply32(s, prec, a, b, h->cg, nrhs, h->buf<char>("cio_pack", coarse_pack_bytes(h->cg, nrhs)),
+                     h->g.ctile, h->st);
       convert<float2, double2>(b, reinterpret_cast<double2*>(out), n, h->st);
     }
   });
@@ -485,7 +486,7 @@ mgdwf_status mgdwf_time_kernel(mgdwf_handle h, mgdwf_kernel k, mgdwf_prec prec, 
               coarse_apply64(h->Dc, h->buf<double2>("t_c", nc), h->buf<double2>("t_d", nc), h->cg, nrhs, h->st);
             else
               coarse_apply32(h->Dc, prec, h->buf<float2>("t_c32", nc), h->buf<float2>("t_d32", nc), h->cg, nrhs,
-                             h->buf<char>("t_pack", coarse_pack_bytes(h->cg, nrhs)), h->st);
+                             h->buf<char>("t_pack", coarse_pack_bytes(h->cg, nrhs)), h->g.ctile, h->st);
           } else {
             fail(MGDWF_ERR_INVALID_ARG, "unknown kernel id");
           }
@@ -577,6 +578,39 @@ mgdwf_status mgdwf_tune(mgdwf_handle h, int32_t nrhs, int32_t iters, mgdwf_tune_
       rep->chosen = dflt_j;
     }
     if (best >= 0) h->g.ftile = best;
+    // MFMA shape of the 16-bit coarse apply, timed on the FP16 store (the BF16
+    // one has the same shape), when a coarse operator is built
+    rep->coarse_chosen = -1;
+    if (h->have_coarse && h->cg.n2 % 16 == 0) {
+      const long long nc = h->coarse_len() * nrhs;
+      float2* ca = h->buf<float2>("t_c32", nc);
+      float2* cb = h->buf<float2>("t_d32", nc);
+      zero<float2>(ca, nc, h->st);
+      char* pk = h->buf<char>("t_pack", coarse_pack_bytes(h->cg, nrhs));
+      for (int ct = 0; ct < 2; ++ct) {
+        auto run = [&](int n) {
+          for (int k = 0; k < n; ++k) coarse_apply32(h->Dc, MGDWF_F16, ca, cb, h->cg, nrhs, pk, ct, h->st);
+        };
+        run(2);
+        MG_HIP(hipEventRecord(ev.e0, h->st));
+        run(4 * iters);
+        MG_HIP(hipEventRecord(ev.e1, h->st));
+        MG_HIP(hipEventSynchronize(ev.e1));
+        float ms = 0.f;
+        MG_HIP(hipEventElapsedTime(&ms, ev.e0, ev.e1));
+        rep->coarse_us[ct] = 1e3 * ms / (4 * iters);
+      }
+      rep->coarse_chosen = rep->coarse_us[1] <= 0.97 * rep->coarse_us[0] ? 1 : 0;
+      h->g.ctile = rep->coarse_chosen;
+    }
+  });
+}
+
+mgdwf_status mgdwf_set_coarse_tiling(mgdwf_handle h, int32_t id) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(id >= -1 && id <= 1, MGDWF_ERR_INVALID_ARG, "coarse tiling id must be -1, 0 or 1");
+    h->g.ctile = id < 0 ? 0 : id;
   });
 }
 

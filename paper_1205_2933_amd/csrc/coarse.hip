@@ -285,6 +285,88 @@ __global__ __launch_bounds__(576) void k_capply_mfma(const uint16_t* __restrict_
   }
 }
 
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+
+template <bool BF>
+__device__ __forceinline__ f4v mfma32(uint4 a, uint4 b, f4v c) {
+  if (BF) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8v, a), __builtin_bit_cast(b8v, b), c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8v, a), __builtin_bit_cast(h8v, b), c, 0, 0, 0);
+}
+
+// k_capply_mfma on the 16x16x32 tiles of gfx950: a lane holds eight
+// consecutive k of its A row and of its B column (16-byte loads), so each
+// direction takes half the MFMA instructions and half the loads.  Whatever
+// order the hardware gives the 32 k-slots, A's and B's slot (lane group,
+// element) hold the same k, so the tile sum is the full contraction.  Needs
+// 2 n2 divisible by 32 (n2 by 16, as for every 16-bit store).
+template <bool BF>
+__global__ __launch_bounds__(576) void k_capply_mfma32(const uint16_t* __restrict__ Are,
+                                                       const uint16_t* __restrict__ Aim,
+                                                       const float* __restrict__ Asc, const uint16_t* __restrict__ xp,
+                                                       const float* __restrict__ xs, float2* __restrict__ y,
+                                                       CoarseArgs a, int nrhs) {
+  constexpr int MTMAX = 8;  // 2 n2 / 16 <= 8
+  constexpr int KTMAX = 4;  // 2 n2 / 32 <= 4
+  __shared__ float red[128][17];
+  const int X = blockIdx.x;
+  const int rhs0 = blockIdx.y * 16;
+  const int n2 = a.n2;
+  const int MT = 2 * n2 / 16, KT = 2 * n2 / 32;
+  const int d = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int col = l & 15, kq = l >> 4;
+  const int rhs = rhs0 + col;
+  const bool valid = rhs < nrhs;
+  const int Y = coarse_neighbour(a, X, d);
+  const long long blk = (long long)X * 9 + d;
+  uint4 bf[KTMAX];
+  const uint16_t* xrow = xp + ((long long)(valid ? rhs : 0) * a.Vc + Y) * 2 * n2;
+#pragma unroll
+  for (int kt = 0; kt < KTMAX; ++kt)
+    bf[kt] = (kt < KT && valid) ? *reinterpret_cast<const uint4*>(xrow + kt * 32 + 8 * kq) : make_uint4(0u, 0u, 0u, 0u);
+  f4v t[MTMAX];
+#pragma unroll
+  for (int m = 0; m < MTMAX; ++m) t[m] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int mt = 0; mt < MTMAX; ++mt) {
+    if (mt >= MT) continue;
+    const int i = mt * 16 + (l & 15);           // expanded row
+    const bool im_row = i >= n2;
+    const int rr = im_row ? i - n2 : i;
+#pragma unroll
+    for (int kt = 0; kt < KTMAX; ++kt) {
+      if (kt >= KT) continue;
+      const int k = kt * 32 + 8 * kq;             // expanded column of this lane's 8 values
+      const bool im_col = k >= n2;                // n2 % 8 == 0: the 8 stay on one side
+      const int kk = im_col ? k - n2 : k;
+      const uint16_t* src = (im_row != im_col) ? Aim : Are;
+      uint4 av = *reinterpret_cast<const uint4*>(src + blk * n2 * n2 + (long long)rr * n2 + kk);
+      if (!im_row && im_col) {  // -Im in the upper right
+        av.x ^= 0x80008000u; av.y ^= 0x80008000u; av.z ^= 0x80008000u; av.w ^= 0x80008000u;
+      }
+      t[mt] = mfma32<BF>(av, bf[kt], t[mt]);
+    }
+  }
+  const float s = Asc[blk] * (valid ? xs[(long long)rhs * a.Vc + Y] : 0.f);
+  for (int w = 0; w < 9; ++w) {
+    if (d == w) {
+#pragma unroll
+      for (int mt = 0; mt < MTMAX; ++mt)
+        if (mt < MT)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            float& r = red[mt * 16 + 4 * kq + j][col];
+            r = (w == 0 ? 0.f : r) + s * t[mt][j];
+          }
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < 16 * n2; i += blockDim.x) {
+    const int r = i % n2, cl = i / n2;
+    if (rhs0 + cl < nrhs) y[((long long)(rhs0 + cl) * a.Vc + X) * n2 + r] = make_float2(red[r][cl], red[n2 + r][cl]);
+  }
+}
+
 }  // namespace
 
 // Build the FP64 coarse operator.  Vhat: orthonormal basis (Nv FP64 fields);
@@ -348,7 +430,7 @@ size_t coarse_pack_bytes(const CoarseGeometry& cg, int nrhs) {
 }
 
 void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, float2* y, const CoarseGeometry& cg,
-                    int nrhs, void* pack, hipStream_t st) {
+                    int nrhs, void* pack, int ctile, hipStream_t st) {
   if (cg.n2 > 64) fail(MGDWF_ERR_INVALID_ARG, "2*nvec above 64 is not supported");
   if (prec == MGDWF_F32 || prec == MGDWF_F64) {
     for (int r0 = 0; r0 < nrhs; r0 += 16) {
@@ -367,6 +449,16 @@ void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, floa
   else hipLaunchKernelGGL(k_pack_vec<false>, dim3(ceil_div(nsv, 4)), dim3(256), 0, st, x, xp, xs, cg.Vc, cg.n2, nrhs);
   MG_LAUNCH_CHECK();
   dim3 grid(cg.Vc, ceil_div(nrhs, 16));
+  if (ctile == 1) {  // 16x16x32 tiles
+    if (bf)
+      hipLaunchKernelGGL(k_capply_mfma32<true>, grid, dim3(576), 0, st, s.reb.as<uint16_t>(), s.imb.as<uint16_t>(),
+                         s.scb.as<float>(), xp, xs, y, coarse_args(cg), nrhs);
+    else
+      hipLaunchKernelGGL(k_capply_mfma32<false>, grid, dim3(576), 0, st, s.re16.as<uint16_t>(),
+                         s.im16.as<uint16_t>(), s.sc16.as<float>(), xp, xs, y, coarse_args(cg), nrhs);
+    MG_LAUNCH_CHECK();
+    return;
+  }
   if (bf)
     hipLaunchKernelGGL(k_capply_mfma<true>, grid, dim3(576), 0, st, s.reb.as<uint16_t>(), s.imb.as<uint16_t>(),
                        s.scb.as<float>(), xp, xs, y, coarse_args(cg), nrhs);

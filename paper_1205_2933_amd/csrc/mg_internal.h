@@ -36,6 +36,7 @@ struct Geometry {
   int V5;        // V4 * Ls
   int bc[4];     // +1 periodic, -1 antiperiodic in direction mu
   int ftile = -1;  // FP32 Dslash tiling (index into its table; -1: the default)
+  int ctile = 0;   // 16-bit coarse apply MFMA shape (0: 16x16x16, 1: 16x16x32)
 };
 
 struct CoarseGeometry {

@@ -98,7 +98,7 @@ inline void coarse_op(mgdwf_ctx* c, const mgdwf_mg_params&, const double2* x, do
 }
 inline void coarse_op(mgdwf_ctx* c, const mgdwf_mg_params& p, const float2* x, float2* y, bool dag, int nrhs) {
   coarse_apply32(dag ? c->DcH : c->Dc, p.coarse_prec, x, y, c->cg, nrhs,
-                 c->buf<char>("vc_pack", coarse_pack_bytes(c->cg, nrhs)), c->st);
+                 c->buf<char>("vc_pack", coarse_pack_bytes(c->cg, nrhs)), c->g.ctile, c->st);
   c->coarse_applies += 1;
 }
 

@@ -71,7 +71,8 @@ void finish_coarse_op(CoarseStore& Dc, CoarseStore& DcH, const CoarseGeometry& c
 void coarse_apply64(const CoarseStore& s, const double2* x, double2* y, const CoarseGeometry& cg, int nrhs,
                     hipStream_t st);
 size_t coarse_pack_bytes(const CoarseGeometry& cg, int nrhs);
+// ctile: MFMA shape of the 16-bit apply, 0 = 16x16x16, 1 = 16x16x32
 void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, float2* y, const CoarseGeometry& cg,
-                    int nrhs, void* pack, hipStream_t st);
+                    int nrhs, void* pack, int ctile, hipStream_t st);
 
 }  // namespace mgdwf

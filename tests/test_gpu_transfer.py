@@ -147,15 +147,19 @@ def test_coarse_operator_matches_oracle(cuda, case):
     assert rel(Dc.cpu().numpy(), ref) < 1e-13
     # apply, both directions, FP64 and FP32
     c = np.random.default_rng(3).standard_normal(Lc[::-1] + (2, nvec)) + 1j * np.random.default_rng(4).standard_normal(Lc[::-1] + (2, nvec))
-    precs = [("f64", 1e-13), ("f32", 2e-6)]
-    if nvec % 8 == 0:
-        precs += [(p, LOWP_TOL[p]) for p in ("f16", "bf16")]
+    precs = [("f64", 1e-13, 0), ("f32", 2e-6, 0)]
+    if nvec % 8 == 0:  # both MFMA shapes of the 16-bit apply
+        precs += [(p, LOWP_TOL[p], ct) for p in ("f16", "bf16") for ct in (0, 1)]
     for dagger in (False, True):
-        for prec, tol in precs:
+        for prec, tol, ct in precs:
+            mg.mgdwf_set_coarse_tiling(h, ct)
             y = torch.empty_like(dev(c))
             mg.mgdwf_apply_coarse(h, dev(c), y, dagger=dagger, prec=prec)
             torch.cuda.synchronize()
-            assert rel(y.cpu().numpy(), oc.apply_coarse(c, ref, dagger=dagger)) < tol, (dagger, prec)
+            assert rel(y.cpu().numpy(), oc.apply_coarse(c, ref, dagger=dagger)) < tol, (dagger, prec, ct)
+    mg.mgdwf_set_coarse_tiling(h, -1)
+    with pytest.raises(mg.MgdwfError):
+        mg.mgdwf_set_coarse_tiling(h, 2)
 
 
 def test_coarse_apply_many_rhs(cuda):
@@ -173,10 +177,17 @@ def test_coarse_apply_many_rhs(cuda):
     c[5] *= 1e-6   # a small RHS next to O(1) ones: the per-(site, RHS) scale keeps it accurate
     for dagger in (False, True):
         want = np.stack([oc.apply_coarse(c[r], ref, dagger=dagger) for r in range(nr)])
-        for prec, tol in (("f64", 1e-13), ("f32", 2e-6), ("f16", LOWP_TOL["f16"]), ("bf16", LOWP_TOL["bf16"])):
+        for prec, tol, ct in (("f64", 1e-13, 0), ("f32", 2e-6, 0), ("f16", LOWP_TOL["f16"], 0),
+                              ("bf16", LOWP_TOL["bf16"], 0), ("f16", LOWP_TOL["f16"], 1),
+                              ("bf16", LOWP_TOL["bf16"], 1)):
+            mg.mgdwf_set_coarse_tiling(h, ct)
             y = torch.empty_like(dev(c))
             mg.mgdwf_apply_coarse(h, dev(c), y, dagger=dagger, prec=prec, nrhs=nr)
             torch.cuda.synchronize()
             got = y.cpu().numpy()
             for r in range(nr):
-                assert rel(got[r], want[r]) < tol, (dagger, prec, r)
+                assert rel(got[r], want[r]) < tol, (dagger, prec, ct, r)
+    # the tuner times both shapes once a coarse operator exists
+    rep = mg.mgdwf_tune(h, nrhs=nr, iters=2)
+    assert rep["coarse_chosen"] in (0, 1) and len(rep["coarse_us"]) == 2
+    assert rep["coarse_chosen"] == 0 or rep["coarse_us"][1] <= 0.97 * rep["coarse_us"][0]
