@@ -165,10 +165,10 @@ struct TwoLevel {
   void cg_iteration(F2* x, int it, int cur, int nxt) {
     coarse_op(c, p, cp, cq, false, nrhs);
     mr_update<F2>(x, cr, cp, cq, nc, nrhs, sl, cur, S_CPP, it == 0, vpart, c->st);
-    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, nxt, nrhs, c->st);
+    finalize_rhs(vpart, vec_blocks(nc), 1, sl, nxt, nrhs, c->st);
     coarse_op(c, p, cr, ct, true, nrhs);
     cg_dir<F2>(cp, ct, nc, nrhs, sl, nxt, cur, vpart, c->st);
-    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, S_CPP, nrhs, c->st);
+    finalize_rhs(vpart, vec_blocks(nc), 1, sl, S_CPP, nrhs, c->st);
   }
 
   hipGraphExec_t block_graph(F2* x) {
@@ -293,7 +293,7 @@ int fgcr_cycle(mgdwf_ctx* c, TwoLevel<F2>& M, F2* r, F2* e, int nrhs, int kmax, 
     }
     if (k == 0) norm_into<F2>(c, Q[k], r, nf, nrhs, S_QN + k);  // |q_0|^2, <q_0, r>
     gcr_update<F2>(e, r, Z[k], Q[k], nf, nrhs, sl, S_QN + k + 1, S_QN + k, k == 0, vpart, c->st);
-    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, S_RIN, nrhs, c->st);
+    finalize_rhs(vpart, vec_blocks(nf), 1, sl, S_RIN, nrhs, c->st);
     std::vector<double> h = read_slots(c, nrhs);
     bool done = true;
     for (int rr = 0; rr < nrhs; ++rr) {
@@ -410,7 +410,7 @@ static void cgnr_null(mgdwf_ctx* c, double2* x, int nrhs, int iters) {
     fine_op<double2>(c, p, t, nullptr, false, 0, nrhs, S_GPAP);  // t = D p, <p, D^+D p> = |t|^2
     fine_op<double2>(c, t, Ap, nullptr, true, 0, nrhs, -1);
     mr_update<double2>(x, r, p, Ap, nf, nrhs, sl, cur, S_GPAP, false, vpart, c->st);
-    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, nxt, nrhs, c->st);
+    finalize_rhs(vpart, vec_blocks(nf), 1, sl, nxt, nrhs, c->st);
     cg_dir<double2>(p, r, nf, nrhs, sl, nxt, cur, nullptr, c->st);
     std::swap(cur, nxt);
   }
@@ -515,11 +515,11 @@ void cgne_solve(mgdwf_ctx* c, double2* b, double2* x, const mgdwf_solve_params& 
   while (it < sp.max_outer && rel >= sp.tol) {
     fine_op<double2>(c, p, q, nullptr, false, 0, 1, -1);      // q = D p
     mr_update<double2>(x, r, p, q, nf, 1, sl, cur, S_GPAP, false, vpart, c->st);
-    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, nxt, 1, c->st);
+    finalize_rhs(vpart, vec_blocks(nf), 1, sl, nxt, 1, c->st);
     double2* t = c->buf<double2>("cg_ap", nf);
     fine_op<double2>(c, r, t, nullptr, true, 0, 1, -1);       // t = D^+ r
     cg_dir<double2>(p, t, nf, 1, sl, nxt, cur, vpart, c->st);
-    finalize_rhs(vpart, VEC_BLOCKS, 1, sl, S_GPAP, 1, c->st);
+    finalize_rhs(vpart, vec_blocks(nf), 1, sl, S_GPAP, 1, c->st);
     std::swap(cur, nxt);
     ++it;
     if (it % check == 0) {

@@ -6,7 +6,9 @@
 namespace mgdwf {
 
 constexpr int NSLOT = 128;       // scalar slots per right-hand side
-constexpr int VEC_BLOCKS = 1024; // workgroups of the grid-stride vector kernels (partials per RHS)
+constexpr int VEC_BLOCKS = 1024; // most workgroups of a grid-stride vector kernel (partials per RHS)
+// workgroups (and partial sums per RHS) of a vector kernel over n elements
+int vec_blocks(long long n);
 
 void finalize_rhs(const double* partial, int nparts, int ncomp, double* sl, int dst, int nrhs, hipStream_t st);
 

@@ -263,9 +263,9 @@ __global__ void k_reflect5(const C2* __restrict__ in, C2* __restrict__ out, long
   }
 }
 
-int grid_for(long long n) { return std::max(1, std::min(ceil_div(n, 256), VEC_BLOCKS)); }
-
 }  // namespace
+
+int vec_blocks(long long n) { return std::max(1, std::min(ceil_div(n, 256), VEC_BLOCKS)); }
 
 void finalize_rhs(const double* partial, int nparts, int ncomp, double* sl, int dst, int nrhs, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize_rhs, dim3(ncomp, nrhs), dim3(256), 0, st, partial, nparts, ncomp, sl, dst);
@@ -275,7 +275,7 @@ void finalize_rhs(const double* partial, int nparts, int ncomp, double* sl, int 
 template <class C2>
 void mr_update(C2* x, C2* r, const C2* p, const C2* q, long long n, int nrhs, const double* sl, int num, int den,
                bool first, double* partial, hipStream_t st) {
-  hipLaunchKernelGGL(k_mr_update<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, x, r, p, q, n, sl, num, den,
+  hipLaunchKernelGGL(k_mr_update<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, x, r, p, q, n, sl, num, den,
                      first ? 1 : 0, partial);
   MG_LAUNCH_CHECK();
 }
@@ -283,7 +283,7 @@ void mr_update(C2* x, C2* r, const C2* p, const C2* q, long long n, int nrhs, co
 template <class C2>
 void res_update(C2* rout, const C2* rin, const C2* q, long long n, int nrhs, const double* sl, int num, int den,
                 hipStream_t st) {
-  hipLaunchKernelGGL(k_res_update<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, rout, rin, q, n, sl, num, den);
+  hipLaunchKernelGGL(k_res_update<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, rout, rin, q, n, sl, num, den);
   MG_LAUNCH_CHECK();
 }
 
@@ -291,14 +291,14 @@ template <class C2>
 void lincomb(C2* x, const C2* const* ps, int nv, long long n, int nrhs, const double* sl, int num, bool acc,
              hipStream_t st) {
   if (nv > 16) fail(MGDWF_ERR_INVALID_ARG, "at most 16 smoother steps");
-  hipLaunchKernelGGL(k_lincomb<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, x, ps, nv, n, sl, num, acc ? 1 : 0);
+  hipLaunchKernelGGL(k_lincomb<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, x, ps, nv, n, sl, num, acc ? 1 : 0);
   MG_LAUNCH_CHECK();
 }
 
 template <class C2>
 void cg_dir(C2* p, const C2* r, long long n, int nrhs, const double* sl, int num, int den, double* partial,
             hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_dir<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, p, r, n, sl, num, den, partial);
+  hipLaunchKernelGGL(k_cg_dir<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, p, r, n, sl, num, den, partial);
   MG_LAUNCH_CHECK();
 }
 
@@ -306,54 +306,54 @@ template <class C2>
 void multidot_rhs(const C2* const* avec, int nv, const C2* b, const C2* c, long long n, int nrhs, double* partial,
                   double* sl, int dst, hipStream_t st) {
   if (nv > 16) fail(MGDWF_ERR_INVALID_ARG, "at most 16 Krylov vectors per restart");
-  hipLaunchKernelGGL(k_multidot<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, avec, nv, b, c, n, partial);
+  hipLaunchKernelGGL(k_multidot<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, avec, nv, b, c, n, partial);
   MG_LAUNCH_CHECK();
-  finalize_rhs(partial, VEC_BLOCKS, 2 * nv + 3, sl, dst, nrhs, st);
+  finalize_rhs(partial, vec_blocks(n), 2 * nv + 3, sl, dst, nrhs, st);
 }
 
 template <class C2>
 void orth_update(C2* q, C2* z, const C2* const* qs, const C2* const* zs, int nv, long long n, int nrhs,
                  const double* sl, int dots, int nrm, hipStream_t st) {
   if (nv == 0) return;
-  hipLaunchKernelGGL(k_orth_update<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, q, z, qs, zs, nv, n, sl, dots, nrm);
+  hipLaunchKernelGGL(k_orth_update<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, q, z, qs, zs, nv, n, sl, dots, nrm);
   MG_LAUNCH_CHECK();
 }
 
 template <class C2>
 void gcr_update(C2* e, C2* r, const C2* z, const C2* q, long long n, int nrhs, const double* sl, int cr, int nq,
                 bool first, double* partial, hipStream_t st) {
-  hipLaunchKernelGGL(k_gcr_update<C2>, dim3(VEC_BLOCKS, nrhs), dim3(256), 0, st, e, r, z, q, n, sl, cr, nq,
+  hipLaunchKernelGGL(k_gcr_update<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, e, r, z, q, n, sl, cr, nq,
                      first ? 1 : 0, partial);
   MG_LAUNCH_CHECK();
 }
 
 template <class C2>
 void scale_by_rsqrt_slot(C2* y, const C2* x, long long n, int nrhs, const double* sl, int den, hipStream_t st) {
-  hipLaunchKernelGGL(k_scale_slot<C2>, dim3(grid_for(n), nrhs), dim3(256), 0, st, y, x, n, sl, den);
+  hipLaunchKernelGGL(k_scale_slot<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, y, x, n, sl, den);
   MG_LAUNCH_CHECK();
 }
 
 template <class A2, class B2>
 void convert(const A2* in, B2* out, long long n, hipStream_t st) {
-  hipLaunchKernelGGL((k_convert<A2, B2>), dim3(grid_for(n)), dim3(256), 0, st, in, out, n);
+  hipLaunchKernelGGL((k_convert<A2, B2>), dim3(vec_blocks(n)), dim3(256), 0, st, in, out, n);
   MG_LAUNCH_CHECK();
 }
 
 template <class A2, class B2>
 void add_to(B2* y, const A2* x, long long n, hipStream_t st) {
-  hipLaunchKernelGGL((k_add_to<A2, B2>), dim3(grid_for(n)), dim3(256), 0, st, y, x, n);
+  hipLaunchKernelGGL((k_add_to<A2, B2>), dim3(vec_blocks(n)), dim3(256), 0, st, y, x, n);
   MG_LAUNCH_CHECK();
 }
 
 template <class C2>
 void zero(C2* y, long long n, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero<C2>, dim3(grid_for(n)), dim3(256), 0, st, y, n);
+  hipLaunchKernelGGL(k_zero<C2>, dim3(vec_blocks(n)), dim3(256), 0, st, y, n);
   MG_LAUNCH_CHECK();
 }
 
 template <class C2>
 void reflect5(const C2* in, C2* out, const Geometry& g, int nf, hipStream_t st) {
-  hipLaunchKernelGGL(k_reflect5<C2>, dim3(grid_for(12LL * g.V5 * nf)), dim3(256), 0, st, in, out, (long long)g.V5,
+  hipLaunchKernelGGL(k_reflect5<C2>, dim3(vec_blocks(12LL * g.V5 * nf)), dim3(256), 0, st, in, out, (long long)g.V5,
                      g.Ls, (long long)nf);
   MG_LAUNCH_CHECK();
 }
