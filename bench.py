@@ -123,10 +123,10 @@ def cpu_baseline(counts):
 
 
 def ragged_leg(mg, h_main, B_main, log):
-    """44 solves over three lattices of uneven size in one mgdwf_solve_batch
-    call: 8^4 x 8 and 12^3 x 24 x 12 with 16 RHS each (12 point sources + 4
-    Gaussian), and the main 16^3 x 32 x 16 lattice with its 12 point sources;
-    mixed precision, tol 1e-10."""
+    """48 solves over three lattices of uneven size in one mgdwf_solve_batch
+    call: 8^4 x 8 with 20 RHS (12 point sources + 8 Gaussian), 12^3 x 24 x 12
+    with 16 (12 + 4), and the main 16^3 x 32 x 16 lattice with its 12 point
+    sources; mixed precision, tol 1e-10."""
     import numpy as np
     import torch
 
@@ -136,16 +136,16 @@ def ragged_leg(mg, h_main, B_main, log):
     # Ls = 12 needs a longer sweep 0: after 400 CG iterations the outer solve
     # stagnates near 5e-4, after 1000 the 16-RHS solve still misses 1e-10 in 400
     # outer iterations, after 2000 it converges in 56
-    for L, Ls, seed, sweep0 in [((8, 8, 8, 8), 8, 14, 400), ((12, 12, 12, 24), 12, 15, 2000)]:
+    for L, Ls, seed, sweep0, ng in [((8, 8, 8, 8), 8, 14, 400, 8), ((12, 12, 12, 24), 12, 15, 2000, 4)]:
         U = prepare_gauge(L, 0.3, seed, ape_steps=2)
         h = mg.Handle(L, Ls, M5, MF, stream=torch.cuda.Stream())
         mg.mgdwf_set_gauge(h, torch.from_numpy(U).cuda())
         p_setup = mg_params(mg, "f64", "f64")
         p_setup.sweep0_iters = sweep0
         mg.mgdwf_setup(h, p_setup, torch.from_numpy(random_starts(L, Ls, NVEC // 2, 21)).cuda())
-        mg.mgdwf_tune(h, nrhs=16, iters=5)
+        mg.mgdwf_tune(h, nrhs=12 + ng, iters=5)
         mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f16"))
-        b = np.concatenate([point_sources(L, Ls), gaussian_fermion(L, Ls, 33, n=4)])
+        b = np.concatenate([point_sources(L, Ls), gaussian_fermion(L, Ls, 33, n=ng)])
         hs.append(h)
         bs.append(torch.from_numpy(b).cuda())
         mem(f"ragged, lattice {L} ready")
@@ -155,7 +155,7 @@ def ragged_leg(mg, h_main, B_main, log):
     hs.append(h_main)
     bs.append(B_main)
     xs = [torch.zeros_like(b) for b in bs]
-    nrhs = [16, 16, 12]
+    nrhs = [20, 16, 12]
     torch.cuda.empty_cache()
     torch.cuda.synchronize()
     mem("ragged, before the batch")
@@ -176,7 +176,7 @@ def ragged_leg(mg, h_main, B_main, log):
     out = {"solves": int(sum(nrhs)), "wall_s": wall, "solves_per_s": sum(nrhs) / wall,
            "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
            "outer_iters": [max(r["outer_iters"] for r in rs) for rs in reps], "max_true_relres": res,
-           "lattices": ["8^4x8 (16 RHS)", "12^3x24x12 (16 RHS, sweep 0 of 2000 iterations)", "16^3x32x16 (12 RHS)"]}
+           "lattices": ["8^4x8 (20 RHS)", "12^3x24x12 (16 RHS, sweep 0 of 2000 iterations)", "16^3x32x16 (12 RHS)"]}
     log(f"ragged batch {out}")
     assert max(res) < 1e-10, res
     return out

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <vector>
 
@@ -258,9 +259,18 @@ struct TwoLevel {
 // ---------------------------------------------------------------- FGCR cycle
 // Up to `kmax` flexible GCR steps on D e = r (inner precision F2), e from 0.
 // Stops early when every |r|^2 <= stop2[rhs].  Returns the steps taken.
+//
+// Only q is orthogonalised on the device.  The search directions follow as
+// z~_k = z_k - sum_{i<k} g_ki z~_i with the Gram-Schmidt coefficients g_ki,
+// and e = sum_k b_k z~_k with b_k = <q_k, r> / |q_k|^2; the host keeps the
+// g and b it reads from the slot table anyway, and e is formed once at the
+// end as sum_j c_j z_j over the unmodified z_j (c = T b, T the unit upper
+// triangular map from z to z~).  Same iterates as updating z~ and e in place,
+// without streaming z and e through every step.
 template <class F2>
 int fgcr_cycle(mgdwf_ctx* c, TwoLevel<F2>& M, F2* r, F2* e, int nrhs, int kmax, const std::vector<double>& stop2,
                std::vector<double>* rin2_out) {
+  using cd = std::complex<double>;
   const long long nf = c->fine_len();
   const std::string t = Prec<F2>::tag;
   std::vector<F2*> Z(kmax), Q(kmax);
@@ -272,32 +282,49 @@ int fgcr_cycle(mgdwf_ctx* c, TwoLevel<F2>& M, F2* r, F2* e, int nrhs, int kmax, 
   const F2* const* Qd = ptr_table<F2>(c, "ptrQ" + t, Q);
   double* sl = c->buf<double>("slots", (size_t)nrhs * NSLOT);
   double* vpart = c->buf<double>("vpart", (size_t)VEC_BLOCKS * nrhs * (2 * 16 + 3));
+  // g[rhs][k][i] and b[rhs][k]
+  std::vector<cd> g((size_t)nrhs * kmax * kmax, cd(0.0, 0.0)), bk((size_t)nrhs * kmax, cd(0.0, 0.0));
+  auto take_g = [&](const std::vector<double>& h, int k) {  // coefficients of the pass just run
+    for (int rr = 0; rr < nrhs; ++rr) {
+      const double* hs = h.data() + (size_t)rr * NSLOT;
+      for (int i = 0; i < k; ++i) {
+        const double d = hs[S_QN + i];
+        const double inv = d > 0.0 ? 1.0 / d : 0.0;
+        g[((size_t)rr * kmax + k) * kmax + i] += cd(hs[S_DOT + 2 * i] * inv, hs[S_DOT + 2 * i + 1] * inv);
+      }
+    }
+  };
   int k = 0;
   for (; k < kmax; ++k) {
     M.apply(r, Z[k]);                                           // z = M r
     fine_op<F2>(c, Z[k], Q[k], nullptr, false, 0, nrhs, -1);    // q = D z
-    // classical Gram-Schmidt against q_0..q_{k-1} (z follows q); a second pass
-    // only where the first cancelled most of q (|q| fell below 1/sqrt 2 of
-    // its norm before the pass), the usual twice-is-enough criterion
+    // classical Gram-Schmidt of q against q_0..q_{k-1}; a second pass only
+    // where the first cancelled most of q (|q| fell below 1/sqrt 2 of its
+    // norm before the pass), the usual twice-is-enough criterion
     for (int pass = 0; pass < 2 && k > 0; ++pass) {
       multidot_rhs<F2>(Qd, k, Q[k], nullptr, nf, nrhs, vpart, sl, S_DOT, c->st);  // |q|^2 before at S_DOT + 2k
-      orth_update<F2>(Q[k], Z[k], Qd, Zd, k, nf, nrhs, sl, S_DOT, S_QN, c->st);
+      orth_update<F2>(Q[k], nullptr, Qd, nullptr, k, nf, nrhs, sl, S_DOT, S_QN, c->st);
       norm_into<F2>(c, Q[k], r, nf, nrhs, S_QN + k);            // |q_k|^2, <q_k, r>
+      std::vector<double> h = read_slots(c, nrhs);
+      take_g(h, k);
       if (pass == 1) break;
-      std::vector<double> g = read_slots(c, nrhs);
       bool again = false;
       for (int rr = 0; rr < nrhs; ++rr)
-        if (!(g[rr * NSLOT + S_QN + k] >= 0.5 * g[rr * NSLOT + S_DOT + 2 * k])) again = true;
+        if (!(h[rr * NSLOT + S_QN + k] >= 0.5 * h[rr * NSLOT + S_DOT + 2 * k])) again = true;
       if (!again) break;
       ++c->gs_repeats;
     }
     if (k == 0) norm_into<F2>(c, Q[k], r, nf, nrhs, S_QN + k);  // |q_0|^2, <q_0, r>
-    gcr_update<F2>(e, r, Z[k], Q[k], nf, nrhs, sl, S_QN + k + 1, S_QN + k, k == 0, vpart, c->st);
+    gcr_update<F2>(nullptr, r, nullptr, Q[k], nf, nrhs, sl, S_QN + k + 1, S_QN + k, false, vpart, c->st);
     finalize_rhs(vpart, vec_blocks(nf), 1, sl, S_RIN, nrhs, c->st);
     std::vector<double> h = read_slots(c, nrhs);
     bool done = true;
     for (int rr = 0; rr < nrhs; ++rr) {
-      double v = h[rr * NSLOT + S_RIN];
+      const double* hs = h.data() + (size_t)rr * NSLOT;
+      const double d = hs[S_QN + k];
+      const double inv = d > 0.0 ? 1.0 / d : 0.0;
+      bk[(size_t)rr * kmax + k] = cd(hs[S_QN + k + 1] * inv, hs[S_QN + k + 2] * inv);
+      double v = hs[S_RIN];
       if (!std::isfinite(v)) fail(MGDWF_ERR_NUMERIC, "non-finite residual in flexible GCR");
       if (!(v <= stop2[rr])) done = false;
     }
@@ -307,6 +334,29 @@ int fgcr_cycle(mgdwf_ctx* c, TwoLevel<F2>& M, F2* r, F2* e, int nrhs, int kmax, 
     }
     if (done) { ++k; break; }
   }
+  // e = sum_j c_j z_j, c = T b with z~_k = sum_j T[j][k] z_j
+  std::vector<double2> coef((size_t)nrhs * 16, make_double2(0.0, 0.0));
+  std::vector<cd> T((size_t)k * k);
+  for (int rr = 0; rr < nrhs; ++rr) {
+    std::fill(T.begin(), T.end(), cd(0.0, 0.0));
+    for (int kk = 0; kk < k; ++kk) {
+      T[(size_t)kk * k + kk] = 1.0;
+      for (int j = 0; j < kk; ++j) {
+        cd acc = 0.0;
+        for (int i = j; i < kk; ++i) acc += g[((size_t)rr * kmax + kk) * kmax + i] * T[(size_t)j * k + i];
+        T[(size_t)j * k + kk] = -acc;
+      }
+    }
+    for (int j = 0; j < k; ++j) {
+      cd cj = 0.0;
+      for (int kk = j; kk < k; ++kk) cj += T[(size_t)j * k + kk] * bk[(size_t)rr * kmax + kk];
+      coef[(size_t)rr * 16 + j] = make_double2(cj.real(), cj.imag());
+    }
+  }
+  double2* coef_d = c->buf<double2>("gcr_coef", (size_t)nrhs * 16);
+  MG_HIP(hipMemcpyAsync(coef_d, coef.data(), coef.size() * sizeof(double2), hipMemcpyHostToDevice, c->st));
+  lincomb_c<F2>(e, Zd, k, nf, nrhs, coef_d, c->st);
+  MG_HIP(hipStreamSynchronize(c->st));  // the host coefficient buffer goes out of scope
   return k;
 }
 

@@ -30,6 +30,10 @@ void multidot_rhs(const C2* const* avec, int nv, const C2* b, const C2* c, long 
 template <class C2>
 void orth_update(C2* q, C2* z, const C2* const* qs, const C2* const* zs, int nv, long long n, int nrhs,
                  const double* sl, int dots, int nrm, hipStream_t st);
+// x = sum_m coef[rhs * 16 + m] p_m, complex FP64 coefficients on the device
+template <class C2>
+void lincomb_c(C2* x, const C2* const* ps, int nv, long long n, int nrhs, const double2* coef, hipStream_t st);
+// z and zs may be null (q alone is orthogonalised); e may be null (r alone moves)
 template <class C2>
 void gcr_update(C2* e, C2* r, const C2* z, const C2* q, long long n, int nrhs, const double* sl, int cr, int nq,
                 bool first, double* partial, hipStream_t st);

@@ -173,17 +173,18 @@ __global__ __launch_bounds__(256) void k_orth_update(C2* __restrict__ q, C2* __r
     } else { br[m] = 0; bi[m] = 0; }
   }
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    C2 qv = q[off + i], zv = z[off + i];
+    C2 qv = q[off + i];
 #pragma unroll
-    for (int m = 0; m < MAXV; ++m) {
-      if (m < nv) {
-        C2 beta = cmk<C2>(br[m], bi[m]);
-        qv = csub(qv, cmul(beta, qs[m][off + i]));
-        zv = csub(zv, cmul(beta, zs[m][off + i]));
-      }
-    }
+    for (int m = 0; m < MAXV; ++m)
+      if (m < nv) qv = csub(qv, cmul(cmk<C2>(br[m], bi[m]), qs[m][off + i]));
     q[off + i] = qv;
-    z[off + i] = zv;
+    if (z) {  // z follows q unless the caller keeps the coefficients instead
+      C2 zv = z[off + i];
+#pragma unroll
+      for (int m = 0; m < MAXV; ++m)
+        if (m < nv) zv = csub(zv, cmul(cmk<C2>(br[m], bi[m]), zs[m][off + i]));
+      z[off + i] = zv;
+    }
   }
 }
 
@@ -200,8 +201,10 @@ __global__ __launch_bounds__(256) void k_gcr_update(C2* __restrict__ e, C2* __re
   const C2 alpha = cmk<C2>((T)(slot(sl, rhs, cr_) * inv), (T)(slot(sl, rhs, cr_ + 1) * inv));
   double nr = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    C2 ev = first ? cmk<C2>(0, 0) : e[off + i];
-    e[off + i] = cadd(ev, cmul(alpha, z[off + i]));
+    if (e) {  // without e only the residual moves
+      C2 ev = first ? cmk<C2>(0, 0) : e[off + i];
+      e[off + i] = cadd(ev, cmul(alpha, z[off + i]));
+    }
     C2 rv = csub(r[off + i], cmul(alpha, q[off + i]));
     r[off + i] = rv;
     nr += (double)rv.x * rv.x + (double)rv.y * rv.y;
@@ -209,6 +212,29 @@ __global__ __launch_bounds__(256) void k_gcr_update(C2* __restrict__ e, C2* __re
   if (partial) {
     double s = block_sum<256>(nr);
     if (threadIdx.x == 0) partial[(long long)rhs * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// x = sum_m c[rhs][m] p_m with complex coefficients c (FP64, [rhs][16]), m < nv
+template <class C2>
+__global__ __launch_bounds__(256) void k_lincomb_c(C2* __restrict__ x, const C2* const* __restrict__ ps, int nv,
+                                                   long long n, const double2* __restrict__ coef) {
+  using T = typename real_of<C2>::type;
+  constexpr int MAXV = 16;
+  const int rhs = blockIdx.y;
+  const long long off = rhs * n;
+  C2 cf[MAXV];
+#pragma unroll
+  for (int m = 0; m < MAXV; ++m) {
+    const double2 v = m < nv ? coef[rhs * MAXV + m] : make_double2(0.0, 0.0);
+    cf[m] = cmk<C2>((T)v.x, (T)v.y);
+  }
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    C2 acc = cmk<C2>(0, 0);
+#pragma unroll
+    for (int m = 0; m < MAXV; ++m)
+      if (m < nv) acc = cadd(acc, cmul(cf[m], ps[m][off + i]));
+    x[off + i] = acc;
   }
 }
 
@@ -320,6 +346,13 @@ void orth_update(C2* q, C2* z, const C2* const* qs, const C2* const* zs, int nv,
 }
 
 template <class C2>
+void lincomb_c(C2* x, const C2* const* ps, int nv, long long n, int nrhs, const double2* coef, hipStream_t st) {
+  if (nv > 16) fail(MGDWF_ERR_INVALID_ARG, "at most 16 Krylov vectors per restart");
+  hipLaunchKernelGGL(k_lincomb_c<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, x, ps, nv, n, coef);
+  MG_LAUNCH_CHECK();
+}
+
+template <class C2>
 void gcr_update(C2* e, C2* r, const C2* z, const C2* q, long long n, int nrhs, const double* sl, int cr, int nq,
                 bool first, double* partial, hipStream_t st) {
   hipLaunchKernelGGL(k_gcr_update<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, e, r, z, q, n, sl, cr, nq,
@@ -363,6 +396,7 @@ void reflect5(const C2* in, C2* out, const Geometry& g, int nf, hipStream_t st) 
                               double*, hipStream_t);                                                             \
   template void cg_dir<C2>(C2*, const C2*, long long, int, const double*, int, int, double*, hipStream_t);      \
   template void res_update<C2>(C2*, const C2*, const C2*, long long, int, const double*, int, int, hipStream_t); \
+  template void lincomb_c<C2>(C2*, const C2* const*, int, long long, int, const double2*, hipStream_t);        \
   template void lincomb<C2>(C2*, const C2* const*, int, long long, int, const double*, int, bool, hipStream_t);        \
   template void multidot_rhs<C2>(const C2* const*, int, const C2*, const C2*, long long, int, double*, double*, \
                                  int, hipStream_t);                                                              \
