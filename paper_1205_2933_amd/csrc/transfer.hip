@@ -391,6 +391,80 @@ __global__ __launch_bounds__(256) void k_prolong_mr(const C2* __restrict__ V, co
   }
 }
 
+// Prolongation for up to RW right-hand sides in one pass over the basis: one
+// thread per fine component (spin-colour c, 5D site), all right-hand sides
+// accumulated in registers, so each basis entry is read once per launch
+// (k_prolong_mr reads the basis once per group of RG right-hand sides).
+// Thread i covers c = i / V5 and i5 = i % V5, the basis layout's own order,
+// so the basis loads and the output stores are unit-stride.  When the
+// wavefront lies in one block and one chirality (64 consecutive 5D sites of
+// one spin-colour component: always so when Ls x block_x is a multiple of 64)
+// its coefficients are wave-uniform and come through scalar loads; otherwise
+// every lane loads its own through the cache.
+template <class C2, class CC2, bool ACC, int RW>
+__global__ __launch_bounds__(256) void k_prolong_wide(const C2* __restrict__ V, const CC2* __restrict__ cvec,
+                                                      C2* __restrict__ out, BlockArgs a, int nrhs) {
+  using T = typename real_of<C2>::type;
+  const long long V5 = a.V5;
+  const long long field = 12 * V5;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= field) return;
+  const int c = (int)(i / V5);
+  const long long i5 = i - (long long)c * V5;
+  const int n2 = 2 * a.Nv;
+  const int cs = coarse_of(a, (int)(i5 / a.Ls));
+  const int chi_off = c < 6 ? 0 : a.Nv;  // spins 0, 1: P+ columns; spins 2, 3: P- columns
+  C2 acc[RW];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) acc[r] = cmk<C2>(0, 0);
+  const long long cstride = (long long)a.Vc * n2;
+  const int cs0 = __builtin_amdgcn_readfirstlane(cs), off0 = __builtin_amdgcn_readfirstlane(chi_off);
+  if (__all(cs == cs0 && chi_off == off0)) {
+    const CC2* cb = cvec + (long long)cs0 * n2 + off0;  // wave-uniform
+    int k = 0;
+    for (; k + 4 <= a.Nv; k += 4) {  // four k at a time: wider scalar loads, more loads in flight
+      C2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = V[(long long)(k + q) * field + i];
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+        if (r < nrhs) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const CC2 w = cb[r * cstride + k + q];
+            cfma(acc[r], v[q], cmk<C2>((T)w.x, (T)w.y));
+          }
+        }
+    }
+    for (; k < a.Nv; ++k) {
+      const C2 v = V[(long long)k * field + i];
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+        if (r < nrhs) {
+          const CC2 w = cb[r * cstride + k];
+          cfma(acc[r], v, cmk<C2>((T)w.x, (T)w.y));
+        }
+    }
+  } else {
+    const CC2* cb = cvec + (long long)cs * n2 + chi_off;
+    for (int k = 0; k < a.Nv; ++k) {
+      const C2 v = V[(long long)k * field + i];
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+        if (r < nrhs) {
+          const CC2 w = cb[r * cstride + k];
+          cfma(acc[r], v, cmk<C2>((T)w.x, (T)w.y));
+        }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RW; ++r)
+    if (r < nrhs) {
+      C2* o = out + (long long)r * field + i;
+      *o = ACC ? cadd(*o, acc[r]) : acc[r];
+    }
+}
+
 // ---------------------------------------------------------------- CholQR
 // Gram matrix of every (block, chirality) panel: G[(B*2 + chi)][i][j] = <v_i, v_j>
 // over the block's sites, all s, the six spin-colour components of chi.
@@ -572,7 +646,14 @@ void prolong_op(const C2* V, const CC2* coarse, C2* fine, bool accumulate, const
   BlockArgs a = make_args(g, cg);
   constexpr bool f64 = sizeof(typename real_of<C2>::type) == 8;
   constexpr int RG = f64 ? 2 : 4;
-  if (nrhs >= 2) {
+  constexpr int RW = f64 ? 8 : 16;
+  if (nrhs > RG && nrhs <= RW) {  // basis read once
+    dim3 grid(ceil_div(12LL * g.V5, 256));
+    if (accumulate)
+      hipLaunchKernelGGL((k_prolong_wide<C2, CC2, true, RW>), grid, dim3(256), 0, st, V, coarse, fine, a, nrhs);
+    else
+      hipLaunchKernelGGL((k_prolong_wide<C2, CC2, false, RW>), grid, dim3(256), 0, st, V, coarse, fine, a, nrhs);
+  } else if (nrhs >= 2) {
     dim3 grid(ceil_div(g.V5, 256), ceil_div(nrhs, RG));
     if (accumulate)
       hipLaunchKernelGGL((k_prolong_mr<C2, CC2, true, RG>), grid, dim3(256), 0, st, V, coarse, fine, a, nrhs);
