@@ -84,3 +84,40 @@ def test_coarse_graph_replay_is_bitwise_eager(cuda, prec, cprec):
     for x1, r1 in out[True]:
         assert torch.equal(x0, x1)
         assert r1 == r0
+
+
+def test_fgcr_iterate_matches_oracle(cuda):
+    """Six FP64 flexible-GCR steps with the two-level V-cycle, on the GPU and in
+    the oracle, from the same basis and right-hand side (paper Sec. 2's
+    five-step cycle, Sec. 3's outer solver): with the coarse CGNE run for a
+    fixed 16 iterations on both sides (a tolerance never met) the two
+    preconditioners are the same map, so the iterates agree up to rounding.
+    Gram-Schmidt is classical on the GPU and modified in the oracle: equal in
+    exact arithmetic."""
+    import paper_1205_2933_amd as mg
+    from oracle import setup as osu
+    L, Ls, mf, block = (4, 4, 4, 4), 8, 0.01, (2, 2, 2, 2)
+    U = prepare_gauge(L, 0.3, 11)
+    A = dwf.DWF(U, 1.8, mf)
+    V = random_starts(L, Ls, 8, 41)
+    prm = osu.MGParams(block=block, nvec=16, nu_pre=4, nu_post=4, smoother="mr_normal", coarse_solver="cgne",
+                       coarse_tol=1e-30, coarse_maxiter=16)
+    omg = osu.MG(A, prm)
+    omg.rebuild(V)
+    b = gaussian_fermion(L, Ls, 31)
+    from oracle import solvers
+    xo, orep = solvers.gcr(A, b, 1e-30, 6, 8, M=omg.preconditioner())
+    assert orep.iters == 6
+    h = mg.Handle(L, Ls, 1.8, mf)
+    mg.mgdwf_set_gauge(h, dev(U))
+    mg.mgdwf_set_nullvecs(h, block, dev(osu.reflect_pairs(V)), 16)
+    mg.mgdwf_build_coarse(h)
+    mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, nu_pre=4, nu_post=4, coarse_tol=1e-30, coarse_maxiter=16,
+                                                fine_prec="f64", coarse_prec="f64"))
+    x = torch.zeros_like(dev(b))
+    reps = mg.mgdwf_solve(h, dev(b), x, tol=1e-30, max_outer=6, restart=8, allow_not_converged=True)
+    assert reps[0]["outer_iters"] == 6
+    xg = x.cpu().numpy()
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-9
+    rg = np.linalg.norm(b - dwf.apply_dwf(xg, U, 1.8, mf)) / np.linalg.norm(b)
+    assert abs(rg - orep.true_relres) < 1e-6 * orep.true_relres
