@@ -434,6 +434,35 @@ def main():
         fp64_iters.append(r["outer_iters"])
         log(f"fp64 solve {j}: {fp64_times[-1]:.2f} s, {r['outer_iters']} iterations")
 
+    # ---- error of each reduced-precision result against FP64 (the FP64 path
+    # is the one parity-tested against the oracle at 1e-13)
+    x0_mixed = X[0].clone()
+    g = torch.Generator(device=dev)
+    g.manual_seed(77)
+    psi = torch.randn(12 * int(np.prod(L)) * LS, dtype=torch.complex128, device=dev, generator=g)
+    d64, d32 = torch.empty_like(psi), torch.empty_like(psi)
+    mg.mgdwf_apply_dwf(h, psi, d64, prec="f64")
+    mg.mgdwf_apply_dwf(h, psi, d32, prec="f32")
+    Lc = tuple(L[m] // BLOCK[m] for m in range(4))
+    cvec = torch.randn(Lc[::-1] + (2, NVEC), dtype=torch.complex128, device=dev, generator=g)
+    c64 = torch.empty_like(cvec)
+    mg.mgdwf_apply_coarse(h, cvec, c64, prec="f64")
+    coarse_err = {}
+    for cp in ("f32", "f16", "bf16"):
+        cy = torch.empty_like(cvec)
+        mg.mgdwf_apply_coarse(h, cvec, cy, prec=cp)
+        coarse_err[cp] = float(torch.linalg.norm(cy - c64) / torch.linalg.norm(c64))
+    precision = {
+        "dslash_f32_relerr": float(torch.linalg.norm(d32 - d64) / torch.linalg.norm(d64)),
+        "coarse_apply_relerr": coarse_err,
+        "solution_mixed_vs_fp64_relerr": (float(torch.linalg.norm(x0_mixed - x1) / torch.linalg.norm(x1))
+                                          if args.fp64_solves >= 1 else None),
+        "note": "relative 2-norm differences from the FP64 path on the same input (random field, random coarse "
+                "vector, and the first point source's solution)",
+    }
+    del psi, d64, d32, x0_mixed
+    log(f"precision {precision}")
+
     # ---- Dslash bandwidth (HIP events on the library stream) and roofline
     V4 = int(np.prod(L))
     bytes64 = 2 * 12 * V4 * LS * 16 + 36 * V4 * 16
@@ -484,6 +513,7 @@ def main():
         "prolong_f32_GBs": rp_bytes32 / (msP * 1e-3) / 1e9,
         "coarse_apply_f32_us": msC * 1e3,
         "dslash_tiling": tiling,
+        "precision": precision,
         "roofline": {"bound": "hbm", "kernel": "k_dslash_tq (FP32 Dslash, 12 RHS per launch, autotuned tiling)",
                      "achieved": gbs32_12, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs32_12 / HBM_PEAK_GBS,
                      "algorithmic_bytes": bytes32_12, "launch_us": ms32_12 * 1e3, "traffic": counted_traffic(tiling["id"])},
