@@ -42,6 +42,8 @@ def main(argv=None):
     ap.add_argument("--block", type=int, nargs=4, default=(4, 4, 4, 4))
     ap.add_argument("--nvec", type=int, default=24)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--coarse-tile", type=int, default=-1,
+                    help="MFMA shape of the 16-bit D_c apply: 0 = 16x16x16, 1 = 16x16x32, -1 = default")
     args = ap.parse_args(argv)
 
     dev = torch.device("cuda:0")
@@ -79,6 +81,7 @@ def main(argv=None):
         mg.mgdwf_set_nullvecs(h, args.block, V, args.nvec)
         del V
         mg.mgdwf_build_coarse(h)
+        mg.mgdwf_set_coarse_tiling(h, args.coarse_tile)
     torch.cuda.synchronize()
     ms = mg.mgdwf_time_kernel(h, KERNELS[args.kernel], args.prec, args.nrhs, args.iters)
     if args.kernel == "dslash":
@@ -92,7 +95,8 @@ def main(argv=None):
         vec = 16 if args.prec == "f64" else 8
         nbytes = 9 * n2 * n2 * Vc * store + args.nrhs * 2 * n2 * Vc * vec
     gbs = nbytes / (ms * 1e-3) / 1e9
-    print(json.dumps({"kernel": args.kernel, "prec": args.prec, "nrhs": args.nrhs, "L": L, "Ls": Ls, "bytes": nbytes,
+    print(json.dumps({"kernel": args.kernel, "prec": args.prec, "nrhs": args.nrhs, "L": L, "Ls": Ls,
+                      "coarse_tile": args.coarse_tile, "bytes": nbytes,
                       "us": ms * 1e3, "GBs": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS}), flush=True)
     h.close()
 
