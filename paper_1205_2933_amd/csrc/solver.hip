@@ -23,12 +23,11 @@ namespace mgdwf {
 namespace {
 
 // slot table (per right-hand side)
-constexpr int S_PP = 0, S_QQ = 1;                                 // MR smoother
 constexpr int S_CRR0 = 2, S_CRR_A = 3, S_CRR_B = 4, S_CPP = 5;    // coarse CGNE
 constexpr int S_DOT = 8;                                          // multidot block (<= 16 dots + 3)
 constexpr int S_QN = 48;                                          // |q_k|^2 at S_QN+k, <q_k, r> after it
 constexpr int S_RIN = 70, S_R64 = 71, S_B = 72, S_TMP = 73;       // FGCR residuals
-constexpr int S_GRR_A = 80, S_GRR_B = 81, S_GPAP = 82, S_G0 = 83; // CG on the normal equations
+constexpr int S_GRR_A = 80, S_GRR_B = 81, S_GPAP = 82;            // CG on the normal equations
 constexpr int S_MR = 96;                                          // MR step i: |p_i|^2, |q_i|^2 at S_MR + 2i, +1
 
 template <class C2> struct Prec;
@@ -368,7 +367,7 @@ template <class F2>
 static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const mgdwf_solve_params& sp,
                        mgdwf_solve_report* rep) {
   const long long nf = c->fine_len();
-  double* sl = c->buf<double>("slots", (size_t)nrhs * NSLOT);
+  c->buf<double>("slots", (size_t)nrhs * NSLOT);  // the slot table, sized for nrhs
   double2* r64 = c->buf<double2>("sol_r64", nf * nrhs);
   F2* rin = c->buf<F2>(std::string("sol_rin") + Prec<F2>::tag, nf * nrhs);
   F2* e = c->buf<F2>(std::string("sol_e") + Prec<F2>::tag, nf * nrhs);
