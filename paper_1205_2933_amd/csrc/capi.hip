@@ -578,6 +578,7 @@ mgdwf_status mgdwf_tune(mgdwf_handle h, int32_t nrhs, int32_t iters, mgdwf_tune_
       rep->chosen = dflt_j;
     }
     if (best >= 0) h->g.ftile = best;
+    h->clear_graphs();  // captured launches carry the old tiling
     // MFMA shape of the 16-bit coarse apply, timed on the FP16 store (the BF16
     // one has the same shape), when a coarse operator is built
     rep->coarse_chosen = -1;
@@ -611,6 +612,7 @@ mgdwf_status mgdwf_set_coarse_tiling(mgdwf_handle h, int32_t id) {
   return guarded(h, [&] {
     need(id >= -1 && id <= 1, MGDWF_ERR_INVALID_ARG, "coarse tiling id must be -1, 0 or 1");
     h->g.ctile = id < 0 ? 0 : id;
+    h->clear_graphs();
   });
 }
 
@@ -621,6 +623,7 @@ mgdwf_status mgdwf_set_tiling(mgdwf_handle h, int32_t id) {
     need(id == -1 || dslash_ftile_desc(h->g, id, desc, &flags), MGDWF_ERR_INVALID_ARG,
          "tiling does not apply to this lattice");
     h->g.ftile = id;
+    h->clear_graphs();
   });
 }
 

@@ -27,11 +27,21 @@ struct mgdwf_ctx {
 
   std::map<std::string, mgdwf::DevBuf> ws;  // named workspaces, grown on demand
   std::map<std::string, std::vector<void*>> ptr_cache;  // device pointer tables as last uploaded
-  std::map<std::string, hipGraphExec_t> graphs;  // captured coarse iteration blocks, keyed by their buffers
-  hipStream_t cap_st = nullptr;                  // private stream the graphs are captured on
+  // Captured launch sequences (coarse iteration blocks, V-cycle segments),
+  // keyed by what they read and write; exec == nullptr marks a sequence that
+  // has run eagerly once (so its workspaces and pointer tables exist) and is
+  // captured on its next use.  fine / coarse: operator applications per replay.
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    long long fine = 0, coarse = 0;
+  };
+  std::map<std::string, Graph> graphs;
+  hipStream_t cap_st = nullptr;  // private stream the graphs are captured on
+  long long ws_gen = 0;          // bumped whenever a workspace is (re)allocated
 
   void clear_graphs() {
-    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : graphs)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     graphs.clear();
   }
   ~mgdwf_ctx() {
@@ -49,7 +59,10 @@ struct mgdwf_ctx {
   T* buf(const std::string& name, size_t count) {
     mgdwf::DevBuf& b = ws[name];
     size_t need = count * sizeof(T);
-    if (b.bytes < need) b.alloc(need);
+    if (b.bytes < need) {
+      b.alloc(need);
+      ++ws_gen;
+    }
     return b.as<T>();
   }
   long long fine_len() const { return 12LL * g.V5; }       // complex numbers per fine field

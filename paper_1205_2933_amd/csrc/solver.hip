@@ -13,6 +13,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <initializer_list>
 #include <vector>
 
 #include "ctx.h"
@@ -171,44 +172,97 @@ struct TwoLevel {
     finalize_rhs(vpart, vec_blocks(nc), 1, sl, S_CPP, nrhs, c->st);
   }
 
-  hipGraphExec_t block_graph(F2* x) {
-    const CoarseStore& s1 = c->Dc;
-    const CoarseStore& s2 = c->DcH;
-    char key[512];
-    snprintf(key, sizeof key, "cg%s:%d:%d:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p:%p", Prec<F2>::tag, nrhs,
-             (int)p.coarse_prec, (void*)x, (void*)cr, (void*)cp, (void*)cq, (void*)ct, (void*)sl, (void*)vpart,
-             s1.m64.p, s1.m32.p, s1.re16.p, s1.reb.p, s2.m64.p, s2.m32.p, s2.re16.p, s2.reb.p);
-    auto found = c->graphs.find(key);
-    if (found != c->graphs.end()) return found->second;
+  // Capture `body` (launches only, no host synchronisation, every workspace
+  // already allocated) as a graph on the private stream; nothing runs now and
+  // replays go to c->st.  The operator-application counters the body bumps are
+  // kept per graph and added at each replay.
+  template <class Body>
+  mgdwf_ctx::Graph& capture(const std::string& key, Body&& body) {
+    mgdwf_ctx::Graph& gr = c->graphs[key];
+    if (gr.exec) return gr;
     if (!c->cap_st) MG_HIP(hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking));
-    // capture on the private stream: nothing runs now; replays go to c->st
     hipStream_t saved = c->st;
-    const long long applies = c->coarse_applies;
+    const long long fa = c->fine_applies, ca = c->coarse_applies;
     c->st = c->cap_st;
     hipGraph_t graph = nullptr;
     MG_HIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
     try {
+      body();
+    } catch (...) {
+      (void)hipStreamEndCapture(c->st, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      c->st = saved;
+      c->fine_applies = fa;
+      c->coarse_applies = ca;
+      c->graphs.erase(key);
+      throw;
+    }
+    MG_HIP(hipStreamEndCapture(c->st, &graph));
+    c->st = saved;
+    gr.fine = c->fine_applies - fa;
+    gr.coarse = c->coarse_applies - ca;
+    c->fine_applies = fa;
+    c->coarse_applies = ca;
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) c->graphs.erase(key);
+    MG_HIP(e);
+    gr.exec = exec;
+    return gr;
+  }
+
+  void replay(const mgdwf_ctx::Graph& gr) {
+    MG_HIP(hipGraphLaunch(gr.exec, c->st));
+    c->fine_applies += gr.fine;
+    c->coarse_applies += gr.coarse;
+  }
+
+  // Run `body` through a graph under `key` when graphs are enabled: eagerly the
+  // first time (allocating its workspaces and uploading its pointer tables),
+  // captured and replayed from the second time on.
+  template <class Body>
+  void segment(const std::string& key, Body&& body) {
+    if (!p.coarse_graph) {
+      body();
+      return;
+    }
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+      body();
+      c->graphs[key];  // seen once
+      return;
+    }
+    replay(capture(key, body));
+  }
+
+  std::string key_of(const char* what, std::initializer_list<const void*> ptrs) const {
+    std::string k = std::string(what) + Prec<F2>::tag + ":" + std::to_string(nrhs) + ":" +
+                    std::to_string((int)p.coarse_prec) + ":" + std::to_string(c->g.ftile) + ":" +
+                    std::to_string(c->g.ctile) + ":" + std::to_string(p.nu_pre) + ":" + std::to_string(p.nu_post) +
+                    ":" + std::to_string(c->ws_gen);
+    char buf[32];
+    for (const void* q : ptrs) {
+      snprintf(buf, sizeof buf, ":%p", q);
+      k += buf;
+    }
+    return k;
+  }
+
+  // one block of `check` coarse CGNE iterations (their arguments are the same
+  // in every block: the slot pair swaps an even number of times)
+  const mgdwf_ctx::Graph& block_graph(F2* x) {
+    const CoarseStore& s1 = c->Dc;
+    const CoarseStore& s2 = c->DcH;
+    const std::string key = key_of("cg", {x, cr, cp, cq, ct, sl, vpart, s1.m64.p, s1.m32.p, s1.re16.p, s1.reb.p,
+                                          s2.m64.p, s2.m32.p, s2.re16.p, s2.reb.p});
+    return capture(key, [&] {
       int cur = S_CRR_A, nxt = S_CRR_B;
       for (int k = 0; k < check; ++k) {
         cg_iteration(x, 1, cur, nxt);
         std::swap(cur, nxt);
       }
-    } catch (...) {
-      (void)hipStreamEndCapture(c->st, &graph);
-      if (graph) (void)hipGraphDestroy(graph);
-      c->st = saved;
-      c->coarse_applies = applies;
-      throw;
-    }
-    MG_HIP(hipStreamEndCapture(c->st, &graph));
-    c->st = saved;
-    c->coarse_applies = applies;
-    hipGraphExec_t exec = nullptr;
-    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    MG_HIP(e);
-    c->graphs[key] = exec;
-    return exec;
+    });
   }
 
   void coarse_solve(const F2* b, F2* x) {
@@ -222,8 +276,7 @@ struct TwoLevel {
     int it = 0;
     while (it < p.coarse_maxiter) {
       if (p.coarse_graph && it > 0 && it % check == 0 && it + check <= p.coarse_maxiter) {
-        MG_HIP(hipGraphLaunch(block_graph(x), c->st));
-        c->coarse_applies += 2 * check;
+        replay(block_graph(x));
         it += check;  // cur and nxt are back where they were
       } else {
         cg_iteration(x, it, cur, nxt);
@@ -241,17 +294,23 @@ struct TwoLevel {
   }
 
   // z = M b (the five steps of the paper's V-cycle)
+  // The launches before and after the coarse solve have no host
+  // synchronisation; with p.coarse_graph each runs as one graph replay.
   void apply(const F2* b, F2* z) {
     const F2* V = basis_of<F2>(c);
-    smooth(b, z, r1, p.nu_pre);                                          // x1 = S1^nu1(A, b), r1 = b - A x1
-    restrict_op<F2, F2>(V, r1, cb, c->buf<double>("rpart", restrict_partial_doubles(c->cg, nrhs)), c->g, c->cg,
-                        nrhs, c->st);                                    // b2 = R r1
+    segment(key_of("pre", {b, z, V, gauge_of<F2>(c)}), [&] {
+      smooth(b, z, r1, p.nu_pre);                                        // x1 = S1^nu1(A, b), r1 = b - A x1
+      restrict_op<F2, F2>(V, r1, cb, c->buf<double>("rpart", restrict_partial_doubles(c->cg, nrhs)), c->g, c->cg,
+                          nrhs, c->st);                                  // b2 = R r1
+    });
     coarse_solve(cb, cx);                                                // x2 = S2(RAP, b2)
-    prolong_op<F2, F2>(V, cx, z, true, c->g, c->cg, nrhs, c->st);       // x1 + P x2
-    if (p.nu_post > 0) {
-      fine_op<F2>(c, z, b3, b, false, 1, nrhs, -1);                      // b3 = b - A(P x2 + x1)
-      smooth(b3, z, r3, p.nu_post, false, true);                         // z += S3^nu3(A, b3)
-    }
+    segment(key_of("post", {b, z, V, gauge_of<F2>(c)}), [&] {
+      prolong_op<F2, F2>(V, cx, z, true, c->g, c->cg, nrhs, c->st);     // x1 + P x2
+      if (p.nu_post > 0) {
+        fine_op<F2>(c, z, b3, b, false, 1, nrhs, -1);                    // b3 = b - A(P x2 + x1)
+        smooth(b3, z, r3, p.nu_post, false, true);                       // z += S3^nu3(A, b3)
+      }
+    });
   }
 };
 

@@ -60,10 +60,11 @@ def test_cgne_control(cuda):
 
 @pytest.mark.parametrize("prec,cprec", [("f64", "f64"), ("f32", "f16")])
 def test_coarse_graph_replay_is_bitwise_eager(cuda, prec, cprec):
-    """The coarse solve's 8-iteration blocks replayed as a captured HIP graph
-    give exactly the eager launches' result: a tight coarse tolerance makes
-    every V-cycle replay the graph several times, with eager work and host
-    synchronisations between the replays."""
+    """The coarse solve's 8-iteration blocks and the V-cycle's launch sequences
+    before and after the coarse solve, replayed as captured HIP graphs, give
+    exactly the eager launches' result and operator counts: a tight coarse
+    tolerance makes every V-cycle replay the block graph several times, with
+    eager work and host synchronisations between the replays."""
     import paper_1205_2933_amd as mg
     L, Ls, mf = (4, 4, 4, 4), 8, 0.01
     U = prepare_gauge(L, 0.3, 11)
@@ -78,9 +79,10 @@ def test_coarse_graph_replay_is_bitwise_eager(cuda, prec, cprec):
         mg.mgdwf_set_mg_params(h, mg.make_mg_params((2, 2, 2, 2), 16, coarse_graph=graph, **kw))
         x = torch.zeros_like(b)
         reps = mg.mgdwf_solve(h, b, x, nrhs=2, tol=1e-10, max_outer=400, restart=8)
-        out.setdefault(graph, []).append((x.clone(), [(r["outer_iters"], r["coarse_applies"]) for r in reps]))
+        out.setdefault(graph, []).append(
+            (x.clone(), [(r["outer_iters"], r["fine_applies"], r["coarse_applies"]) for r in reps]))
     x0, r0 = out[False][0]
-    assert r0[0][1] > 40 * r0[0][0]  # many coarse iterations per V-cycle: several graph blocks each
+    assert r0[0][2] > 40 * r0[0][0]  # many coarse iterations per V-cycle: several graph blocks each
     for x1, r1 in out[True]:
         assert torch.equal(x0, x1)
         assert r1 == r0
