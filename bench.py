@@ -503,6 +503,11 @@ def main():
         "mixed_over_fp64_speedup": float(np.mean(fp64_times)) / s_per_rhs,
         "mixed_outer_iters": int(r0["outer_iters"]),
         "mixed_fine_applies_per_rhs": counts["fine"],
+        "mixed_coarse_applies_per_rhs": counts["coarse"],
+        "step_phases_s": {"presmooth_restrict": r0["phase_seconds"][0], "coarse_solve": r0["phase_seconds"][1],
+                          "prolong_postsmooth": r0["phase_seconds"][2],
+                          "outer_fgcr_and_fp64": r0["seconds"] - sum(r0["phase_seconds"]),
+                          "note": "one timed step (12 RHS), V-cycle phases from HIP events on the solve's stream"},
         "max_true_relres": worst,
         "setup_s": setup_s,
         "null_residual": srep["null_residual"],

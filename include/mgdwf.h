@@ -111,6 +111,13 @@ typedef struct {
   double seconds;         /* wall time of the call                                */
   uint32_t flags;         /* bit 0: NaN/Inf met; bit 1: stagnation; bit 2: a   */
                           /* second Gram-Schmidt pass was needed in the FGCR    */
+  double phase_seconds[3]; /* device time of the V-cycle's phases summed over   */
+                          /* the call, from HIP events on the handle's stream:  */
+                          /* [0] pre-smoother + restriction, [1] coarse solve   */
+                          /* (with the host's convergence checks), [2]          */
+                          /* prolongation + residual + post-smoother.  The rest */
+                          /* of `seconds` is the outer FGCR and the FP64 true  */
+                          /* residuals.  Zero for mgdwf_cgne.                  */
 } mgdwf_solve_report;
 
 /* Setup report: median |D v|/|v| over the adaptive vectors after each sweep. */

@@ -53,10 +53,12 @@ class mgdwf_solve_report(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("fine_applies", ctypes.c_int64), ("coarse_applies", ctypes.c_int64),
                 ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("phase_seconds", ctypes.c_double * 3)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["phase_seconds"] = list(self.phase_seconds)
+        return d
 
 
 class mgdwf_setup_report(ctypes.Structure):

@@ -44,9 +44,37 @@ struct mgdwf_ctx {
       if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     graphs.clear();
   }
+  // V-cycle phase timing: events on st bracketing the three phases of the
+  // last V-cycle (before pre-smoothing, after restriction, after the coarse
+  // solve, after post-smoothing) and the seconds summed per phase so far.
+  hipEvent_t phase_ev[4] = {};
+  bool phase_pending = false;
+  double phase_s[3] = {0.0, 0.0, 0.0};
+
+  void phase_mark(int i) {
+    if (!phase_ev[0])
+      for (hipEvent_t& e : phase_ev) MG_HIP(hipEventCreate(&e));
+    if (i == 0) harvest_phases();
+    MG_HIP(hipEventRecord(phase_ev[i], st));
+    if (i == 3) phase_pending = true;
+  }
+  // Add the last complete V-cycle's phase times (waits for its last event).
+  void harvest_phases() {
+    if (!phase_pending) return;
+    phase_pending = false;
+    MG_HIP(hipEventSynchronize(phase_ev[3]));
+    for (int k = 0; k < 3; ++k) {
+      float ms = 0.0f;
+      MG_HIP(hipEventElapsedTime(&ms, phase_ev[k], phase_ev[k + 1]));
+      phase_s[k] += 1e-3 * ms;
+    }
+  }
+
   ~mgdwf_ctx() {
     clear_graphs();
     if (cap_st) (void)hipStreamDestroy(cap_st);
+    for (hipEvent_t e : phase_ev)
+      if (e) (void)hipEventDestroy(e);
   }
   std::string err;
 

@@ -298,12 +298,15 @@ struct TwoLevel {
   // synchronisation; with p.coarse_graph each runs as one graph replay.
   void apply(const F2* b, F2* z) {
     const F2* V = basis_of<F2>(c);
+    c->phase_mark(0);
     segment(key_of("pre", {b, z, V, gauge_of<F2>(c)}), [&] {
       smooth(b, z, r1, p.nu_pre);                                        // x1 = S1^nu1(A, b), r1 = b - A x1
       restrict_op<F2, F2>(V, r1, cb, c->buf<double>("rpart", restrict_partial_doubles(c->cg, nrhs)), c->g, c->cg,
                           nrhs, c->st);                                  // b2 = R r1
     });
+    c->phase_mark(1);
     coarse_solve(cb, cx);                                                // x2 = S2(RAP, b2)
+    c->phase_mark(2);
     segment(key_of("post", {b, z, V, gauge_of<F2>(c)}), [&] {
       prolong_op<F2, F2>(V, cx, z, true, c->g, c->cg, nrhs, c->st);     // x1 + P x2
       if (p.nu_post > 0) {
@@ -311,6 +314,7 @@ struct TwoLevel {
         smooth(b3, z, r3, p.nu_post, false, true);                       // z += S3^nu3(A, b3)
       }
     });
+    c->phase_mark(3);
   }
 };
 
@@ -432,6 +436,8 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
   F2* e = c->buf<F2>(std::string("sol_e") + Prec<F2>::tag, nf * nrhs);
   TwoLevel<F2> M(c, nrhs, c->mp);
   const long long fa0 = c->fine_applies, ca0 = c->coarse_applies, gs0 = c->gs_repeats;
+  c->harvest_phases();
+  const double ph0[3] = {c->phase_s[0], c->phase_s[1], c->phase_s[2]};
   auto t0 = std::chrono::steady_clock::now();
   norm_into<double2>(c, b64, nullptr, nf, nrhs, S_B);
   std::vector<double> h = read_slots(c, nrhs);
@@ -471,6 +477,7 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
     outer += k;
     ++restarts;
   }
+  c->harvest_phases();
   double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (c->gs_repeats > gs0) flags |= 4u;
   if (rep)
@@ -482,6 +489,7 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
       rep[r].true_relres = rel[r];
       rep[r].seconds = secs;
       rep[r].flags = flags;
+      for (int k = 0; k < 3; ++k) rep[r].phase_seconds[k] = c->phase_s[k] - ph0[k];
     }
   if (!converged) fail(MGDWF_ERR_NOT_CONVERGED, "solve did not reach the requested tolerance");
 }
@@ -647,6 +655,7 @@ void cgne_solve(mgdwf_ctx* c, double2* b, double2* x, const mgdwf_solve_params& 
     rep->true_relres = tr;
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     rep->flags = 0;
+    for (double& ph : rep->phase_seconds) ph = 0.0;
   }
   if (!(tr < sp.tol)) fail(MGDWF_ERR_NOT_CONVERGED, "CGNE did not reach the requested tolerance");
 }

@@ -79,6 +79,11 @@ def test_coarse_graph_replay_is_bitwise_eager(cuda, prec, cprec):
         mg.mgdwf_set_mg_params(h, mg.make_mg_params((2, 2, 2, 2), 16, coarse_graph=graph, **kw))
         x = torch.zeros_like(b)
         reps = mg.mgdwf_solve(h, b, x, nrhs=2, tol=1e-10, max_outer=400, restart=8)
+        # the V-cycle's three phase times are measured and fit inside the call
+        for r in reps:
+            assert all(t > 0.0 for t in r["phase_seconds"]), r
+            assert sum(r["phase_seconds"]) < r["seconds"], r
+            assert r["phase_seconds"] == reps[0]["phase_seconds"]
         out.setdefault(graph, []).append(
             (x.clone(), [(r["outer_iters"], r["fine_applies"], r["coarse_applies"]) for r in reps]))
     x0, r0 = out[False][0]
