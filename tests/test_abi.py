@@ -44,3 +44,30 @@ def test_invalid_arguments_are_rejected_without_a_device():
     a.L[:] = [4, 4, 4, 4]
     a.bc[:] = [1, 2, 1, 1]
     assert L._lib.mgdwf_create(ctypes.byref(a), None, ctypes.byref(h)) == L.MGDWF_ERR_INVALID_ARG
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field offsets
+    (a C probe built with gcc against include/mgdwf.h prints them)."""
+    import subprocess
+    import paper_1205_2933_amd._lib as L
+    structs = [L.mgdwf_action, L.mgdwf_mg_params, L.mgdwf_solve_params, L.mgdwf_solve_report,
+               L.mgdwf_setup_report, L.mgdwf_tune_report, L.mgdwf_net_config]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "mgdwf.h"', "int main(void) {"]
+    for s in structs:
+        n = s.__name__
+        lines.append(f'  printf("{n} size %zu\\n", sizeof({n}));')
+        for f, _ in s._fields_:
+            lines.append(f'  printf("{n} {f} %zu\\n", offsetof({n}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", str(ROOT / "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    c_side = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for s in structs:
+        n = s.__name__
+        assert c_side[(n, "size")] == ctypes.sizeof(s), n
+        for f, _ in s._fields_:
+            assert c_side[(n, f)] == getattr(s, f).offset, (n, f)
