@@ -4,7 +4,7 @@ Orchestration of C-ABI calls only: the network's forward pass, loss,
 backward pass and Adam step run in the library (mgdwf_net_*), and so do the
 adaptive setups that produce the training targets and refine the proposals.
 
-Workflow (the adaptive setup of the paper's Sec. 2 stays the judge and the
+Workflow (the adaptive setup of the paper's Sec. 2 decides what is kept and is the
 fallback):
 
 1. ``targets``: on each training lattice, a full adaptive setup (mgdwf_setup)
