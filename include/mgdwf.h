@@ -91,7 +91,17 @@ typedef struct {
   mgdwf_prec coarse_prec; /* F64, F32, F16 or BF16: storage of D_c in the V-cycle */
   int32_t coarse_graph;   /* 1: after the first 8 coarse iterations, replay each
                              block of 8 as one captured HIP graph; 0: launch
-                             every kernel.  Results are bitwise the same.        */
+                             every kernel.  Results are bitwise the same.
+                             2: the whole coarse solve as one persistent
+                             cooperative kernel (FP32 fine level, F16/BF16 D_c,
+                             nrhs <= 16, at most as many coarse sites as the
+                             GPU has CUs: one workgroup per site, one per CU;
+                             otherwise as 1).  Same iterations and
+                             tests as 1 (the residual every 8 iterations), its
+                             sums in another order: results agree to rounding;
+                             it skips the last unused D_c^+ apply.  With
+                             1 and 2 the V-cycle's launches before and after
+                             the coarse solve are graph replays too.          */
 } mgdwf_mg_params;
 
 /* Outer flexible GCR (Sec. 3).  Every restart recomputes the true residual

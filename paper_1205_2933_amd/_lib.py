@@ -283,7 +283,8 @@ def make_mg_params(block, nvec, sweeps=3, sweep0_iters=100, sweep_iters=4, nu_pr
     p.nvec, p.sweeps, p.sweep0_iters, p.sweep_iters = nvec, sweeps, sweep0_iters, sweep_iters
     p.nu_pre, p.nu_post, p.coarse_tol, p.coarse_maxiter = nu_pre, nu_post, coarse_tol, coarse_maxiter
     p.fine_prec, p.coarse_prec = PREC[fine_prec], PREC[coarse_prec]
-    p.coarse_graph = 1 if coarse_graph else 0
+    # True / 1: graph replays; "persistent" / 2: one persistent coarse kernel; False / 0: plain launches
+    p.coarse_graph = 2 if coarse_graph in ("persistent", 2) else (1 if coarse_graph else 0)
     return p
 
 

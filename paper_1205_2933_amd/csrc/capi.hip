@@ -68,7 +68,7 @@ void check_params(const mgdwf_ctx* c, const mgdwf_mg_params* p) {
        "bad coarse solver settings");
   check_prec_fine(p->fine_prec);
   need(p->coarse_prec >= MGDWF_F64 && p->coarse_prec <= MGDWF_BF16, MGDWF_ERR_INVALID_ARG, "bad coarse precision");
-  need(p->coarse_graph == 0 || p->coarse_graph == 1, MGDWF_ERR_INVALID_ARG, "coarse_graph must be 0 or 1");
+  need(p->coarse_graph >= 0 && p->coarse_graph <= 2, MGDWF_ERR_INVALID_ARG, "coarse_graph must be 0, 1 or 2");
   (void)make_coarse(c->g, p->block, p->nvec);
 }
 

@@ -17,6 +17,8 @@
 // Internal storage of a block: column major, element (row r, col c) of
 // Dc[X][d] at ((X * 9 + d) * n2 + c) * n2 + r, so that lane r of a wavefront
 // reads consecutive addresses for a fixed column.
+#include <hip/hip_cooperative_groups.h>
+
 #include "mg_internal.h"
 #include "blas.h"
 
@@ -300,18 +302,18 @@ __device__ __forceinline__ f4v mfma32(uint4 a, uint4 b, f4v c) {
 // order the hardware gives the 32 k-slots, A's and B's slot (lane group,
 // element) hold the same k, so the tile sum is the full contraction.  Needs
 // 2 n2 divisible by 32 (n2 by 16, as for every 16-bit store).
+// y(X) for RHS rhs0 .. rhs0 + 15 into red[row][col] (row < 2 n2: Re rows, then
+// Im rows).  Called by all 576 threads of a workgroup; ends with a barrier.
 template <bool BF>
-__global__ __launch_bounds__(576) void k_capply_mfma32(const uint16_t* __restrict__ Are,
-                                                       const uint16_t* __restrict__ Aim,
-                                                       const float* __restrict__ Asc, const uint16_t* __restrict__ xp,
-                                                       const float* __restrict__ xs, float2* __restrict__ y,
-                                                       CoarseArgs a, int nrhs) {
+__device__ __forceinline__ void apply_site32(const uint16_t* Are, const uint16_t* Aim, const float* Asc,
+                                             const uint16_t* xp, const float* xs, const CoarseArgs& a, int nrhs,
+                                             int X, int rhs0, float (*red)[17]) {
+  // opaque to the optimiser, so a caller that applies in a loop recomputes
+  // the operator addresses each time instead of holding them in registers
+  int n2 = a.n2;
+  asm volatile("" : "+s"(X), "+s"(n2));
   constexpr int MTMAX = 8;  // 2 n2 / 16 <= 8
   constexpr int KTMAX = 4;  // 2 n2 / 32 <= 4
-  __shared__ float red[128][17];
-  const int X = blockIdx.x;
-  const int rhs0 = blockIdx.y * 16;
-  const int n2 = a.n2;
   const int MT = 2 * n2 / 16, KT = 2 * n2 / 32;
   const int d = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int col = l & 15, kq = l >> 4;
@@ -361,10 +363,168 @@ __global__ __launch_bounds__(576) void k_capply_mfma32(const uint16_t* __restric
     }
     __syncthreads();
   }
+}
+
+template <bool BF>
+__global__ __launch_bounds__(576) void k_capply_mfma32(const uint16_t* __restrict__ Are,
+                                                       const uint16_t* __restrict__ Aim,
+                                                       const float* __restrict__ Asc, const uint16_t* __restrict__ xp,
+                                                       const float* __restrict__ xs, float2* __restrict__ y,
+                                                       CoarseArgs a, int nrhs) {
+  __shared__ float red[128][17];
+  const int X = blockIdx.x;
+  const int rhs0 = blockIdx.y * 16;
+  const int n2 = a.n2;
+  apply_site32<BF>(Are, Aim, Asc, xp, xs, a, nrhs, X, rhs0, red);
   for (int i = threadIdx.x; i < 16 * n2; i += blockDim.x) {
     const int r = i % n2, cl = i / n2;
     if (rhs0 + cl < nrhs) y[((long long)(rhs0 + cl) * a.Vc + X) * n2 + r] = make_float2(red[r][cl], red[n2 + r][cl]);
   }
+}
+
+// ---------------------------------------------------------------- persistent coarse CGNE
+// The coarse solve (CGNE on D_c D_c^+ y = b, x = D_c^+ y, from x = 0) as one
+// cooperative launch: one workgroup per coarse site, every RHS (<= 16) at
+// once.  Per iteration: q = D_c p at the own site, then x += alpha p and
+// r -= alpha q there (alpha = |r|^2 / |p|^2), r packed to 16 bits with its
+// per-site |r|^2; grid barrier; |r|^2 summed over all sites (each workgroup
+// sums the same partials in the same order, so all take the same decision);
+// t = D_c^+ r, p = t + beta p (beta = |r_new|^2 / |r|^2), p packed with its
+// |p|^2; grid barrier.  The loop ends when every RHS has |r|^2 <= tol^2 |b|^2
+// at one of the tests after every 8th iteration (as in the launched loop), or
+// after maxiter iterations; the last iteration skips the D_c^+ apply, whose
+// result nobody reads.
+struct PersistArgs {
+  const uint16_t *Are, *Aim, *Hre, *Him;  // 16-bit D_c and D_c^+ (the adjoint stencil)
+  const float *Asc, *Hsc;
+  const float2* b;
+  float2 *x, *r, *p;
+  uint16_t *rp, *pp;     // packed r and p: [rhs][X][2 n2]
+  float *rs, *ps;        // their per-(rhs, X) scales
+  double *part_r, *part_p;  // per-(rhs, X) |.|^2
+  long long* count;      // coarse applications are added here (one thread)
+  double tol2;
+  int maxiter, nrhs;
+  CoarseArgs a;
+};
+
+template <bool BF>
+__global__ __launch_bounds__(576) void k_cgne_persistent(PersistArgs q) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  __shared__ float red[128][17];
+  __shared__ float2 v[16][64];  // the site's new r or p, per RHS
+  __shared__ double rr0[16], rr[16], pp[16], rn[16];
+  const CoarseArgs& a = q.a;
+  const int X = blockIdx.x, n2 = a.n2, nrhs = q.nrhs, Vc = a.Vc;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int ne = nrhs * n2;
+  auto at = [&](int rhs, int k) { return ((long long)rhs * Vc + X) * n2 + k; };
+  // v -> 16-bit (one scale per RHS) and |v|^2 per RHS; wave w takes RHS w, w + 9
+  auto pack_site = [&](uint16_t* xp, float* xs, double* part) {
+    for (int rhs = w; rhs < nrhs; rhs += 9) {
+      const float2 val = l < n2 ? v[rhs][l] : make_float2(0.f, 0.f);
+      float mx = fmaxf(fabsf(val.x), fabsf(val.y));
+      double nn = (double)val.x * val.x + (double)val.y * val.y;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+        nn += __shfl_xor(nn, off, 64);
+      }
+      const float inv = mx > 0.f ? 1.f / mx : 0.f;
+      const long long i = (long long)rhs * Vc + X;
+      if (l == 0) {
+        xs[i] = mx;
+        part[i] = nn;
+      }
+      if (l < n2) {
+        xp[i * 2 * n2 + l] = to16<BF>(val.x * inv);
+        xp[i * 2 * n2 + n2 + l] = to16<BF>(val.y * inv);
+      }
+    }
+  };
+  // dst[rhs] = sum over all sites of part[rhs][.], fixed order
+  auto reduce_all = [&](const double* part, double* dst) {
+    for (int rhs = w; rhs < nrhs; rhs += 9) {
+      double s = 0.0;
+      for (int Y = l; Y < Vc; Y += 64) s += part[(long long)rhs * Vc + Y];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (l == 0) dst[rhs] = s;
+    }
+    __syncthreads();
+  };
+  long long napp = 0;
+  // x = 0, r = b, |b|^2
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int rhs = e / n2, k = e - rhs * n2;
+    const float2 bv = q.b[at(rhs, k)];
+    q.x[at(rhs, k)] = make_float2(0.f, 0.f);
+    q.r[at(rhs, k)] = bv;
+    v[rhs][k] = bv;
+  }
+  __syncthreads();
+  pack_site(q.rp, q.rs, q.part_r);
+  grid.sync();
+  reduce_all(q.part_r, rr0);
+  if (threadIdx.x < nrhs) rr[threadIdx.x] = rr0[threadIdx.x];
+  // p = D_c^+ r, |p|^2
+  apply_site32<BF>(q.Hre, q.Him, q.Hsc, q.rp, q.rs, a, nrhs, X, 0, red);
+  ++napp;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int rhs = e / n2, k = e - rhs * n2;
+    const float2 t = make_float2(red[k][rhs], red[n2 + k][rhs]);
+    q.p[at(rhs, k)] = t;
+    v[rhs][k] = t;
+  }
+  __syncthreads();
+  pack_site(q.pp, q.ps, q.part_p);
+  grid.sync();
+  reduce_all(q.part_p, pp);
+  for (int it = 0; it < q.maxiter; ++it) {
+    // q = D_c p; x += alpha p; r -= alpha q
+    apply_site32<BF>(q.Are, q.Aim, q.Asc, q.pp, q.ps, a, nrhs, X, 0, red);
+    ++napp;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      const int rhs = e / n2, k = e - rhs * n2;
+      const float alpha = (float)(pp[rhs] > 0.0 ? rr[rhs] / pp[rhs] : 0.0);
+      const long long i = at(rhs, k);
+      const float2 pv = q.p[i], xv = q.x[i], rv = q.r[i];
+      const float2 qv = make_float2(red[k][rhs], red[n2 + k][rhs]);
+      q.x[i] = make_float2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
+      const float2 rn2 = make_float2(rv.x - alpha * qv.x, rv.y - alpha * qv.y);
+      q.r[i] = rn2;
+      v[rhs][k] = rn2;
+    }
+    __syncthreads();
+    pack_site(q.rp, q.rs, q.part_r);
+    grid.sync();
+    reduce_all(q.part_r, rn);
+    // the launched loop's schedule: the residual is tested after every 8th
+    // iteration (the same decision in every workgroup)
+    const int n = it + 1;
+    bool done = n % 8 == 0;
+    for (int rhs = 0; rhs < nrhs && done; ++rhs)
+      if (!(rn[rhs] <= q.tol2 * rr0[rhs])) done = false;
+    if (done || n == q.maxiter) break;
+    // t = D_c^+ r; p = t + beta p
+    apply_site32<BF>(q.Hre, q.Him, q.Hsc, q.rp, q.rs, a, nrhs, X, 0, red);
+    ++napp;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      const int rhs = e / n2, k = e - rhs * n2;
+      const float beta = (float)(rr[rhs] > 0.0 ? rn[rhs] / rr[rhs] : 0.0);
+      const long long i = at(rhs, k);
+      const float2 pv = q.p[i];
+      const float2 t = make_float2(red[k][rhs] + beta * pv.x, red[n2 + k][rhs] + beta * pv.y);
+      q.p[i] = t;
+      v[rhs][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < nrhs) rr[threadIdx.x] = rn[threadIdx.x];
+    pack_site(q.pp, q.ps, q.part_p);
+    grid.sync();
+    reduce_all(q.part_p, pp);
+  }
+  if (X == 0 && threadIdx.x == 0) *q.count += napp;
 }
 
 }  // namespace
@@ -466,6 +626,63 @@ void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, floa
     hipLaunchKernelGGL(k_capply_mfma<false>, grid, dim3(576), 0, st, s.re16.as<uint16_t>(), s.im16.as<uint16_t>(),
                        s.sc16.as<float>(), xp, xs, y, coarse_args(cg), nrhs);
   MG_LAUNCH_CHECK();
+}
+
+size_t persistent_cgne_bytes(const CoarseGeometry& cg, int nrhs) {
+  const size_t nsv = (size_t)nrhs * cg.Vc;
+  return 2 * nsv * 2 * cg.n2 * sizeof(uint16_t) + 2 * nsv * sizeof(float) + 2 * nsv * sizeof(double) + 6 * 256;
+}
+
+bool coarse_cgne_persistent(const CoarseStore& D, const CoarseStore& DH, mgdwf_prec prec, const float2* b, float2* x,
+                            float2* r, float2* p, void* work, long long* count, const CoarseGeometry& cg, int nrhs,
+                            double tol, int maxiter, int device, hipStream_t st) {
+  if (!(prec == MGDWF_F16 || prec == MGDWF_BF16) || cg.n2 % 16 || cg.n2 > 64 || nrhs < 1 || nrhs > 16 ||
+      maxiter < 1)
+    return false;
+  const bool bf = prec == MGDWF_BF16;
+  const void* fn = bf ? reinterpret_cast<const void*>(&k_cgne_persistent<true>)
+                      : reinterpret_cast<const void*>(&k_cgne_persistent<false>);
+  int coop = 0, ncu = 0, per_cu = 0;
+  MG_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device));
+  MG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
+  MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 576, 0));
+  // One workgroup per CU at most: the grid of one workgroup per coarse site
+  // must fit the CUs.  Two per CU (512 sites of a 16^3x32 lattice with 4^4
+  // blocks on 256 CUs) did not finish once, for a reason not found; that
+  // configuration is not used.
+  if (!coop || per_cu < 1 || cg.Vc > ncu) return false;
+  const size_t nsv = (size_t)nrhs * cg.Vc;
+  char* w = static_cast<char*>(work);
+  auto take = [&](size_t bytes) {
+    char* q = w;
+    w += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  PersistArgs q;
+  q.Are = (bf ? D.reb : D.re16).as<uint16_t>();
+  q.Aim = (bf ? D.imb : D.im16).as<uint16_t>();
+  q.Asc = (bf ? D.scb : D.sc16).as<float>();
+  q.Hre = (bf ? DH.reb : DH.re16).as<uint16_t>();
+  q.Him = (bf ? DH.imb : DH.im16).as<uint16_t>();
+  q.Hsc = (bf ? DH.scb : DH.sc16).as<float>();
+  q.b = b;
+  q.x = x;
+  q.r = r;
+  q.p = p;
+  q.rp = reinterpret_cast<uint16_t*>(take(nsv * 2 * cg.n2 * sizeof(uint16_t)));
+  q.pp = reinterpret_cast<uint16_t*>(take(nsv * 2 * cg.n2 * sizeof(uint16_t)));
+  q.rs = reinterpret_cast<float*>(take(nsv * sizeof(float)));
+  q.ps = reinterpret_cast<float*>(take(nsv * sizeof(float)));
+  q.part_r = reinterpret_cast<double*>(take(nsv * sizeof(double)));
+  q.part_p = reinterpret_cast<double*>(take(nsv * sizeof(double)));
+  q.count = count;
+  q.tol2 = tol * tol;
+  q.maxiter = maxiter;
+  q.nrhs = nrhs;
+  q.a = coarse_args(cg);
+  void* args[] = {&q};
+  MG_HIP(hipLaunchCooperativeKernel(fn, dim3(cg.Vc), dim3(576), args, 0, st));
+  return true;
 }
 
 }  // namespace mgdwf

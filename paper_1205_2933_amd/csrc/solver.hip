@@ -14,6 +14,7 @@
 #include <complex>
 #include <cstdio>
 #include <initializer_list>
+#include <type_traits>
 #include <vector>
 
 #include "ctx.h"
@@ -266,6 +267,14 @@ struct TwoLevel {
   }
 
   void coarse_solve(const F2* b, F2* x) {
+    if constexpr (std::is_same<F2, float2>::value) {
+      if (p.coarse_graph == 2 &&
+          coarse_cgne_persistent(c->Dc, c->DcH, p.coarse_prec, b, x, cr, cp,
+                                 c->buf<char>("cg_persist", persistent_cgne_bytes(c->cg, nrhs)),
+                                 c->buf<long long>("cg_count", 1), c->cg, nrhs, p.coarse_tol, p.coarse_maxiter,
+                                 c->device, c->st))
+        return;
+    }
     copy(c, b, cr, nc * nrhs);
     norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR0);
     norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR_A);
@@ -438,6 +447,8 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
   const long long fa0 = c->fine_applies, ca0 = c->coarse_applies, gs0 = c->gs_repeats;
   c->harvest_phases();
   const double ph0[3] = {c->phase_s[0], c->phase_s[1], c->phase_s[2]};
+  long long* pcount = c->buf<long long>("cg_count", 1);  // applications made by persistent coarse solves
+  MG_HIP(hipMemsetAsync(pcount, 0, sizeof(long long), c->st));
   auto t0 = std::chrono::steady_clock::now();
   norm_into<double2>(c, b64, nullptr, nf, nrhs, S_B);
   std::vector<double> h = read_slots(c, nrhs);
@@ -478,6 +489,12 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
     ++restarts;
   }
   c->harvest_phases();
+  {
+    long long n = 0;
+    MG_HIP(hipMemcpyAsync(&n, c->buf<long long>("cg_count", 1), sizeof n, hipMemcpyDeviceToHost, c->st));
+    MG_HIP(hipStreamSynchronize(c->st));
+    c->coarse_applies += n;
+  }
   double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (c->gs_repeats > gs0) flags |= 4u;
   if (rep)

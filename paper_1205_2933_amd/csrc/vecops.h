@@ -80,5 +80,16 @@ size_t coarse_pack_bytes(const CoarseGeometry& cg, int nrhs);
 // ctile: MFMA shape of the 16-bit apply, 0 = 16x16x16, 1 = 16x16x32
 void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, float2* y, const CoarseGeometry& cg,
                     int nrhs, void* pack, int ctile, hipStream_t st);
+// Coarse CGNE (x = D_c^+ y, D_c D_c^+ y = b, from x = 0, to |r| <= tol |b| tested
+// every 8 iterations, or maxiter iterations) as one persistent cooperative
+// launch on the 16-bit store;
+// r and p are workspaces of the vector size, work holds persistent_cgne_bytes,
+// and the coarse applications it makes are added to *count (device).  Returns
+// false, launching nothing, where it does not apply (precision, nrhs > 16, or
+// more coarse sites than CUs: one workgroup per site, at most one per CU).
+size_t persistent_cgne_bytes(const CoarseGeometry& cg, int nrhs);
+bool coarse_cgne_persistent(const CoarseStore& D, const CoarseStore& DH, mgdwf_prec prec, const float2* b, float2* x,
+                            float2* r, float2* p, void* work, long long* count, const CoarseGeometry& cg, int nrhs,
+                            double tol, int maxiter, int device, hipStream_t st);
 
 }  // namespace mgdwf

@@ -128,3 +128,55 @@ def test_fgcr_iterate_matches_oracle(cuda):
     assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) < 1e-9
     rg = np.linalg.norm(b - dwf.apply_dwf(xg, U, 1.8, mf)) / np.linalg.norm(b)
     assert abs(rg - orep.true_relres) < 1e-6 * orep.true_relres
+
+
+@pytest.mark.parametrize("cprec", ["f16", "bf16"])
+def test_persistent_coarse_solve(cuda, cprec):
+    """The coarse CGNE as one persistent cooperative kernel (coarse_graph = 2)
+    against the launched iterations (paper Sec. 2's coarse step): with a
+    tolerance never met both run 16 iterations per V-cycle, so six FGCR steps
+    agree up to the rounding of the coarse sums, which the persistent kernel
+    takes in another order; it skips the launched loop's last, unused D_c^+
+    apply.  With the tolerance of 0.1, tested every 8 iterations on both
+    sides, it reaches 1e-10 against the oracle's D in the graph path's
+    number of outer iterations (up to rounding)."""
+    import paper_1205_2933_amd as mg
+    L, Ls, mf, block = (4, 4, 4, 4), 8, 0.01, (2, 2, 2, 2)
+    U = prepare_gauge(L, 0.3, 11)
+    h = mg.Handle(L, Ls, 1.8, mf)
+    mg.mgdwf_set_gauge(h, dev(U))
+    kw = dict(sweeps=1, sweep0_iters=100, sweep_iters=4, fine_prec="f32", coarse_prec=cprec)
+    mg.mgdwf_setup(h, mg.make_mg_params(block, 16, coarse_graph=False, **kw), dev(random_starts(L, Ls, 8, 21)))
+    b = gaussian_fermion(L, Ls, 31, n=2)
+    xs, counts = {}, {}
+    for mode in (False, "persistent"):
+        mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, coarse_graph=mode, coarse_tol=1e-30,
+                                                    coarse_maxiter=16, **kw))
+        x = torch.zeros_like(dev(b))
+        reps = mg.mgdwf_solve(h, dev(b), x, nrhs=2, tol=1e-30, max_outer=6, restart=8, allow_not_converged=True)
+        xs[mode] = x
+        counts[mode] = [(r["outer_iters"], r["fine_applies"], r["coarse_applies"]) for r in reps]
+    print("counts", counts, flush=True)
+    for (o0, f0, c0), (o1, f1, c1) in zip(counts[False], counts["persistent"]):
+        assert (o0, f0) == (o1, f1) == (6, f0)
+        assert c0 == 6 * 33 and c1 == 6 * 32
+    rel = float(torch.linalg.norm(xs[False] - xs["persistent"]) / torch.linalg.norm(xs[False]))
+    print("persistent vs launched", rel, flush=True)
+    assert rel < 1e-3
+    outer = {}
+    for mode in (True, "persistent"):
+        mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, coarse_graph=mode, coarse_tol=0.1,
+                                                    coarse_maxiter=200, **kw))
+        x = torch.zeros_like(dev(b))
+        reps = mg.mgdwf_solve(h, dev(b), x, nrhs=2, tol=1e-10, max_outer=400, restart=8, allow_not_converged=True)
+        print("mode", mode, reps[0], flush=True)
+        outer[mode] = reps[0]["outer_iters"]
+        assert max(r["true_relres"] for r in reps) < 1e-10
+    print("outer iterations", outer, flush=True)
+    assert abs(outer[True] - outer["persistent"]) <= 8
+    xh = x.cpu().numpy()
+    for k in range(2):
+        bk = b[k]
+        r = bk - dwf.apply_dwf(xh[k], U, 1.8, mf)
+        assert np.linalg.norm(r) / np.linalg.norm(bk) < 1e-10
+        assert reps[k]["true_relres"] < 1e-10
