@@ -5,6 +5,9 @@
 // fixed slot table per right-hand side: slot(rhs, i) = sl[rhs * NSLOT + i].
 // Reductions are two-stage: a per-workgroup partial, then k_finalize; the
 // summation order is fixed, so results are bitwise reproducible.
+#include <cstdint>
+#include <type_traits>
+
 #include "mg_internal.h"
 #include "blas.h"
 #include "vecops.h"
@@ -62,6 +65,53 @@ __global__ __launch_bounds__(256) void k_res_update(C2* __restrict__ rout, const
   const T alpha = (T)(dd > 0.0 ? slot(sl, rhs, num) / dd : 0.0);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     rout[off + i] = csub(rin[off + i], cscale(q[off + i], alpha));
+}
+
+// FP32 forms of k_res_update and k_lincomb for vectors of even length with
+// 16-byte aligned storage: each lane moves two complex numbers per access
+// (np = n / 2 pairs per RHS), the same arithmetic per element.
+__global__ __launch_bounds__(256) void k_res_update_pair(float4* rout, const float4* rin, const float4* __restrict__ q,
+                                                         long long np, const double* __restrict__ sl, int num, int den) {
+  const int rhs = blockIdx.y;
+  const long long off = rhs * np;
+  const double dd = slot(sl, rhs, den);
+  const float alpha = (float)(dd > 0.0 ? slot(sl, rhs, num) / dd : 0.0);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (long long)gridDim.x * blockDim.x) {
+    const float4 a = rin[off + i], b = q[off + i];
+    const float2 lo = csub(make_float2(a.x, a.y), cscale(make_float2(b.x, b.y), alpha));
+    const float2 hi = csub(make_float2(a.z, a.w), cscale(make_float2(b.z, b.w), alpha));
+    rout[off + i] = make_float4(lo.x, lo.y, hi.x, hi.y);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lincomb_pair(float4* __restrict__ x, const float2* const* __restrict__ ps,
+                                                      int nv, long long np, const double* __restrict__ sl, int num,
+                                                      int acc0) {
+  constexpr int MAXV = 16;
+  const int rhs = blockIdx.y;
+  const long long off = rhs * np;
+  float al[MAXV];
+#pragma unroll
+  for (int m = 0; m < MAXV; ++m) {
+    const double d = m < nv ? slot(sl, rhs, num + 2 * m + 1) : 0.0;
+    al[m] = (float)(d > 0.0 ? slot(sl, rhs, num + 2 * m) / d : 0.0);
+  }
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (long long)gridDim.x * blockDim.x) {
+    float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+    if (acc0) {
+      const float4 v = x[off + i];
+      lo = make_float2(v.x, v.y);
+      hi = make_float2(v.z, v.w);
+    }
+#pragma unroll
+    for (int m = 0; m < MAXV; ++m)
+      if (m < nv) {
+        const float4 v = reinterpret_cast<const float4*>(ps[m])[off + i];
+        lo = cadd(lo, cscale(make_float2(v.x, v.y), al[m]));
+        hi = cadd(hi, cscale(make_float2(v.z, v.w), al[m]));
+      }
+    x[off + i] = make_float4(lo.x, lo.y, hi.x, hi.y);
+  }
 }
 
 // x = sum_m alpha_m p_m (acc: x += ...), alpha_m = sl[num + 2m] / sl[num + 2m + 1]  (m < nv)
@@ -306,9 +356,20 @@ void mr_update(C2* x, C2* r, const C2* p, const C2* q, long long n, int nrhs, co
   MG_LAUNCH_CHECK();
 }
 
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 template <class C2>
 void res_update(C2* rout, const C2* rin, const C2* q, long long n, int nrhs, const double* sl, int num, int den,
                 hipStream_t st) {
+  if constexpr (std::is_same<C2, float2>::value) {
+    if (n % 2 == 0 && aligned16(rout) && aligned16(rin) && aligned16(q)) {
+      hipLaunchKernelGGL(k_res_update_pair, dim3(vec_blocks(n / 2), nrhs), dim3(256), 0, st,
+                         reinterpret_cast<float4*>(rout), reinterpret_cast<const float4*>(rin),
+                         reinterpret_cast<const float4*>(q), n / 2, sl, num, den);
+      MG_LAUNCH_CHECK();
+      return;
+    }
+  }
   hipLaunchKernelGGL(k_res_update<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, rout, rin, q, n, sl, num, den);
   MG_LAUNCH_CHECK();
 }
@@ -317,6 +378,14 @@ template <class C2>
 void lincomb(C2* x, const C2* const* ps, int nv, long long n, int nrhs, const double* sl, int num, bool acc,
              hipStream_t st) {
   if (nv > 16) fail(MGDWF_ERR_INVALID_ARG, "at most 16 smoother steps");
+  if constexpr (std::is_same<C2, float2>::value) {
+    if (n % 2 == 0 && aligned16(x)) {  // the vectors ps[m] are workspaces: 256-byte aligned
+      hipLaunchKernelGGL(k_lincomb_pair, dim3(vec_blocks(n / 2), nrhs), dim3(256), 0, st,
+                         reinterpret_cast<float4*>(x), ps, nv, n / 2, sl, num, acc ? 1 : 0);
+      MG_LAUNCH_CHECK();
+      return;
+    }
+  }
   hipLaunchKernelGGL(k_lincomb<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, x, ps, nv, n, sl, num, acc ? 1 : 0);
   MG_LAUNCH_CHECK();
 }
