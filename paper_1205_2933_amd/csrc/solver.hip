@@ -154,7 +154,9 @@ struct TwoLevel {
       fine_op<F2>(c, P[i], qq, nullptr, false, 0, nrhs, S_MR + 2 * i + 1);  // q = D p_i, |q|^2
       if (need_r || i + 1 < nu) res_update<F2>(r, rin, qq, nf, nrhs, sl, S_MR + 2 * i, S_MR + 2 * i + 1, c->st);
     }
-    lincomb<F2>(x, ptr_table<F2>(c, "ptrP" + t, P), nu, nf, nrhs, sl, S_MR, add_x, c->st);
+    // one table per smoother length: with nu_pre != nu_post a shared table
+    // would be re-uploaded (with a stream synchronisation) inside captures
+    lincomb<F2>(x, ptr_table<F2>(c, "ptrP" + t + std::to_string(nu), P), nu, nf, nrhs, sl, S_MR, add_x, c->st);
   }
 
   // CGNE on D_c: x = D_c^+ y with D_c D_c^+ y = b, to |r| < tol |b| or maxiter.

@@ -93,6 +93,32 @@ def test_coarse_graph_replay_is_bitwise_eager(cuda, prec, cprec):
         assert r1 == r0
 
 
+def test_asymmetric_smoother_steps_with_graphs(cuda):
+    """nu_pre != nu_post (paper Sec. 2 leaves nu1 and nu3 independent) with the
+    V-cycle's launch sequences replayed as graphs: the solve converges and is
+    bitwise the eager launches' result (regression: the two smoothers once
+    shared a pointer table that had to be re-uploaded inside a capture)."""
+    import paper_1205_2933_amd as mg
+    L, Ls, mf, block = (4, 4, 4, 4), 8, 0.01, (2, 2, 2, 2)
+    U = prepare_gauge(L, 0.3, 11)
+    h = mg.Handle(L, Ls, 1.8, mf)
+    mg.mgdwf_set_gauge(h, dev(U))
+    kw = dict(sweeps=1, sweep0_iters=100, sweep_iters=4, coarse_tol=0.1, coarse_maxiter=200, nu_pre=6, nu_post=3,
+              fine_prec="f32", coarse_prec="f16")
+    mg.mgdwf_setup(h, mg.make_mg_params(block, 16, coarse_graph=False, **kw), dev(random_starts(L, Ls, 8, 21)))
+    b = dev(gaussian_fermion(L, Ls, 31, n=2))
+    out = []
+    for graph in (False, True, True):
+        mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, coarse_graph=graph, **kw))
+        x = torch.zeros_like(b)
+        reps = mg.mgdwf_solve(h, b, x, nrhs=2, tol=1e-10, max_outer=400, restart=8)
+        assert max(r["true_relres"] for r in reps) < 1e-10
+        out.append((x.clone(), [(r["outer_iters"], r["fine_applies"]) for r in reps]))
+    for x1, r1 in out[1:]:
+        assert torch.equal(out[0][0], x1)
+        assert r1 == out[0][1]
+
+
 def test_fgcr_iterate_matches_oracle(cuda):
     """Six FP64 flexible-GCR steps with the two-level V-cycle, on the GPU and in
     the oracle, from the same basis and right-hand side (paper Sec. 2's
