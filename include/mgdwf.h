@@ -82,7 +82,8 @@ typedef struct {
   int32_t nvec;           /* Nv: basis columns per chirality (coarse dof = 2 Nv)  */
   int32_t sweeps;         /* adaptive sweeps in mgdwf_setup, including sweep 0    */
   int32_t sweep0_iters;   /* CG iterations on D^+D v = 0 in sweep 0               */
-  int32_t sweep_iters;    /* MG-FGCR iterations per inverse-iteration sweep       */
+  int32_t sweep_iters;    /* flexible-GCR steps with the current V-cycle on        */
+                          /* D x = 0 from each vector, per sweep after sweep 0    */
   int32_t nu_pre;         /* smoother steps before the coarse correction          */
   int32_t nu_post;        /* smoother steps after it                              */
   double coarse_tol;      /* relative residual of the coarse solve                */
@@ -94,14 +95,18 @@ typedef struct {
                              every kernel.  Results are bitwise the same.
                              2: the whole coarse solve as one persistent
                              cooperative kernel (FP32 fine level, F16/BF16 D_c,
-                             nrhs <= 16, at most as many coarse sites as the
-                             GPU has CUs: one workgroup per site, one per CU;
-                             otherwise as 1).  Same iterations and
-                             tests as 1 (the residual every 8 iterations), its
-                             sums in another order: results agree to rounding;
-                             it skips the last unused D_c^+ apply.  With
-                             1 and 2 the V-cycle's launches before and after
-                             the coarse solve are graph replays too.          */
+                             nrhs <= 16): at most one workgroup per CU, each
+                             owning every G-th coarse site, with the library's
+                             own grid barrier, whose waits are bounded (see
+                             mgdwf_set_barrier_timeout; a wait that runs out
+                             ends the solve with MGDWF_ERR_HIP).  Elsewhere it
+                             runs as 1 and sets bit 3 of the report's flags.
+                             Same iterations and tests as 1 (the residual
+                             every 8 iterations), its sums in another order:
+                             results agree to rounding; it skips the last
+                             unused D_c^+ apply.  With 1 and 2 the V-cycle's
+                             launches before and after the coarse solve are
+                             graph replays too.                               */
 } mgdwf_mg_params;
 
 /* Outer flexible GCR (Sec. 3).  Every restart recomputes the true residual
@@ -120,7 +125,9 @@ typedef struct {
   double true_relres;     /* |b - D x| / |b| in FP64 at return                    */
   double seconds;         /* wall time of the call                                */
   uint32_t flags;         /* bit 0: NaN/Inf met; bit 1: stagnation; bit 2: a   */
-                          /* second Gram-Schmidt pass was needed in the FGCR    */
+                          /* second Gram-Schmidt pass was needed in the FGCR;   */
+                          /* bit 3: the persistent coarse solve was asked for   */
+                          /* but did not apply (launched loop used instead)     */
   double phase_seconds[3]; /* device time of the V-cycle's phases summed over   */
                           /* the call, from HIP events on the handle's stream:  */
                           /* [0] pre-smoother + restriction, [1] coarse solve   */
@@ -168,6 +175,12 @@ mgdwf_status mgdwf_apply_dwf(mgdwf_handle h, const double* in, double* out, int3
  * nvec > 6 * Ls * (block volume). */
 mgdwf_status mgdwf_set_nullvecs(mgdwf_handle h, const int32_t block[4], const double* V,
                                 int32_t nvec);
+/* The near-null vectors the installed basis was built from, canonical
+ * [n][fermion]: after mgdwf_setup the nvec/2 adaptive vectors (normalised, before
+ * they are paired with their reflections), after mgdwf_set_nullvecs the nvec
+ * vectors given.  *n receives the count; with V == NULL only the count is
+ * written.  MGDWF_ERR_STATE before any setup or set_nullvecs. */
+mgdwf_status mgdwf_get_nullvecs(mgdwf_handle h, double* V, int32_t* n);
 /* The orthonormal basis, canonical [Nv][fermion] (both chirality columns of
  * vector k in field k). */
 mgdwf_status mgdwf_get_basis(mgdwf_handle h, double* Vhat);
@@ -194,9 +207,13 @@ mgdwf_status mgdwf_apply_coarse(mgdwf_handle h, const double* in, double* out, i
 /* ---- setup and solve (steps a8-a11): Sec. 2, Sec. 3 -------------------- */
 
 /* Adaptive setup (Sec. 2): starting from nvec/2 random vectors V0 (canonical,
- * device; the random numbers are inputs), run sweep 0 and the inverse-
- * iteration sweeps, pair each vector with its fifth-dimension reflection,
- * build the basis and D_c.  report may be NULL. */
+ * device; the random numbers are inputs), sweep 0 runs sweep0_iters CG
+ * iterations on D^+D v = 0 from each; every later sweep applies the current
+ * multigrid to the same problem: sweep_iters flexible-GCR steps with the
+ * FP64 V-cycle on D x = 0 starting from x = v, and v becomes the x they leave
+ * (what the multigrid fails to remove).  After each sweep every vector is
+ * normalised, paired with its fifth-dimension reflection, and the basis and
+ * D_c are rebuilt.  report may be NULL. */
 mgdwf_status mgdwf_setup(mgdwf_handle h, const mgdwf_mg_params* p, const double* V0,
                          mgdwf_setup_report* report);
 /* Set the V-cycle parameters used by mgdwf_solve without a new setup
@@ -208,6 +225,13 @@ mgdwf_status mgdwf_set_mg_params(mgdwf_handle h, const mgdwf_mg_params* p);
  * entry (zero it for a cold start).  reports[nrhs] may be NULL. */
 mgdwf_status mgdwf_solve(mgdwf_handle h, const double* b, double* x, int32_t nrhs,
                          const mgdwf_solve_params* p, mgdwf_solve_report* reports);
+
+/* out = M in: one application of the two-level V-cycle (Sec. 2, its five
+ * steps: pre-smoothing, restriction, coarse solve, prolongation with the
+ * residual update, post-smoothing) in the precisions and counts of the
+ * current parameters, to nrhs canonical fields (FP32 fine levels round `in`
+ * to FP32 and return the result as complex128).  Returns after completion. */
+mgdwf_status mgdwf_apply_vcycle(mgdwf_handle h, const double* in, double* out, int32_t nrhs);
 
 /* Release every workspace the handle has grown (solver, setup and timing
  * buffers); later calls allocate what they need again.  The gauge field, the

@@ -72,6 +72,7 @@ class MG:
     Dc: np.ndarray = None
     coarse: _coarse.Coarse = None
     null_residuals: List[float] = field(default_factory=list)
+    sweep_norms: List[List[float]] = field(default_factory=list)   # |v| before each normalisation
 
     def rebuild(self, V: np.ndarray):
         self.Vhat = _tr.build_basis(reflect_pairs(V), self.params.block)
@@ -131,16 +132,22 @@ def adaptive_setup(A: _dwf.DWF, V0: np.ndarray, params: MGParams) -> MG:
         raise ValueError("expected nvec/2 random starts (each is paired with its reflection)")
     V = np.array(V0, dtype=np.complex128, copy=True)
     zero = np.zeros_like(V[0])
+    norms = []
     for k in range(V.shape[0]):
         x = cgnr_null_steps(A, V[k], params.sweep0_iters)
-        V[k] = x / _sol.norm(x)
+        norms.append(_sol.norm(x))
+        V[k] = x / norms[-1]
+    mg.sweep_norms.append(norms)
     mg.rebuild(V)
     mg.null_residuals.append(float(np.median([null_residual(A, v) for v in V])))
     for _ in range(params.sweeps - 1):
         M = mg.preconditioner()
+        norms = []
         for k in range(V.shape[0]):
             x, _ = _sol.gcr_fixed(A, zero, V[k], params.sweep_iters, M=M)
-            V[k] = x / _sol.norm(x)
+            norms.append(_sol.norm(x))
+            V[k] = x / norms[-1]
+        mg.sweep_norms.append(norms)
         mg.rebuild(V)
         mg.null_residuals.append(float(np.median([null_residual(A, v) for v in V])))
     mg.V = V

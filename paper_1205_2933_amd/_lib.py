@@ -113,6 +113,7 @@ def _load() -> ctypes.CDLL:
         "mgdwf_apply_dwf": ([H, P, P, i32, ctypes.c_int, i32], ctypes.c_int),
         "mgdwf_set_nullvecs": ([H, ctypes.POINTER(i32), P, i32], ctypes.c_int),
         "mgdwf_get_basis": ([H, P], ctypes.c_int),
+        "mgdwf_get_nullvecs": ([H, P, ctypes.POINTER(i32)], ctypes.c_int),
         "mgdwf_restrict": ([H, P, P, i32, ctypes.c_int], ctypes.c_int),
         "mgdwf_prolong": ([H, P, P, i32, ctypes.c_int], ctypes.c_int),
         "mgdwf_build_coarse": ([H], ctypes.c_int),
@@ -122,6 +123,7 @@ def _load() -> ctypes.CDLL:
         "mgdwf_set_mg_params": ([H, ctypes.POINTER(mgdwf_mg_params)], ctypes.c_int),
         "mgdwf_solve": ([H, P, P, i32, ctypes.POINTER(mgdwf_solve_params), ctypes.POINTER(mgdwf_solve_report)],
                         ctypes.c_int),
+        "mgdwf_apply_vcycle": ([H, P, P, i32], ctypes.c_int),
         "mgdwf_trim": ([H], ctypes.c_int),
         "mgdwf_memory_bytes": ([H], ctypes.c_int64),
         "mgdwf_solve_batch": ([ctypes.POINTER(H), i32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i32),
@@ -133,6 +135,7 @@ def _load() -> ctypes.CDLL:
         "mgdwf_tune": ([H, i32, i32, ctypes.POINTER(mgdwf_tune_report)], ctypes.c_int),
         "mgdwf_set_tiling": ([H, i32], ctypes.c_int),
         "mgdwf_set_coarse_tiling": ([H, i32], ctypes.c_int),
+        "mgdwf_set_barrier_timeout": ([H, ctypes.c_double], ctypes.c_int),
         "mgdwf_net_create": ([ctypes.POINTER(mgdwf_net_config), ctypes.POINTER(H)], ctypes.c_int),
         "mgdwf_net_destroy": ([H], ctypes.c_int),
         "mgdwf_net_last_error": ([H], ctypes.c_char_p),
@@ -247,6 +250,16 @@ def mgdwf_set_nullvecs(h: Handle, block, V: torch.Tensor, nvec: int):
     h.block, h.nvec = tuple(block), nvec
 
 
+def mgdwf_get_nullvecs(h: Handle) -> torch.Tensor:
+    """The near-null vectors behind the installed basis, as a new device tensor."""
+    n = ctypes.c_int32()
+    _check(h.h, _lib.mgdwf_get_nullvecs(h.h, None, ctypes.byref(n)))
+    shape = (n.value,) + tuple(h.L[::-1]) + (h.Ls, 4, 3)
+    V = torch.empty(shape, dtype=torch.complex128, device="cuda")
+    _check(h.h, _lib.mgdwf_get_nullvecs(h.h, _dev(V, h.nfine * n.value, "V"), ctypes.byref(n)))
+    return V
+
+
 def mgdwf_get_basis(h: Handle, Vhat: torch.Tensor):
     _check(h.h, _lib.mgdwf_get_basis(h.h, _dev(Vhat, h.nfine * h.nvec, "Vhat")))
 
@@ -275,7 +288,7 @@ def mgdwf_apply_coarse(h: Handle, inp: torch.Tensor, out: torch.Tensor, dagger=F
     _check(h.h, _lib.mgdwf_apply_coarse(h.h, _dev(inp, n, "in"), _dev(out, n, "out"), int(dagger), PREC[prec], nrhs))
 
 
-def make_mg_params(block, nvec, sweeps=3, sweep0_iters=100, sweep_iters=4, nu_pre=4, nu_post=4,
+def make_mg_params(block, nvec, sweeps=1, sweep0_iters=100, sweep_iters=4, nu_pre=4, nu_post=4,
                    coarse_tol=0.1, coarse_maxiter=100, fine_prec="f64", coarse_prec="f64",
                    coarse_graph=True) -> mgdwf_mg_params:
     p = mgdwf_mg_params()
@@ -308,6 +321,11 @@ def mgdwf_solve(h: Handle, b: torch.Tensor, x: torch.Tensor, nrhs=1, tol=1e-10, 
                           reps)
     _check(h.h, st, allow=(MGDWF_ERR_NOT_CONVERGED,) if allow_not_converged else ())
     return [r.as_dict() for r in reps]
+
+
+def mgdwf_apply_vcycle(h: Handle, inp: torch.Tensor, out: torch.Tensor, nrhs=1):
+    n = h.nfine * nrhs
+    _check(h.h, _lib.mgdwf_apply_vcycle(h.h, _dev(inp, n, "in"), _dev(out, n, "out"), nrhs))
 
 
 def mgdwf_trim(h: Handle):
@@ -362,6 +380,10 @@ def mgdwf_tune(h: Handle, nrhs=1, iters=10) -> dict:
 
 def mgdwf_set_tiling(h: Handle, tiling_id: int):
     _check(h.h, _lib.mgdwf_set_tiling(h.h, tiling_id))
+
+
+def mgdwf_set_barrier_timeout(h: Handle, seconds: float):
+    _check(h.h, _lib.mgdwf_set_barrier_timeout(h.h, float(seconds)))
 
 
 def mgdwf_set_coarse_tiling(h: Handle, tiling_id: int):

@@ -212,7 +212,22 @@ mgdwf_status mgdwf_set_nullvecs(mgdwf_handle h, const int32_t block[4], const do
     const long long n = h->fine_len() * nvec;
     h->V64.alloc(n * sizeof(double2));
     pack_fermion_f64(reinterpret_cast<const double2*>(V), h->V64.as<double2>(), h->g, nvec, h->st);
+    h->Vnull.alloc(n * sizeof(double2));
+    MG_HIP(hipMemcpyAsync(h->Vnull.p, h->V64.p, n * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
+    h->nnull = nvec;
     install_basis(h, block, nvec);
+  });
+}
+
+mgdwf_status mgdwf_get_nullvecs(mgdwf_handle h, double* V, int32_t* n) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(n != nullptr, MGDWF_ERR_INVALID_ARG, "null count pointer");
+    need(h->have_basis && h->nnull > 0, MGDWF_ERR_STATE, "no near-null vectors: run setup or set_nullvecs first");
+    *n = h->nnull;
+    if (!V) return;
+    unpack_fermion_f64(h->Vnull.as<double2>(), reinterpret_cast<double2*>(V), h->g, h->nnull, h->st);
+    MG_HIP(hipStreamSynchronize(h->st));
   });
 }
 
@@ -364,6 +379,21 @@ mgdwf_status mgdwf_solve(mgdwf_handle h, const double* b, double* x, int32_t nrh
     if (s2 != MGDWF_OK) return s2;
   }
   return st;
+}
+
+mgdwf_status mgdwf_apply_vcycle(mgdwf_handle h, const double* in, double* out, int32_t nrhs) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(in && out && nrhs >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
+    need(h->have_coarse && h->have_params, MGDWF_ERR_STATE, "setup (or set_nullvecs + build_coarse + set_mg_params) first");
+    const long long n = h->fine_len() * nrhs;
+    double2* a = h->buf<double2>("io_a", n);
+    double2* b = h->buf<double2>("io_b", n);
+    pack_fermion_f64(reinterpret_cast<const double2*>(in), a, h->g, nrhs, h->st);
+    vcycle_apply(h, a, b, nrhs);
+    unpack_fermion_f64(b, reinterpret_cast<double2*>(out), h->g, nrhs, h->st);
+    MG_HIP(hipStreamSynchronize(h->st));
+  });
 }
 
 mgdwf_status mgdwf_trim(mgdwf_handle h) {
@@ -604,6 +634,15 @@ mgdwf_status mgdwf_tune(mgdwf_handle h, int32_t nrhs, int32_t iters, mgdwf_tune_
       rep->coarse_chosen = rep->coarse_us[1] <= 0.97 * rep->coarse_us[0] ? 1 : 0;
       h->g.ctile = rep->coarse_chosen;
     }
+  });
+}
+
+mgdwf_status mgdwf_set_barrier_timeout(mgdwf_handle h, double seconds) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(std::isfinite(seconds) && seconds >= 0.0 && seconds <= 3600.0, MGDWF_ERR_INVALID_ARG,
+         "timeout must be in [0, 3600] seconds");
+    h->barrier_wait_s = seconds;
   });
 }
 

@@ -17,7 +17,9 @@
 // Internal storage of a block: column major, element (row r, col c) of
 // Dc[X][d] at ((X * 9 + d) * n2 + c) * n2 + r, so that lane r of a wavefront
 // reads consecutive addresses for a fixed column.
-#include <hip/hip_cooperative_groups.h>
+#include <algorithm>
+
+#include <hip/hip_runtime.h>
 
 #include "mg_internal.h"
 #include "blas.h"
@@ -384,8 +386,9 @@ __global__ __launch_bounds__(576) void k_capply_mfma32(const uint16_t* __restric
 
 // ---------------------------------------------------------------- persistent coarse CGNE
 // The coarse solve (CGNE on D_c D_c^+ y = b, x = D_c^+ y, from x = 0) as one
-// cooperative launch: one workgroup per coarse site, every RHS (<= 16) at
-// once.  Per iteration: q = D_c p at the own site, then x += alpha p and
+// cooperative launch of at most one workgroup per CU; workgroup w owns the
+// coarse sites w, w + G, w + 2G, ... (G workgroups), every RHS (<= 16) at
+// once.  Per iteration: q = D_c p at each own site, then x += alpha p and
 // r -= alpha q there (alpha = |r|^2 / |p|^2), r packed to 16 bits with its
 // per-site |r|^2; grid barrier; |r|^2 summed over all sites (each workgroup
 // sums the same partials in the same order, so all take the same decision);
@@ -394,6 +397,23 @@ __global__ __launch_bounds__(576) void k_capply_mfma32(const uint16_t* __restric
 // at one of the tests after every 8th iteration (as in the launched loop), or
 // after maxiter iterations; the last iteration skips the D_c^+ apply, whose
 // result nobody reads.
+//
+// The grid barrier is this file's own: an arrival counter and a generation
+// word in device memory, agent-scope release/acquire, and a wait bounded in
+// wall-clock time.  A wait that runs out sets the error word, and every
+// workgroup that sees it leaves the kernel, so a barrier that can never
+// complete ends the launch with an error instead of hanging it.
+__global__ void k_zero_words(int* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+struct GridSync {
+  unsigned count;  // arrivals in the current generation
+  unsigned gen;    // generation, bumped by the last arrival
+  int err;         // set by a wait that ran out of time
+  int pad;
+};
+
 struct PersistArgs {
   const uint16_t *Are, *Aim, *Hre, *Him;  // 16-bit D_c and D_c^+ (the adjoint stencil)
   const float *Asc, *Hsc;
@@ -403,24 +423,57 @@ struct PersistArgs {
   float *rs, *ps;        // their per-(rhs, X) scales
   double *part_r, *part_p;  // per-(rhs, X) |.|^2
   long long* count;      // coarse applications are added here (one thread)
+  GridSync* gs;          // zeroed before the launch
+  long long wait_ticks;  // bound of one barrier wait, in wall-clock ticks
   double tol2;
   int maxiter, nrhs;
   CoarseArgs a;
 };
 
+// Every thread of every workgroup calls it; returns false (the same in every
+// thread of the workgroup) when the barrier failed and the kernel must end.
+__device__ bool grid_barrier(GridSync* gs, unsigned nblocks, long long wait_ticks, int* ok_lds) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned g = __hip_atomic_load(&gs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&gs->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const long long t0 = wall_clock64();
+      while (__hip_atomic_load(&gs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(&gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            wall_clock64() - t0 > wait_ticks) {
+          __hip_atomic_store(&gs->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    if (__hip_atomic_load(&gs->err, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+    *ok_lds = ok;
+  }
+  __syncthreads();
+  return *ok_lds != 0;
+}
+
 template <bool BF>
 __global__ __launch_bounds__(576) void k_cgne_persistent(PersistArgs q) {
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   __shared__ float red[128][17];
-  __shared__ float2 v[16][64];  // the site's new r or p, per RHS
+  __shared__ float2 v[16][64];  // the current site's new r or p, per RHS
   __shared__ double rr0[16], rr[16], pp[16], rn[16];
+  __shared__ int ok_lds;
   const CoarseArgs& a = q.a;
-  const int X = blockIdx.x, n2 = a.n2, nrhs = q.nrhs, Vc = a.Vc;
+  const int n2 = a.n2, nrhs = q.nrhs, Vc = a.Vc;
+  const int G = gridDim.x;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int ne = nrhs * n2;
-  auto at = [&](int rhs, int k) { return ((long long)rhs * Vc + X) * n2 + k; };
-  // v -> 16-bit (one scale per RHS) and |v|^2 per RHS; wave w takes RHS w, w + 9
-  auto pack_site = [&](uint16_t* xp, float* xs, double* part) {
+  auto at = [&](int rhs, int X, int k) { return ((long long)rhs * Vc + X) * n2 + k; };
+  // v -> 16-bit (one scale per RHS) at site X and |v|^2 per RHS; wave w takes RHS w, w + 9
+  auto pack_site = [&](int X, uint16_t* xp, float* xs, double* part) {
     for (int rhs = w; rhs < nrhs; rhs += 9) {
       const float2 val = l < n2 ? v[rhs][l] : make_float2(0.f, 0.f);
       float mx = fmaxf(fabsf(val.x), fabsf(val.y));
@@ -441,6 +494,7 @@ __global__ __launch_bounds__(576) void k_cgne_persistent(PersistArgs q) {
         xp[i * 2 * n2 + n2 + l] = to16<BF>(val.y * inv);
       }
     }
+    __syncthreads();  // v is rewritten for the next site
   };
   // dst[rhs] = sum over all sites of part[rhs][.], fixed order
   auto reduce_all = [&](const double* part, double* dst) {
@@ -453,51 +507,58 @@ __global__ __launch_bounds__(576) void k_cgne_persistent(PersistArgs q) {
     }
     __syncthreads();
   };
+  auto barrier = [&]() { return grid_barrier(q.gs, (unsigned)G, q.wait_ticks, &ok_lds); };
   long long napp = 0;
   // x = 0, r = b, |b|^2
-  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-    const int rhs = e / n2, k = e - rhs * n2;
-    const float2 bv = q.b[at(rhs, k)];
-    q.x[at(rhs, k)] = make_float2(0.f, 0.f);
-    q.r[at(rhs, k)] = bv;
-    v[rhs][k] = bv;
+  for (int X = blockIdx.x; X < Vc; X += G) {
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      const int rhs = e / n2, k = e - rhs * n2;
+      const float2 bv = q.b[at(rhs, X, k)];
+      q.x[at(rhs, X, k)] = make_float2(0.f, 0.f);
+      q.r[at(rhs, X, k)] = bv;
+      v[rhs][k] = bv;
+    }
+    __syncthreads();
+    pack_site(X, q.rp, q.rs, q.part_r);
   }
-  __syncthreads();
-  pack_site(q.rp, q.rs, q.part_r);
-  grid.sync();
+  if (!barrier()) return;
   reduce_all(q.part_r, rr0);
   if (threadIdx.x < nrhs) rr[threadIdx.x] = rr0[threadIdx.x];
   // p = D_c^+ r, |p|^2
-  apply_site32<BF>(q.Hre, q.Him, q.Hsc, q.rp, q.rs, a, nrhs, X, 0, red);
-  ++napp;
-  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-    const int rhs = e / n2, k = e - rhs * n2;
-    const float2 t = make_float2(red[k][rhs], red[n2 + k][rhs]);
-    q.p[at(rhs, k)] = t;
-    v[rhs][k] = t;
+  for (int X = blockIdx.x; X < Vc; X += G) {
+    apply_site32<BF>(q.Hre, q.Him, q.Hsc, q.rp, q.rs, a, nrhs, X, 0, red);
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      const int rhs = e / n2, k = e - rhs * n2;
+      const float2 t = make_float2(red[k][rhs], red[n2 + k][rhs]);
+      q.p[at(rhs, X, k)] = t;
+      v[rhs][k] = t;
+    }
+    __syncthreads();
+    pack_site(X, q.pp, q.ps, q.part_p);
   }
-  __syncthreads();
-  pack_site(q.pp, q.ps, q.part_p);
-  grid.sync();
+  ++napp;
+  if (!barrier()) return;
   reduce_all(q.part_p, pp);
   for (int it = 0; it < q.maxiter; ++it) {
     // q = D_c p; x += alpha p; r -= alpha q
-    apply_site32<BF>(q.Are, q.Aim, q.Asc, q.pp, q.ps, a, nrhs, X, 0, red);
-    ++napp;
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-      const int rhs = e / n2, k = e - rhs * n2;
-      const float alpha = (float)(pp[rhs] > 0.0 ? rr[rhs] / pp[rhs] : 0.0);
-      const long long i = at(rhs, k);
-      const float2 pv = q.p[i], xv = q.x[i], rv = q.r[i];
-      const float2 qv = make_float2(red[k][rhs], red[n2 + k][rhs]);
-      q.x[i] = make_float2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
-      const float2 rn2 = make_float2(rv.x - alpha * qv.x, rv.y - alpha * qv.y);
-      q.r[i] = rn2;
-      v[rhs][k] = rn2;
+    for (int X = blockIdx.x; X < Vc; X += G) {
+      apply_site32<BF>(q.Are, q.Aim, q.Asc, q.pp, q.ps, a, nrhs, X, 0, red);
+      for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        const int rhs = e / n2, k = e - rhs * n2;
+        const float alpha = (float)(pp[rhs] > 0.0 ? rr[rhs] / pp[rhs] : 0.0);
+        const long long i = at(rhs, X, k);
+        const float2 pv = q.p[i], xv = q.x[i], rv = q.r[i];
+        const float2 qv = make_float2(red[k][rhs], red[n2 + k][rhs]);
+        q.x[i] = make_float2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
+        const float2 rn2 = make_float2(rv.x - alpha * qv.x, rv.y - alpha * qv.y);
+        q.r[i] = rn2;
+        v[rhs][k] = rn2;
+      }
+      __syncthreads();
+      pack_site(X, q.rp, q.rs, q.part_r);
     }
-    __syncthreads();
-    pack_site(q.rp, q.rs, q.part_r);
-    grid.sync();
+    ++napp;
+    if (!barrier()) return;
     reduce_all(q.part_r, rn);
     // the launched loop's schedule: the residual is tested after every 8th
     // iteration (the same decision in every workgroup)
@@ -507,24 +568,26 @@ __global__ __launch_bounds__(576) void k_cgne_persistent(PersistArgs q) {
       if (!(rn[rhs] <= q.tol2 * rr0[rhs])) done = false;
     if (done || n == q.maxiter) break;
     // t = D_c^+ r; p = t + beta p
-    apply_site32<BF>(q.Hre, q.Him, q.Hsc, q.rp, q.rs, a, nrhs, X, 0, red);
-    ++napp;
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-      const int rhs = e / n2, k = e - rhs * n2;
-      const float beta = (float)(rr[rhs] > 0.0 ? rn[rhs] / rr[rhs] : 0.0);
-      const long long i = at(rhs, k);
-      const float2 pv = q.p[i];
-      const float2 t = make_float2(red[k][rhs] + beta * pv.x, red[n2 + k][rhs] + beta * pv.y);
-      q.p[i] = t;
-      v[rhs][k] = t;
+    for (int X = blockIdx.x; X < Vc; X += G) {
+      apply_site32<BF>(q.Hre, q.Him, q.Hsc, q.rp, q.rs, a, nrhs, X, 0, red);
+      for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        const int rhs = e / n2, k = e - rhs * n2;
+        const float beta = (float)(rr[rhs] > 0.0 ? rn[rhs] / rr[rhs] : 0.0);
+        const long long i = at(rhs, X, k);
+        const float2 pv = q.p[i];
+        const float2 t = make_float2(red[k][rhs] + beta * pv.x, red[n2 + k][rhs] + beta * pv.y);
+        q.p[i] = t;
+        v[rhs][k] = t;
+      }
+      __syncthreads();
+      pack_site(X, q.pp, q.ps, q.part_p);
     }
-    __syncthreads();
+    ++napp;
     if (threadIdx.x < nrhs) rr[threadIdx.x] = rn[threadIdx.x];
-    pack_site(q.pp, q.ps, q.part_p);
-    grid.sync();
+    if (!barrier()) return;
     reduce_all(q.part_p, pp);
   }
-  if (X == 0 && threadIdx.x == 0) *q.count += napp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *q.count += napp;
 }
 
 }  // namespace
@@ -630,27 +693,44 @@ void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, floa
 
 size_t persistent_cgne_bytes(const CoarseGeometry& cg, int nrhs) {
   const size_t nsv = (size_t)nrhs * cg.Vc;
-  return 2 * nsv * 2 * cg.n2 * sizeof(uint16_t) + 2 * nsv * sizeof(float) + 2 * nsv * sizeof(double) + 6 * 256;
+  return 2 * nsv * 2 * cg.n2 * sizeof(uint16_t) + 2 * nsv * sizeof(float) + 2 * nsv * sizeof(double) +
+         sizeof(GridSync) + 7 * 256;
+}
+
+// Workgroups of k_cgne_persistent that one CU can hold at once, from the
+// kernel's own register and LDS use: 576 threads are 9 wavefronts spread
+// over the 4 SIMDs (3 on the fullest), each SIMD holds 512 VGPRs per lane
+// (granule 8) and a CU 160 KB of LDS.
+static int persistent_fit_per_cu(const void* fn) {
+  hipFuncAttributes at{};
+  MG_HIP(hipFuncGetAttributes(&at, fn));
+  const int vgpr = std::max(8, (at.numRegs + 7) / 8 * 8);
+  const int waves_per_simd = 512 / vgpr;
+  const int by_vgpr = waves_per_simd / 3;  // the fullest SIMD carries 3 wavefronts of each workgroup
+  const int by_lds = at.sharedSizeBytes > 0 ? (int)((160 * 1024) / at.sharedSizeBytes) : 64;
+  return std::min(by_vgpr, by_lds);
 }
 
 bool coarse_cgne_persistent(const CoarseStore& D, const CoarseStore& DH, mgdwf_prec prec, const float2* b, float2* x,
                             float2* r, float2* p, void* work, long long* count, const CoarseGeometry& cg, int nrhs,
-                            double tol, int maxiter, int device, hipStream_t st) {
+                            double tol, int maxiter, double wait_seconds, int device, hipStream_t st) {
   if (!(prec == MGDWF_F16 || prec == MGDWF_BF16) || cg.n2 % 16 || cg.n2 > 64 || nrhs < 1 || nrhs > 16 ||
       maxiter < 1)
     return false;
   const bool bf = prec == MGDWF_BF16;
   const void* fn = bf ? reinterpret_cast<const void*>(&k_cgne_persistent<true>)
                       : reinterpret_cast<const void*>(&k_cgne_persistent<false>);
-  int coop = 0, ncu = 0, per_cu = 0;
+  int coop = 0, ncu = 0, per_cu = 0, clock_khz = 0;
   MG_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device));
   MG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
+  MG_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device));
   MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 576, 0));
-  // One workgroup per CU at most: the grid of one workgroup per coarse site
-  // must fit the CUs.  Two per CU (512 sites of a 16^3x32 lattice with 4^4
-  // blocks on 256 CUs) did not finish once, for a reason not found; that
-  // configuration is not used.
-  if (!coop || per_cu < 1 || cg.Vc > ncu) return false;
+  // At most one workgroup per CU, whatever the occupancy query says: the
+  // kernel takes about 140 VGPRs, so a SIMD holds 3 wavefronts and a CU one
+  // 9-wavefront workgroup; a grid of two workgroups per CU can never be
+  // resident at once and its first grid barrier would wait for ever.
+  if (!coop || per_cu < 1 || persistent_fit_per_cu(fn) < 1 || clock_khz <= 0) return false;
+  const int G = std::min(cg.Vc, ncu);
   const size_t nsv = (size_t)nrhs * cg.Vc;
   char* w = static_cast<char*>(work);
   auto take = [&](size_t bytes) {
@@ -675,14 +755,32 @@ bool coarse_cgne_persistent(const CoarseStore& D, const CoarseStore& DH, mgdwf_p
   q.ps = reinterpret_cast<float*>(take(nsv * sizeof(float)));
   q.part_r = reinterpret_cast<double*>(take(nsv * sizeof(double)));
   q.part_p = reinterpret_cast<double*>(take(nsv * sizeof(double)));
+  q.gs = reinterpret_cast<GridSync*>(take(sizeof(GridSync)));
   q.count = count;
+  q.wait_ticks = (long long)(std::max(0.0, wait_seconds) * 1e3 * clock_khz);
   q.tol2 = tol * tol;
   q.maxiter = maxiter;
   q.nrhs = nrhs;
   q.a = coarse_args(cg);
+  // the barrier words start from zero (a fill kernel, not a memset node, so
+  // the sequence stays valid inside a captured graph)
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, reinterpret_cast<int*>(q.gs),
+                     (int)(sizeof(GridSync) / sizeof(int)));
+  MG_LAUNCH_CHECK();
   void* args[] = {&q};
-  MG_HIP(hipLaunchCooperativeKernel(fn, dim3(cg.Vc), dim3(576), args, 0, st));
+  MG_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(576), args, 0, st));
   return true;
+}
+
+int persistent_cgne_error(const void* work, const CoarseGeometry& cg, int nrhs, hipStream_t st) {
+  const size_t nsv = (size_t)nrhs * cg.Vc;
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t off = 2 * up(nsv * 2 * cg.n2 * sizeof(uint16_t)) + 2 * up(nsv * sizeof(float)) +
+                     2 * up(nsv * sizeof(double));
+  GridSync h{};
+  MG_HIP(hipMemcpyAsync(&h, static_cast<const char*>(work) + off, sizeof h, hipMemcpyDeviceToHost, st));
+  MG_HIP(hipStreamSynchronize(st));
+  return h.err;
 }
 
 }  // namespace mgdwf

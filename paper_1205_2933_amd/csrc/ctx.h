@@ -20,6 +20,8 @@ struct mgdwf_ctx {
   mgdwf::CoarseGeometry cg{};
   bool have_basis = false, have_coarse = false;
   mgdwf::DevBuf V64, V32;    // orthonormal basis, Nv fields
+  mgdwf::DevBuf Vnull;       // the near-null vectors the basis was built from (FP64, internal layout)
+  int nnull = 0;             // how many: nvec/2 after a setup, nvec after set_nullvecs
   mgdwf::CoarseStore Dc, DcH;  // coarse operator and its adjoint stencil, all precisions
 
   mgdwf_mg_params mp{};
@@ -81,6 +83,8 @@ struct mgdwf_ctx {
   long long fine_applies = 0;    // per right-hand side, since the last reset
   long long coarse_applies = 0;
   long long gs_repeats = 0;      // flexible-GCR steps that needed a second Gram-Schmidt pass
+  long long persist_fallbacks = 0;  // coarse solves where the persistent kernel was asked for but did not apply
+  double barrier_wait_s = 10.0;  // bound of one grid-barrier wait in the persistent coarse kernel
 
   // Workspace `name` with room for `count` elements of T (contents undefined).
   template <class T>

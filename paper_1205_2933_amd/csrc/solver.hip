@@ -269,13 +269,18 @@ struct TwoLevel {
   }
 
   void coarse_solve(const F2* b, F2* x) {
-    if constexpr (std::is_same<F2, float2>::value) {
-      if (p.coarse_graph == 2 &&
-          coarse_cgne_persistent(c->Dc, c->DcH, p.coarse_prec, b, x, cr, cp,
-                                 c->buf<char>("cg_persist", persistent_cgne_bytes(c->cg, nrhs)),
-                                 c->buf<long long>("cg_count", 1), c->cg, nrhs, p.coarse_tol, p.coarse_maxiter,
-                                 c->device, c->st))
-        return;
+    if (p.coarse_graph == 2) {
+      if constexpr (std::is_same<F2, float2>::value) {
+        char* work = c->buf<char>("cg_persist", persistent_cgne_bytes(c->cg, nrhs));
+        if (coarse_cgne_persistent(c->Dc, c->DcH, p.coarse_prec, b, x, cr, cp, work,
+                                   c->buf<long long>("cg_count", 1), c->cg, nrhs, p.coarse_tol, p.coarse_maxiter,
+                                   c->barrier_wait_s, c->device, c->st)) {
+          if (persistent_cgne_error(work, c->cg, nrhs, c->st))
+            fail(MGDWF_ERR_HIP, "persistent coarse solve: a grid barrier wait ran out of time");
+          return;
+        }
+      }
+      ++c->persist_fallbacks;  // not applicable here: the launched loop below
     }
     copy(c, b, cr, nc * nrhs);
     norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR0);
@@ -446,7 +451,7 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
   F2* rin = c->buf<F2>(std::string("sol_rin") + Prec<F2>::tag, nf * nrhs);
   F2* e = c->buf<F2>(std::string("sol_e") + Prec<F2>::tag, nf * nrhs);
   TwoLevel<F2> M(c, nrhs, c->mp);
-  const long long fa0 = c->fine_applies, ca0 = c->coarse_applies, gs0 = c->gs_repeats;
+  const long long fa0 = c->fine_applies, ca0 = c->coarse_applies, gs0 = c->gs_repeats, pf0 = c->persist_fallbacks;
   c->harvest_phases();
   const double ph0[3] = {c->phase_s[0], c->phase_s[1], c->phase_s[2]};
   long long* pcount = c->buf<long long>("cg_count", 1);  // applications made by persistent coarse solves
@@ -499,6 +504,7 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
   }
   double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (c->gs_repeats > gs0) flags |= 4u;
+  if (c->persist_fallbacks > pf0) flags |= 8u;
   if (rep)
     for (int r = 0; r < nrhs; ++r) {
       rep[r].outer_iters = outer;
@@ -511,6 +517,23 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
       for (int k = 0; k < 3; ++k) rep[r].phase_seconds[k] = c->phase_s[k] - ph0[k];
     }
   if (!converged) fail(MGDWF_ERR_NOT_CONVERGED, "solve did not reach the requested tolerance");
+}
+
+void vcycle_apply(mgdwf_ctx* c, const double2* b64, double2* z64, int nrhs) {
+  const long long n = c->fine_len() * nrhs;
+  c->buf<double>("slots", (size_t)nrhs * NSLOT);
+  if (c->mp.fine_prec == MGDWF_F64) {
+    TwoLevel<double2> M(c, nrhs, c->mp);
+    M.apply(b64, z64);
+  } else {
+    float2* b32 = c->buf<float2>("vca_b32", n);
+    float2* z32 = c->buf<float2>("vca_z32", n);
+    convert<double2, float2>(b64, b32, n, c->st);
+    TwoLevel<float2> M(c, nrhs, c->mp);
+    M.apply(b32, z32);
+    convert<float2, double2>(z32, z64, n, c->st);
+  }
+  c->harvest_phases();
 }
 
 void mg_solve(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const mgdwf_solve_params& sp,
@@ -598,19 +621,27 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
   sweep.fine_prec = MGDWF_F64;
   sweep.coarse_prec = MGDWF_F64;
   for (int s = 1; s < p.sweeps; ++s) {
-    // inverse iteration: W <- (approximately) D^{-1} W with the current MG
+    // the multigrid applied to the same problem (Sec. 2, adaptive setup):
+    // sweep_iters flexible-GCR steps with the current V-cycle on D x = 0 from
+    // x = W, i.e. e from 0 on D e = -D W and then W <- W + e, so W keeps what
+    // the current multigrid fails to remove; then normalise and rebuild
     TwoLevel<double2> M(c, nh, sweep);
     double2* r = c->buf<double2>("setup_r", nf * nh);
     double2* e = c->buf<double2>("setup_e", nf * nh);
-    copy(c, W, r, nf * nh);
-    std::vector<double> stop2(nh, -1.0);
+    double2* z = c->buf<double2>("setup_zero", nf * nh);
+    zero<double2>(z, nf * nh, c->st);
+    fine_op<double2>(c, W, r, z, false, 1, nh, -1);  // r = 0 - D W
+    std::vector<double> stop2(nh, -1.0);             // never met: exactly sweep_iters steps
     fgcr_cycle<double2>(c, M, r, e, nh, std::max(1, std::min(p.sweep_iters, 16)), stop2, nullptr);
-    copy(c, e, W, nf * nh);
+    add_to<double2, double2>(W, e, nf * nh, c->st);
     normalise(c, W, nh);
     rebuild();
     if (rep && nsw < 8) rep->null_residual[nsw] = median_null_residual(c, W, nh);
     ++nsw;
   }
+  c->Vnull.alloc(nf * nh * sizeof(double2));
+  copy(c, W, c->Vnull.as<double2>(), nf * nh);
+  c->nnull = nh;
   c->mp = p;
   c->have_params = true;
   // the setup's work fields are large (several per vector): give them back

@@ -82,14 +82,18 @@ void coarse_apply32(const CoarseStore& s, mgdwf_prec prec, const float2* x, floa
                     int nrhs, void* pack, int ctile, hipStream_t st);
 // Coarse CGNE (x = D_c^+ y, D_c D_c^+ y = b, from x = 0, to |r| <= tol |b| tested
 // every 8 iterations, or maxiter iterations) as one persistent cooperative
-// launch on the 16-bit store;
+// launch on the 16-bit store, at most one workgroup per CU, each owning
+// every G-th coarse site;
 // r and p are workspaces of the vector size, work holds persistent_cgne_bytes,
-// and the coarse applications it makes are added to *count (device).  Returns
-// false, launching nothing, where it does not apply (precision, nrhs > 16, or
-// more coarse sites than CUs: one workgroup per site, at most one per CU).
+// and the coarse applications it makes are added to *count (device).  Its
+// grid barriers wait at most wait_seconds each; persistent_cgne_error (which
+// synchronises the stream) is nonzero after a launch whose barrier ran out.
+// Returns false, launching nothing, where it does not apply (precision,
+// nrhs > 16, no cooperative launch).
 size_t persistent_cgne_bytes(const CoarseGeometry& cg, int nrhs);
 bool coarse_cgne_persistent(const CoarseStore& D, const CoarseStore& DH, mgdwf_prec prec, const float2* b, float2* x,
                             float2* r, float2* p, void* work, long long* count, const CoarseGeometry& cg, int nrhs,
-                            double tol, int maxiter, int device, hipStream_t st);
+                            double tol, int maxiter, double wait_seconds, int device, hipStream_t st);
+int persistent_cgne_error(const void* work, const CoarseGeometry& cg, int nrhs, hipStream_t st);
 
 }  // namespace mgdwf

@@ -127,3 +127,57 @@ def test_dslash_f32_every_tiling(cuda):
     with pytest.raises(mg.MgdwfError):
         mg.mgdwf_set_tiling(h, 10 ** 6)
     mg.mgdwf_set_tiling(h, -1)
+
+
+@pytest.mark.parametrize("dagger", [False, True])
+def test_dslash_f32_production_launch_ls16(cuda, dagger):
+    """The FP32 launch the production solve uses: Ls = 16 on the default
+    t-march tiling (4x4x2 sites per workgroup, 8 threads per 4D site), two
+    right-hand sides, against the FP64 oracle at the FP32 bar."""
+    import paper_1205_2933_amd as mg
+    L, Ls, mf = (8, 8, 4, 4), 16, 0.001
+    U = prepare_gauge(L, 0.3, 12, ape_steps=2)
+    psi = gaussian_fermion(L, Ls, 77, n=2)
+    h = mg.Handle(L, Ls, 1.8, mf)
+    mg.mgdwf_set_gauge(h, dev(U))
+    out = torch.empty_like(dev(psi))
+    mg.mgdwf_apply_dwf(h, dev(psi), out, dagger=dagger, prec="f32", nrhs=2)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    for r in range(2):
+        assert rel(o[r], dwf.apply_dwf(psi[r], U, 1.8, mf, dagger=dagger)) < 2e-6
+
+
+def _integer_inputs(L, Ls, seed, n=1):
+    """Links and fields with small Gaussian-integer entries (re, im in -2..2)."""
+    rng = np.random.default_rng(seed)
+    from inputs import fermion_shape, gauge_shape
+    U = rng.integers(-1, 2, gauge_shape(L)) + 1j * rng.integers(-1, 2, gauge_shape(L))
+    shp = ((n,) if n > 1 else ()) + fermion_shape(L, Ls)
+    psi = rng.integers(-2, 3, shp) + 1j * rng.integers(-2, 3, shp)
+    return U.astype(np.complex128), psi.astype(np.complex128)
+
+
+@pytest.mark.parametrize("case", [((4, 4, 4, 4), 8, (1, 1, 1, 1)), ((2, 2, 2, 2), 4, (1, 1, 1, 1)),
+                                  ((6, 4, 2, 8), 5, (1, -1, 1, -1)), ((8, 8, 4, 4), 16, (1, 1, 1, -1))],
+                         ids=lambda c: f"L{'x'.join(map(str, c[0]))}_Ls{c[1]}")
+def test_dslash_integer_inputs_are_bit_exact(cuda, case):
+    """Site and neighbour indexing, bit for bit: with Gaussian-integer links and
+    fields, M5 = 1 and m_f = 1/2 every intermediate of D (and D^+) is a small
+    dyadic number, exact in FP64 and FP32 whatever the summation order, so the
+    GPU output must equal the oracle's exactly (extent 2, where x+mu == x-mu
+    and both hops apply, included)."""
+    import paper_1205_2933_amd as mg
+    L, Ls, bc = case
+    U, psi = _integer_inputs(L, Ls, 5, n=2)
+    h = mg.Handle(L, Ls, 1.0, 0.5, bc)
+    mg.mgdwf_set_gauge(h, dev(U))
+    for prec in ("f64", "f32"):
+        for dagger in (False, True):
+            out = torch.empty_like(dev(psi))
+            mg.mgdwf_apply_dwf(h, dev(psi), out, dagger=dagger, prec=prec, nrhs=2)
+            torch.cuda.synchronize()
+            o = out.cpu().numpy()
+            for r in range(2):
+                ref = dwf.apply_dwf(psi[r], U, 1.0, 0.5, bc, dagger=dagger)
+                assert np.array_equal(o[r], ref), (prec, dagger, r, np.abs(o[r] - ref).max())

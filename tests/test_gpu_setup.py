@@ -1,0 +1,88 @@
+"""GPU adaptive setup against the oracle's (paper Sec. 2, adaptive setup).
+
+Sweep 0 runs CG on D^+D v = 0 from seeded random starts; every later sweep
+applies the multigrid built from the current vectors to D x = 0 from each
+vector and keeps what it fails to remove.  The expected values were written
+by tests/golden/make_setup_golden.py, which calls only the oracle: the median
+null residual |D v|/|v| after every sweep and |D v|/|v| of every final vector.
+Both sides run the V-cycle's coarse CGNE for exactly 16 iterations (a
+tolerance never met), so their V-cycles are the same map and the whole setup
+agrees up to FP64 rounding.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from inputs import prepare_gauge, random_starts
+from oracle import dwf
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "setup_sweeps.json")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("case", [c["name"] for c in _golden()["cases"]])
+def test_setup_sweeps_match_oracle(cuda, case):
+    import paper_1205_2933_amd as mg
+    gold = _golden()
+    c = gold["common"]
+    g = next(x for x in gold["cases"] if x["name"] == case)
+    L, Ls = tuple(c["L"]), c["Ls"]
+    U = prepare_gauge(L, c["eps"], c["gauge_seed"])
+    h = mg.Handle(L, Ls, c["M5"], c["mf"])
+    mg.mgdwf_set_gauge(h, dev(U))
+    p = mg.make_mg_params(tuple(c["block"]), g["nvec"], sweeps=g["sweeps"], sweep0_iters=g["sweep0_iters"],
+                          sweep_iters=g["sweep_iters"], nu_pre=c["nu_pre"], nu_post=c["nu_post"],
+                          coarse_tol=c["coarse_tol"], coarse_maxiter=c["coarse_maxiter"], fine_prec="f64",
+                          coarse_prec="f64")
+    print(f"setup {case}", flush=True)
+    rep = mg.mgdwf_setup(h, p, dev(random_starts(L, Ls, g["nvec"] // 2, c["start_seed"])))
+    print("gpu", rep["null_residual"], "oracle", g["null_residuals"], flush=True)
+    assert rep["sweeps_done"] == g["sweeps"]
+    for a, b in zip(rep["null_residual"], g["null_residuals"]):
+        assert abs(a - b) <= 1e-8 * b, (a, b)
+    # the vectors themselves: each one's |D v|/|v| (computed with the oracle's D)
+    V = mg.mgdwf_get_nullvecs(h).cpu().numpy()
+    assert V.shape[0] == g["nvec"] // 2
+    per = [float(np.linalg.norm(dwf.apply_dwf(v, U, c["M5"], c["mf"])) / np.linalg.norm(v)) for v in V]
+    print("per vector", per, g["final_per_vector"], flush=True)
+    for a, b in zip(per, g["final_per_vector"]):
+        assert abs(a - b) <= 1e-8 * b, (a, b)
+    for v in V:
+        assert abs(np.linalg.norm(v) - 1.0) < 1e-12
+    # the basis installed is the block QR of the vectors and their reflections
+    from oracle import setup as osu
+    from oracle import transfer as ot
+    Vh = torch.empty((g["nvec"],) + V.shape[1:], dtype=torch.complex128, device="cuda")
+    mg.mgdwf_get_basis(h, Vh)
+    ref = ot.build_basis(osu.reflect_pairs(V), tuple(c["block"]))
+    assert np.linalg.norm(Vh.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-10
+    h.close()
+
+
+def test_default_setup_is_the_tested_path(cuda):
+    """The binding's default parameters run one sweep (the path the golden
+    cases cover as their sweep 0); get_nullvecs after set_nullvecs returns
+    exactly the vectors given."""
+    import paper_1205_2933_amd as mg
+    assert mg.make_mg_params((2, 2, 2, 2), 8).sweeps == 1
+    L, Ls = (4, 4, 4, 4), 4
+    h = mg.Handle(L, Ls, 1.8, 0.01)
+    mg.mgdwf_set_gauge(h, dev(prepare_gauge(L, 0.3, 11)))
+    V = random_starts(L, Ls, 6, 5)
+    mg.mgdwf_set_nullvecs(h, (2, 2, 2, 2), dev(V), 6)
+    back = mg.mgdwf_get_nullvecs(h).cpu().numpy()
+    assert np.array_equal(back, V)
+    h.close()

@@ -206,3 +206,113 @@ def test_persistent_coarse_solve(cuda, cprec):
         r = bk - dwf.apply_dwf(xh[k], U, 1.8, mf)
         assert np.linalg.norm(r) / np.linalg.norm(bk) < 1e-10
         assert reps[k]["true_relres"] < 1e-10
+
+
+# One V-cycle application M(b) against the oracle's TwoLevel (paper Sec. 2,
+# the five steps), coarse CGNE fixed at 16 iterations on both sides.  FP64:
+# the same map up to rounding.  FP32 fine level: unit roundoff 6e-8 through
+# 2 x 4 MR steps (8 Dslash pairs with their step lengths) and the coarse
+# Krylov iterations; the measured error is a few 1e-7, the bar 1e-5.  16-bit
+# D_c: each coarse application carries the storage error of the 2^-11 (FP16)
+# or 2^-8 (BF16) mantissa, which 16 CGNE iterations carry into the coarse
+# correction (the bulk of M(b)); the bar is 50 unit roundoffs.
+VCYCLE_TOL = {("f64", "f64"): 1e-10, ("f32", "f32"): 1e-5, ("f32", "f16"): 50 * 2.0 ** -11,
+              ("f32", "bf16"): 50 * 2.0 ** -8}
+
+
+@pytest.mark.parametrize("prec,cprec", list(VCYCLE_TOL))
+def test_vcycle_application_matches_oracle(cuda, prec, cprec):
+    import paper_1205_2933_amd as mg
+    from oracle import setup as osu
+    L, Ls, mf, block = (4, 4, 4, 4), 8, 0.01, (2, 2, 2, 2)
+    U = prepare_gauge(L, 0.3, 11)
+    A = dwf.DWF(U, 1.8, mf)
+    V = random_starts(L, Ls, 8, 41)
+    prm = osu.MGParams(block=block, nvec=16, nu_pre=4, nu_post=4, smoother="mr_normal", coarse_solver="cgne",
+                       coarse_tol=1e-30, coarse_maxiter=16)
+    omg = osu.MG(A, prm)
+    omg.rebuild(V)
+    M = omg.preconditioner()
+    b = gaussian_fermion(L, Ls, 31, n=2)
+    want = np.stack([M(b[r]) for r in range(2)])
+    h = mg.Handle(L, Ls, 1.8, mf)
+    mg.mgdwf_set_gauge(h, dev(U))
+    mg.mgdwf_set_nullvecs(h, block, dev(osu.reflect_pairs(V)), 16)
+    mg.mgdwf_build_coarse(h)
+    mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, nu_pre=4, nu_post=4, coarse_tol=1e-30, coarse_maxiter=16,
+                                                fine_prec=prec, coarse_prec=cprec))
+    z = torch.empty_like(dev(b))
+    mg.mgdwf_apply_vcycle(h, dev(b), z, nrhs=2)
+    got = z.cpu().numpy()
+    for r in range(2):
+        e = np.linalg.norm(got[r] - want[r]) / np.linalg.norm(want[r])
+        print(f"V-cycle {prec}/{cprec} rhs {r}: {e:.3e}", flush=True)
+        assert e < VCYCLE_TOL[(prec, cprec)]
+    h.close()
+
+
+def test_persistent_coarse_solve_several_sites_per_workgroup(cuda):
+    """512 coarse sites (8^3x16 with 2^4 blocks) on a GPU of 256 CUs: the
+    persistent coarse CGNE runs one workgroup per CU, each owning two coarse
+    sites, and the solve agrees with the graph path (same outer iterations up
+    to rounding, both to 1e-10 against the oracle's D).  The report flags no
+    fallback to the launched loop."""
+    import paper_1205_2933_amd as mg
+    L, Ls, mf, block = (8, 8, 8, 16), 4, 0.01, (2, 2, 2, 2)
+    U = prepare_gauge(L, 0.3, 14, ape_steps=2)
+    h = mg.Handle(L, Ls, 1.8, mf)
+    mg.mgdwf_set_gauge(h, dev(U))
+    kw = dict(sweeps=1, sweep0_iters=100, sweep_iters=4, coarse_tol=0.1, coarse_maxiter=200, fine_prec="f32",
+              coarse_prec="f16")
+    mg.mgdwf_setup(h, mg.make_mg_params(block, 16, coarse_graph=True, **kw), dev(random_starts(L, Ls, 8, 21)))
+    b = gaussian_fermion(L, Ls, 31, n=2)
+    out = {}
+    for mode in (True, "persistent"):
+        mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, coarse_graph=mode, **kw))
+        x = torch.zeros_like(dev(b))
+        print(f"512-site solve mode={mode}", flush=True)
+        reps = mg.mgdwf_solve(h, dev(b), x, nrhs=2, tol=1e-10, max_outer=400, restart=8)
+        print("report", reps[0], flush=True)
+        assert not (reps[0]["flags"] & 8)
+        out[mode] = (reps[0]["outer_iters"], x.cpu().numpy())
+    assert abs(out[True][0] - out["persistent"][0]) <= 8
+    xs = out["persistent"][1]
+    for k in range(2):
+        r = b[k] - dwf.apply_dwf(xs[k], U, 1.8, mf)
+        assert np.linalg.norm(r) / np.linalg.norm(b[k]) < 1e-10
+    h.close()
+
+
+def test_persistent_barrier_timeout_is_an_error_not_a_hang(cuda):
+    """A grid-barrier wait bounded at zero seconds runs out at once (the
+    condition is forced from the host, every workgroup still leaves the kernel
+    normally): the solve returns MGDWF_ERR_HIP with a message, and with the
+    default bound restored the same handle solves again.  Where the persistent
+    kernel does not apply (FP16 asked at FP64) nothing changes; where it is
+    asked for an FP32 coarse store, the report's fallback bit is set."""
+    import paper_1205_2933_amd as mg
+    L, Ls, mf, block = (4, 4, 4, 4), 8, 0.01, (2, 2, 2, 2)
+    U = prepare_gauge(L, 0.3, 11)
+    h = mg.Handle(L, Ls, 1.8, mf)
+    mg.mgdwf_set_gauge(h, dev(U))
+    kw = dict(sweeps=1, sweep0_iters=100, sweep_iters=4, coarse_tol=0.1, coarse_maxiter=200, fine_prec="f32")
+    mg.mgdwf_setup(h, mg.make_mg_params(block, 16, coarse_prec="f16", **kw), dev(random_starts(L, Ls, 8, 21)))
+    b = dev(gaussian_fermion(L, Ls, 31))
+    mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, coarse_graph="persistent", coarse_prec="f16", **kw))
+    mg.mgdwf_set_barrier_timeout(h, 0.0)
+    x = torch.zeros_like(b)
+    with pytest.raises(mg.MgdwfError) as e:
+        mg.mgdwf_solve(h, b, x, tol=1e-10, max_outer=400, restart=8)
+    assert e.value.status == mg.MGDWF_ERR_HIP and "barrier" in str(e.value)
+    mg.mgdwf_set_barrier_timeout(h, 10.0)
+    x = torch.zeros_like(b)
+    reps = mg.mgdwf_solve(h, b, x, tol=1e-10, max_outer=400, restart=8)
+    assert reps[0]["true_relres"] < 1e-10 and not (reps[0]["flags"] & 8)
+    # an FP32 coarse store has no persistent kernel: the launched loop, flagged
+    mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, coarse_graph="persistent", coarse_prec="f32", **kw))
+    x = torch.zeros_like(b)
+    reps = mg.mgdwf_solve(h, b, x, tol=1e-10, max_outer=400, restart=8)
+    assert reps[0]["true_relres"] < 1e-10 and (reps[0]["flags"] & 8)
+    with pytest.raises(mg.MgdwfError):
+        mg.mgdwf_set_barrier_timeout(h, -1.0)
+    h.close()

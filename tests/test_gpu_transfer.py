@@ -31,8 +31,20 @@ CASES = [
 LOWP_TOL = {"f16": 3e-3, "bf16": 2.5e-2}
 
 
+# per coarse site the relative error may exceed the global one where a site's
+# output is smaller than average; the bound allows that much and no more
+SITE_FACTOR = 4.0
+
+
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def site_max_rel(got, want):
+    """max over coarse sites of |got(X) - want(X)| / |want(X)| (all 2 Nv components of a site)."""
+    g = got.reshape(-1, got.shape[-2] * got.shape[-1])
+    w = want.reshape(g.shape)
+    return float(np.max(np.linalg.norm(g - w, axis=1) / np.linalg.norm(w, axis=1)))
 
 
 def rel(a, b):
@@ -156,7 +168,12 @@ def test_coarse_operator_matches_oracle(cuda, case):
             y = torch.empty_like(dev(c))
             mg.mgdwf_apply_coarse(h, dev(c), y, dagger=dagger, prec=prec)
             torch.cuda.synchronize()
-            assert rel(y.cpu().numpy(), oc.apply_coarse(c, ref, dagger=dagger)) < tol, (dagger, prec, ct)
+            got, want = y.cpu().numpy(), oc.apply_coarse(c, ref, dagger=dagger)
+            assert rel(got, want) < tol, (dagger, prec, ct)
+            # site by site: no single coarse site may hide a larger error
+            worst = site_max_rel(got, want)
+            print(f"{prec} ct={ct} dagger={dagger} global {rel(got, want):.2e} worst site {worst:.2e}", flush=True)
+            assert worst < SITE_FACTOR * tol, (dagger, prec, ct, worst)
     mg.mgdwf_set_coarse_tiling(h, -1)
     with pytest.raises(mg.MgdwfError):
         mg.mgdwf_set_coarse_tiling(h, 2)
@@ -187,6 +204,7 @@ def test_coarse_apply_many_rhs(cuda):
             got = y.cpu().numpy()
             for r in range(nr):
                 assert rel(got[r], want[r]) < tol, (dagger, prec, ct, r)
+                assert site_max_rel(got[r], want[r]) < SITE_FACTOR * tol, (dagger, prec, ct, r)
     # the tuner times both shapes once a coarse operator exists
     rep = mg.mgdwf_tune(h, nrhs=nr, iters=2)
     assert rep["coarse_chosen"] in (0, 1) and len(rep["coarse_us"]) == 2
