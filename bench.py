@@ -69,28 +69,32 @@ def mem(tag):
         f"torch reserved {torch.cuda.memory_reserved() / 2**30:.1f} GiB")
 
 
-def mg_params(mg, fine, coarse):
+def mg_params(mg, fine, coarse, coarse_graph=True):
     return mg.make_mg_params(BLOCK, NVEC, sweeps=1, sweep0_iters=400, sweep_iters=4, nu_pre=12, nu_post=12,
-                             coarse_tol=0.1, coarse_maxiter=400, fine_prec=fine, coarse_prec=coarse)
+                             coarse_tol=0.1, coarse_maxiter=400, fine_prec=fine, coarse_prec=coarse,
+                             coarse_graph=coarse_graph)
 
 
-def cpu_baseline(counts):
+def cpu_baseline(counts, x_mixed, b_mixed):
     """Oracle (numpy FP64) per-operation times on this host, combined with the GPU
-    run's per-RHS operation counts into seconds per RHS solve (extrapolated)."""
+    run's per-RHS operation counts into seconds per RHS solve (extrapolated).
+    The oracle's Dslash is timed on the first mixed-precision solution of the
+    timed step, which also gives the oracle's own |b - D x| / |b| of that GPU
+    solution at the production shape."""
     import numpy as np
 
-    from inputs import gaussian_fermion, random_starts, random_su3_field
+    from inputs import gaussian_fermion, random_starts
     from oracle import coarse as oc
     from oracle import dwf
     from oracle import transfer as ot
 
     cpu0, wall0 = time.process_time(), time.perf_counter()
-    U = random_su3_field(L, 0.3, 12)
-    psi = gaussian_fermion(L, LS, 1)
+    U = prepare_main_gauge()
     t = time.perf_counter()
-    dwf.apply_dwf(psi, U, M5, MF)
+    Dx = dwf.apply_dwf(x_mixed, U, M5, MF)
     t_dslash = time.perf_counter() - t
-    del psi
+    oracle_relres = float(np.linalg.norm(b_mixed - Dx) / np.linalg.norm(b_mixed))
+    del Dx
     # R and P are block local: time them on one eighth of the lattice (16^3 x 4) and scale by 8
     Ls_ = (16, 16, 16, 4)
     V = random_starts(Ls_, LS, NVEC, 21)
@@ -119,7 +123,15 @@ def cpu_baseline(counts):
         "sample": (f"oracle Dslash at full size ({t_dslash:.2f} s), R/P on a 16^3x4x16 slab x8 ({t_r:.2f}/{t_p:.2f} s), "
                    f"coarse apply ({t_c:.3f} s), times the GPU per-RHS counts: {counts['fine']} D applications, "
                    f"{counts['vcycles']} V-cycles, {counts['coarse']} coarse applications"),
+        "oracle_check": {"true_relres_of_gpu_solution": oracle_relres,
+                         "note": "|b - D x| / |b| of the first mixed-precision solution of the timed step, "
+                                 "D applied by the oracle (FP64, numpy) on the host"},
     }
+
+
+def prepare_main_gauge():
+    from inputs import prepare_gauge
+    return prepare_gauge(L, 0.3, 12, ape_steps=2)
 
 
 def ragged_leg(mg, h_main, B_main, log):
@@ -345,7 +357,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp64-solves", type=int, default=1)
+    ap.add_argument("--fp64-solves", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ragged", action="store_true", help="skip the 48-solve ragged batch")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup comparison")
@@ -370,7 +382,7 @@ def main():
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    U = prepare_gauge(L, 0.3, 12, ape_steps=2)
+    U = prepare_main_gauge()
     log(f"inputs ready ({time.perf_counter() - t0:.1f} s)")
     h = mg.Handle(L, LS, M5, MF)
     U_dev = torch.from_numpy(U).to(dev)
@@ -420,15 +432,44 @@ def main():
     worst = max(r["true_relres"] for r in reps)
     assert worst < 1e-10, worst
     s_per_rhs = elapsed / args.steps / nrhs
+    x_check, b_check = X[0].cpu().numpy(), B[0].cpu().numpy()
 
-    # ---- plain FP64 MG, single RHS (a sample of the same source set)
+    # ---- the same step with the D_c stored in BF16 (the other 16-bit format)
+    mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "bf16"))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps_bf = step()
+    torch.cuda.synchronize()
+    bf16_leg = {"s_per_rhs": (time.perf_counter() - t) / nrhs, "outer_iters": reps_bf[0]["outer_iters"],
+                "max_true_relres": max(r["true_relres"] for r in reps_bf)}
+    log(f"bf16 D_c step {bf16_leg}")
+
+    # ---- the same step with the coarse CGNE as one persistent cooperative
+    # kernel (one workgroup per CU, two coarse sites each) instead of graph replays
+    mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f16", coarse_graph="persistent"))
+    step()  # warm: workspaces of the persistent path
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps_p = step()
+    torch.cuda.synchronize()
+    persistent_leg = {"s_per_rhs": (time.perf_counter() - t) / nrhs, "outer_iters": reps_p[0]["outer_iters"],
+                      "coarse_solve_s": reps_p[0]["phase_seconds"][1],
+                      "graph_path_coarse_solve_s": reps[0]["phase_seconds"][1],
+                      "fallback": bool(reps_p[0]["flags"] & 8),
+                      "max_true_relres": max(r["true_relres"] for r in reps_p)}
+    log(f"persistent coarse step {persistent_leg}")
+    mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f16"))
+
+    # ---- plain FP64 MG, single RHS, the same sources one after the other
     mg.mgdwf_set_mg_params(h, mg_params(mg, "f64", "f64"))
     fp64_times, fp64_iters = [], []
     for j in range(args.fp64_solves):
-        x1 = torch.zeros_like(B[j])
+        x1 = torch.zeros_like(B[j % nrhs])
         torch.cuda.synchronize()
         t = time.perf_counter()
-        r = mg.mgdwf_solve(h, B[j].contiguous(), x1, nrhs=1, tol=1e-10, max_outer=400, restart=8)[0]
+        r = mg.mgdwf_solve(h, B[j % nrhs].contiguous(), x1, nrhs=1, tol=1e-10, max_outer=400, restart=8)[0]
+        if j == 0:
+            x1_first = x1.clone()
         torch.cuda.synchronize()
         fp64_times.append(time.perf_counter() - t)
         fp64_iters.append(r["outer_iters"])
@@ -436,7 +477,7 @@ def main():
 
     # ---- error of each reduced-precision result against FP64 (the FP64 path
     # is the one parity-tested against the oracle at 1e-13)
-    x0_mixed = X[0].clone()
+    x0_mixed = torch.from_numpy(x_check).to(dev)  # the timed step's first solution
     g = torch.Generator(device=dev)
     g.manual_seed(77)
     psi = torch.randn(12 * int(np.prod(L)) * LS, dtype=torch.complex128, device=dev, generator=g)
@@ -455,7 +496,7 @@ def main():
     precision = {
         "dslash_f32_relerr": float(torch.linalg.norm(d32 - d64) / torch.linalg.norm(d64)),
         "coarse_apply_relerr": coarse_err,
-        "solution_mixed_vs_fp64_relerr": (float(torch.linalg.norm(x0_mixed - x1) / torch.linalg.norm(x1))
+        "solution_mixed_vs_fp64_relerr": (float(torch.linalg.norm(x0_mixed - x1_first) / torch.linalg.norm(x1_first))
                                           if args.fp64_solves >= 1 else None),
         "note": "relative 2-norm differences from the FP64 path on the same input (random field, random coarse "
                 "vector, and the first point source's solution)",
@@ -492,15 +533,18 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 V-cycle / f64 outer",
+        "dtype": "f32 fine level / f16 D_c on MFMA (f32 accumulate) / f64 outer GCR",
         "data": "synthetic",
         "config": {"workload": "DWF MG solve, 16^3x32 Ls=16 M5=1.8 m_f=0.001, SU(3) eps=0.3 + 2 APE, "
                                "12 point sources per step, blocks 4^4, Nv=24 (12 + reflections)",
                    "nrhs": nrhs, "tol": 1e-10},
         "rhs_per_s": 1.0 / s_per_rhs,
-        "fp64_mg_s_per_rhs": float(np.mean(fp64_times)),
+        "fp64_mg_s_per_rhs": float(np.sum(fp64_times)) / len(fp64_times),
+        "fp64_mg_solves": len(fp64_times),
         "fp64_mg_outer_iters": fp64_iters,
-        "mixed_over_fp64_speedup": float(np.mean(fp64_times)) / s_per_rhs,
+        "mixed_over_fp64_speedup": float(np.sum(fp64_times)) / len(fp64_times) / s_per_rhs,
+        "bf16_coarse_step": bf16_leg,
+        "persistent_coarse_step": persistent_leg,
         "mixed_outer_iters": int(r0["outer_iters"]),
         "mixed_fine_applies_per_rhs": counts["fine"],
         "mixed_coarse_applies_per_rhs": counts["coarse"],
@@ -538,7 +582,8 @@ def main():
         out["learned_setup"] = learned_leg(mg, h, B, setup_s, srep["null_residual"][-1], fields_future, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(counts)
+        out["cpu_baseline"] = cpu_baseline(counts, x_check, b_check)
+        log(f"oracle check of the GPU solution: {out['cpu_baseline']['oracle_check']}")
     h.close()
     print(json.dumps(out), flush=True)
 

@@ -212,12 +212,13 @@ def test_persistent_coarse_solve(cuda, cprec):
 # the five steps), coarse CGNE fixed at 16 iterations on both sides.  FP64:
 # the same map up to rounding.  FP32 fine level: unit roundoff 6e-8 through
 # 2 x 4 MR steps (8 Dslash pairs with their step lengths) and the coarse
-# Krylov iterations; the measured error is a few 1e-7, the bar 1e-5.  16-bit
-# D_c: each coarse application carries the storage error of the 2^-11 (FP16)
-# or 2^-8 (BF16) mantissa, which 16 CGNE iterations carry into the coarse
-# correction (the bulk of M(b)); the bar is 50 unit roundoffs.
-VCYCLE_TOL = {("f64", "f64"): 1e-10, ("f32", "f32"): 1e-5, ("f32", "f16"): 50 * 2.0 ** -11,
-              ("f32", "bf16"): 50 * 2.0 ** -8}
+# Krylov iterations; the measured error is 8e-8, the bar 1e-5.  16-bit D_c:
+# each coarse application carries the storage error of the 2^-11 (FP16) or
+# 2^-8 (BF16) mantissa into the coarse correction; measured on M(b) it is
+# 0.009 and 0.009 of a unit roundoff (4.5e-6 and 3.6e-5), the bar 0.1 unit
+# roundoff.
+VCYCLE_TOL = {("f64", "f64"): 1e-10, ("f32", "f32"): 1e-5, ("f32", "f16"): 0.1 * 2.0 ** -11,
+              ("f32", "bf16"): 0.1 * 2.0 ** -8}
 
 
 @pytest.mark.parametrize("prec,cprec", list(VCYCLE_TOL))
@@ -254,32 +255,33 @@ def test_vcycle_application_matches_oracle(cuda, prec, cprec):
 def test_persistent_coarse_solve_several_sites_per_workgroup(cuda):
     """512 coarse sites (8^3x16 with 2^4 blocks) on a GPU of 256 CUs: the
     persistent coarse CGNE runs one workgroup per CU, each owning two coarse
-    sites, and the solve agrees with the graph path (same outer iterations up
-    to rounding, both to 1e-10 against the oracle's D).  The report flags no
+    sites.  With the coarse CGNE fixed at 16 iterations (a tolerance never
+    met) six FGCR steps agree with the launched loop's up to the rounding of
+    the coarse sums (taken in another order), and the report flags no
     fallback to the launched loop."""
     import paper_1205_2933_amd as mg
     L, Ls, mf, block = (8, 8, 8, 16), 4, 0.01, (2, 2, 2, 2)
     U = prepare_gauge(L, 0.3, 14, ape_steps=2)
     h = mg.Handle(L, Ls, 1.8, mf)
     mg.mgdwf_set_gauge(h, dev(U))
-    kw = dict(sweeps=1, sweep0_iters=100, sweep_iters=4, coarse_tol=0.1, coarse_maxiter=200, fine_prec="f32",
-              coarse_prec="f16")
+    kw = dict(sweeps=1, sweep0_iters=100, sweep_iters=4, fine_prec="f32", coarse_prec="f16")
     mg.mgdwf_setup(h, mg.make_mg_params(block, 16, coarse_graph=True, **kw), dev(random_starts(L, Ls, 8, 21)))
     b = gaussian_fermion(L, Ls, 31, n=2)
     out = {}
-    for mode in (True, "persistent"):
-        mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, coarse_graph=mode, **kw))
+    for mode in (False, "persistent"):
+        mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, coarse_graph=mode, coarse_tol=1e-30,
+                                                    coarse_maxiter=16, **kw))
         x = torch.zeros_like(dev(b))
         print(f"512-site solve mode={mode}", flush=True)
-        reps = mg.mgdwf_solve(h, dev(b), x, nrhs=2, tol=1e-10, max_outer=400, restart=8)
+        reps = mg.mgdwf_solve(h, dev(b), x, nrhs=2, tol=1e-30, max_outer=6, restart=8, allow_not_converged=True)
         print("report", reps[0], flush=True)
         assert not (reps[0]["flags"] & 8)
-        out[mode] = (reps[0]["outer_iters"], x.cpu().numpy())
-    assert abs(out[True][0] - out["persistent"][0]) <= 8
-    xs = out["persistent"][1]
-    for k in range(2):
-        r = b[k] - dwf.apply_dwf(xs[k], U, 1.8, mf)
-        assert np.linalg.norm(r) / np.linalg.norm(b[k]) < 1e-10
+        out[mode] = ([(r["outer_iters"], r["fine_applies"]) for r in reps], [r["coarse_applies"] for r in reps], x)
+    assert out[False][0] == out["persistent"][0] == [(6, out[False][0][0][1])] * 2
+    assert out[False][1] == [6 * 33] * 2 and out["persistent"][1] == [6 * 32] * 2
+    rel = float(torch.linalg.norm(out[False][2] - out["persistent"][2]) / torch.linalg.norm(out[False][2]))
+    print("persistent vs launched", rel, flush=True)
+    assert rel < 1e-3
     h.close()
 
 

@@ -32,8 +32,9 @@ LOWP_TOL = {"f16": 3e-3, "bf16": 2.5e-2}
 
 
 # per coarse site the relative error may exceed the global one where a site's
-# output is smaller than average; the bound allows that much and no more
-SITE_FACTOR = 4.0
+# output is smaller than average (measured: worst site 1.3x the global error
+# in every precision); the bound allows 2x
+SITE_FACTOR = 2.0
 
 
 def dev(a):
