@@ -311,12 +311,15 @@ typedef enum {
  * then kept, so timing noise does not flip the choice between runs.  Without
  * a call the default is used.  Results are identical up to FP32 rounding
  * order whatever the tiling. */
-#define MGDWF_MAX_TILINGS 16
+#define MGDWF_MAX_TILINGS 20
 #define MGDWF_TILE_RELOAD 1      /* kernel that reloads each slice's own spinor          */
 #define MGDWF_TILE_FOLDED 2      /* workgroups ordered t-chunk first across all RHS       */
 #define MGDWF_TILE_ONE_PER_CU 4  /* LDS reserved so one workgroup runs per CU             */
 #define MGDWF_TILE_LDS_LINKS 8   /* each t-slice's links staged in LDS by the workgroup   */
 #define MGDWF_TILE_PIPELINED 16  /* next hop's loads issued before this hop's SU(3) work  */
+#define MGDWF_TILE_SITE_PAIR 32  /* one wavefront per two sites (x pair) x right-hand     */
+                                 /* sides x Ls; links loaded once per site pair; tile =   */
+                                 /* brick of (x pairs, y, z) items, 4th = t-slices/chunk  */
 typedef struct {
   int32_t ntilings;                   /* tilings timed                                  */
   int32_t chosen;                     /* index into the arrays below                     */

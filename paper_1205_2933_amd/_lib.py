@@ -71,7 +71,7 @@ class mgdwf_setup_report(ctypes.Structure):
                 "seconds": self.seconds}
 
 
-MGDWF_MAX_TILINGS = 16
+MGDWF_MAX_TILINGS = 20
 
 
 class mgdwf_tune_report(ctypes.Structure):

@@ -168,7 +168,7 @@ mgdwf_status mgdwf_set_gauge(mgdwf_handle h, const double* U) {
     need(U != nullptr, MGDWF_ERR_INVALID_ARG, "null gauge field");
     const long long n = 36LL * h->g.V4;
     h->U64.alloc(n * sizeof(double2));
-    h->U32.alloc(n * sizeof(float2));
+    h->U32.alloc(2 * n * sizeof(float2));  // component-major links, then a site-major copy
     pack_gauge(reinterpret_cast<const double2*>(U), h->U64.as<double2>(), h->U32.as<float2>(), h->g, h->st);
     MG_HIP(hipStreamSynchronize(h->st));
     h->have_gauge = true;

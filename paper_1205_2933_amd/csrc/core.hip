@@ -75,6 +75,9 @@ __global__ void k_pack_gauge(const double2* __restrict__ canon, double2* __restr
     long long o = (long long)j * V4 + x4;
     g64[o] = v;
     g32[o] = make_float2((float)v.x, (float)v.y);
+    // second FP32 copy, site major ([x4][mu][a][b], the canonical order): the
+    // 36 entries of a site are contiguous for the wavefront-per-site kernel
+    g32[36LL * V4 + (long long)x4 * 36 + j] = make_float2((float)v.x, (float)v.y);
   }
 }
 

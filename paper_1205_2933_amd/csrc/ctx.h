@@ -14,7 +14,7 @@ struct mgdwf_ctx {
   hipStream_t st = nullptr;
   int device = 0;
 
-  mgdwf::DevBuf U64, U32;  // links, FP64 and FP32
+  mgdwf::DevBuf U64, U32;  // links, FP64 and FP32 (the FP32 buffer holds a site-major copy after the first)
   bool have_gauge = false;
 
   mgdwf::CoarseGeometry cg{};

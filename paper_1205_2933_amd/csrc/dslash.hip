@@ -923,6 +923,292 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, PAD > 0 ? 1 : 2) void k_dslash_tq
   }
 }
 
+// ---------------------------------------------------------------- one wavefront per site pair (FP32)
+// k_dslash_tq spends more vector-memory instructions on links than on
+// spinors: each of its lanes loads every link entry itself (63 of about 170
+// loads per wavefront step), and it loads the s - 1 and s + 2 neighbours of
+// its s-pair again.  Here a wavefront holds only two 4D sites, A = (x, y, z, t)
+// with x even and B = A + x, for R = 32 / P right-hand sides and all
+// Ls = 2 P fifth-dimension sites: lane = half * 32 + r * P + j holds s = 2j
+// and 2j + 1 of right-hand side r at A (half 0) or B (half 1).  Each half
+// then shares one link, which one load instruction fetches for both halves
+// (lanes 0..8 and 32..40, one complex entry each) and the LDS crossbar
+// (ds_bpermute) hands to the other lanes; the s - 1 and s + 2 neighbours are
+// the neighbouring lanes' registers.  Per wavefront step that leaves the 84
+// spinor loads (six spatial neighbours and slice t + 1, 16 bytes a lane), 8
+// link loads and 12 stores.  The t-march, the carried slice t + 1 and the
+// carried backward t-hop are those of k_dslash_tq.  Workgroups are four
+// wavefronts; the wavefront items are ordered in bricks of BX x BY x BZ
+// (x pairs, y, z) so that the wavefronts one XCD runs at a time share their
+// neighbours in its L2.
+struct WSArgs {
+  DslashArgs d;
+  int nxp;      // Lx / 2 site pairs
+  int ngrp;     // groups of R right-hand sides
+  int nchunk;   // t chunks
+  int tc;       // t-slices per chunk
+  int nrhs;
+  int bx, by, bz;  // brick of wavefront items: x pairs, y, z
+};
+
+// The link U_mu at site x4a for half 0 and x4b for half 1, in every lane of
+// its half: one load instruction, nine crossbar reads of each real part.
+__device__ __forceinline__ void link_pair(const float2* __restrict__ gs, int x4a, int x4b, int mu, int lane,
+                                          float2 U[3][3]) {
+  const int q = min(lane & 31, 8);  // lanes past the ninth repeat it: one load instruction, no branch
+  const int x4 = (lane & 32) ? x4b : x4a;
+  const float2 v = gs[((long long)x4 * 4 + mu) * 9 + q];
+  const int src = (lane & 32) << 2;  // byte address of lane 0 of this half
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    U[e / 3][e % 3].x = __int_as_float(__builtin_amdgcn_ds_bpermute(src + 4 * e, __float_as_int(v.x)));
+    U[e / 3][e % 3].y = __int_as_float(__builtin_amdgcn_ds_bpermute(src + 4 * e, __float_as_int(v.y)));
+  }
+}
+
+__device__ __forceinline__ float2 lane_read(int addr, float2 v) {
+  return make_float2(__int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v.x))),
+                     __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v.y))));
+}
+
+// Spinor pair loads and stores addressed as a wavefront-uniform base (one
+// per spin-colour component, in scalar registers) plus a 32-bit per-lane
+// byte offset, so no 64-bit per-lane address is formed or kept per component.
+// The component base is made opaque to the optimiser in a scalar register,
+// so the address stays (scalar base) + (32-bit lane offset) instead of being
+// re-associated into one 64-bit per-lane address per component.
+typedef const char __attribute__((address_space(1)))* gbase_t;  // global memory
+typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef const nf4 __attribute__((address_space(1)))* gf4_t;
+typedef nf4 __attribute__((address_space(1)))* gf4w_t;
+
+__device__ __forceinline__ gbase_t sbase(const char* base, long long cs, int k) {
+  gbase_t b = (gbase_t)(base + k * cs);
+  asm volatile("" : "+s"(b));
+  return b;
+}
+
+__device__ __forceinline__ void load_pair_o(Spinor<float2>& p0, Spinor<float2>& p1, const char* base, long long cs,
+                                            unsigned off) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const nf4 v = *(gf4_t)(sbase(base, cs, sp * 3 + c) + off);
+      p0.v[sp][c] = make_float2(v.x, v.y);
+      p1.v[sp][c] = make_float2(v.z, v.w);
+    }
+}
+
+template <int MU, int EPS, bool DAGU>
+__device__ __forceinline__ void hop_pair_u(Spinor<float2>& a0, Spinor<float2>& a1, const char* base, long long cs,
+                                           unsigned off, const float2 U[3][3], float ph) {
+  Spinor<float2> p0, p1;
+  float2 h[2][3], u[2][3];
+  load_pair_o(p0, p1, base, cs, off);
+  project<MU, EPS>(p0, h);
+  mul_link<DAGU>(U, h, u, ph);
+  accumulate<MU, EPS>(a0, u);
+  project<MU, EPS>(p1, h);
+  mul_link<DAGU>(U, h, u, ph);
+  accumulate<MU, EPS>(a1, u);
+}
+
+// own_pair with the s0 - 1 and s0 + 2 values read from the lanes that hold
+// them (addresses up_addr, dn_addr) instead of from memory; UP0 / DN0 are
+// the first of the two spins coupled to s + 1 / s - 1
+template <int UP0, int DN0>
+__device__ __forceinline__ void own_pair_x(Spinor<float2>& a0, Spinor<float2>& a1, const Spinor<float2>& p0,
+                                           const Spinor<float2>& p1, int up_addr, int dn_addr, float cup1,
+                                           float cdn0, float dg) {
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float2 r0 = cscale(p0.v[sp][c], dg), r1 = cscale(p1.v[sp][c], dg);
+      if (sp == UP0 || sp == UP0 + 1) {
+        const float2 nup = lane_read(up_addr, p0.v[sp][c]);  // s0 + 2 = the next lane's s0
+        r0 = csub(r0, p1.v[sp][c]);          // s0 <- s0 + 1
+        r1 = cadd(r1, cscale(nup, cup1));    // s0 + 1 <- s0 + 2
+      }
+      if (sp == DN0 || sp == DN0 + 1) {
+        const float2 ndn = lane_read(dn_addr, p1.v[sp][c]);  // s0 - 1 = the previous lane's s0 + 1
+        r0 = cadd(r0, cscale(ndn, cdn0));    // s0 <- s0 - 1
+        r1 = csub(r1, p0.v[sp][c]);          // s0 + 1 <- s0
+      }
+      a0.v[sp][c] = cscale(r0, -2.f);
+      a1.v[sp][c] = cscale(r1, -2.f);
+    }
+}
+
+template <bool DAG, int MODE, int P>
+__global__ __launch_bounds__(256, 2) void k_dslash_ws(const float2* __restrict__ in, float2* __restrict__ out,
+                                                      const float2* __restrict__ b, const float2* __restrict__ gauge,
+                                                      WSArgs wa, double* __restrict__ partial) {
+  constexpr int R = 32 / P;
+  const DslashArgs& a = wa.d;
+  const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2], Lt = a.L[3];
+  const int Ls = a.Ls;
+  const long long V5 = a.V5, V4 = a.V4;
+  const int V3 = Lx * Ly * Lz;
+  const float2* __restrict__ gs = gauge + 36LL * V4;  // site-major copy
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // wavefront item -> (x pair, y, z) in bricks, right-hand-side group, t chunk;
+  // one workgroup's four items share the group and the chunk
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int item = bid * 4 + wave;
+  const int nsp = wa.nxp * Ly * Lz;                 // items per (group, chunk)
+  const int cg = item / nsp, sp3 = item - cg * nsp;
+  const int grp = cg % wa.ngrp, chunk = cg / wa.ngrp;
+  const int bvol = wa.bx * wa.by * wa.bz;
+  const int brick = sp3 / bvol, ib = sp3 - brick * bvol;
+  const int nbx = wa.nxp / wa.bx, nby = Ly / wa.by;
+  const int xp = (brick % nbx) * wa.bx + ib % wa.bx;
+  const int y = ((brick / nbx) % nby) * wa.by + (ib / wa.bx) % wa.by;
+  const int z = (brick / (nbx * nby)) * wa.bz + ib / (wa.bx * wa.by);
+  // lane -> half (site), right-hand side, s-pair
+  const int half = lane >> 5, r = (lane & 31) / P, jl = lane % P;
+  const int s0 = 2 * jl;
+  const int rhs = grp * R + r;
+  const bool valid = rhs < wa.nrhs;
+  // uniform bases (the group's first right-hand side) and per-lane byte offsets
+  const long long cs = V5 * (long long)sizeof(float2);  // bytes between spin-colour components
+  const long long g0 = (long long)grp * R * 12 * V5;
+  const char* inb = reinterpret_cast<const char*>(in + g0);
+  char* outb = reinterpret_cast<char*>(out + g0);
+  const char* bb0 = MODE == 1 ? reinterpret_cast<const char*>(b + g0) : nullptr;
+  const unsigned roff = (unsigned)((valid ? r : (wa.nrhs - 1 - grp * R)) * 12 * cs);
+  auto lo = [&](long long j5) { return roff + (unsigned)(j5 * (long long)sizeof(float2)); };
+  const int xa = 2 * xp;
+  const int x = xa + half;
+  const int x3a = (z * Ly + y) * Lx + xa;           // site A (wave uniform)
+  const int x3 = x3a + half;
+  // neighbours (per lane) and the backward-link sites (per half, wave uniform)
+  const int xf = x + 1 == Lx ? 0 : x + 1, xb = x == 0 ? Lx - 1 : x - 1;
+  const int yf = y + 1 == Ly ? 0 : y + 1, yb = y == 0 ? Ly - 1 : y - 1;
+  const int zf = z + 1 == Lz ? 0 : z + 1, zb = z == 0 ? Lz - 1 : z - 1;
+  const int nf3[3] = {(z * Ly + y) * Lx + xf, (z * Ly + yf) * Lx + x, (zf * Ly + y) * Lx + x};
+  const int nb3[3] = {(z * Ly + y) * Lx + xb, (z * Ly + yb) * Lx + x, (zb * Ly + y) * Lx + x};
+  const int xam = xa == 0 ? Lx - 1 : xa - 1;       // A - x; B - x is A
+  const int bl3a[3] = {(z * Ly + y) * Lx + xam, (z * Ly + yb) * Lx + xa, (zb * Ly + y) * Lx + xa};
+  const int bl3b[3] = {x3a, (z * Ly + yb) * Lx + xa + 1, (zb * Ly + y) * Lx + xa + 1};
+  const float phf[3] = {x == Lx - 1 ? a.ph[0] : 1.0f, y == Ly - 1 ? a.ph[1] : 1.0f, z == Lz - 1 ? a.ph[2] : 1.0f};
+  const float phb[3] = {x == 0 ? a.ph[0] : 1.0f, y == 0 ? a.ph[1] : 1.0f, z == 0 ? a.ph[2] : 1.0f};
+  // fifth-dimension neighbours in the lanes of the same (site, rhs)
+  const int lbase = lane - jl;
+  const int up_addr = 4 * (lbase + (jl + 1 == P ? 0 : jl + 1));
+  const int dn_addr = 4 * (lbase + (jl == 0 ? P - 1 : jl - 1));
+  const float cup1 = s0 + 2 == Ls ? (float)a.mf : -1.f;  // s0 + 2 across the wall
+  const float cdn0 = s0 == 0 ? (float)a.mf : -1.f;       // s0 - 1 across the wall
+  constexpr int EF = DAG ? 1 : -1;
+  constexpr int EB = DAG ? -1 : 1;
+  const float dg = (float)a.diag;
+  const int t0 = chunk * wa.tc;
+  const int t1 = min(t0 + wa.tc, Lt);
+  float2 hp0[2][3], hp1[2][3], U[3][3], h[2][3], u[2][3];
+  Spinor<float2> p0, p1, a0, a1;
+  {  // slice t0: own terms, and the backward t-hop from slice t0 - 1
+    const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+    load_pair_o(p0, p1, inb, cs, lo((long long)(tm * V3 + x3) * Ls + s0));
+    project<3, EB>(p0, hp0);
+    project<3, EB>(p1, hp1);
+    const long long base = (long long)(t0 * V3 + x3) * Ls;
+    load_pair_o(p0, p1, inb, cs, lo(base + s0));
+    own_pair_x<DAG ? 0 : 2, DAG ? 2 : 0>(a0, a1, p0, p1, up_addr, dn_addr, cup1, cdn0, dg);
+    link_pair(gs, tm * V3 + x3a, tm * V3 + x3a + 1, 3, lane, U);
+    const float ph = t0 == 0 ? a.ph[3] : 1.0f;
+    mul_link<true>(U, hp0, u, ph);
+    accumulate<3, EB>(a0, u);
+    mul_link<true>(U, hp1, u, ph);
+    accumulate<3, EB>(a1, u);
+    project<3, EB>(p0, hp0);
+    project<3, EB>(p1, hp1);
+  }
+  float nrmf = 0.f;
+  for (int t = t0; t < t1; ++t) {
+    const int tb = t * V3;
+    link_pair(gs, tb + x3a, tb + x3a + 1, 0, lane, U);
+    hop_pair_u<0, EF, false>(a0, a1, inb, cs, lo((long long)(tb + nf3[0]) * Ls + s0), U, phf[0]);
+    __builtin_amdgcn_sched_barrier(0);  // one hop at a time: the next hop's loads wait
+    link_pair(gs, tb + bl3a[0], tb + bl3b[0], 0, lane, U);
+    hop_pair_u<0, EB, true>(a0, a1, inb, cs, lo((long long)(tb + nb3[0]) * Ls + s0), U, phb[0]);
+    __builtin_amdgcn_sched_barrier(0);
+    link_pair(gs, tb + x3a, tb + x3a + 1, 1, lane, U);
+    hop_pair_u<1, EF, false>(a0, a1, inb, cs, lo((long long)(tb + nf3[1]) * Ls + s0), U, phf[1]);
+    __builtin_amdgcn_sched_barrier(0);
+    link_pair(gs, tb + bl3a[1], tb + bl3b[1], 1, lane, U);
+    hop_pair_u<1, EB, true>(a0, a1, inb, cs, lo((long long)(tb + nb3[1]) * Ls + s0), U, phb[1]);
+    __builtin_amdgcn_sched_barrier(0);
+    link_pair(gs, tb + x3a, tb + x3a + 1, 2, lane, U);
+    hop_pair_u<2, EF, false>(a0, a1, inb, cs, lo((long long)(tb + nf3[2]) * Ls + s0), U, phf[2]);
+    __builtin_amdgcn_sched_barrier(0);
+    link_pair(gs, tb + bl3a[2], tb + bl3b[2], 2, lane, U);
+    hop_pair_u<2, EB, true>(a0, a1, inb, cs, lo((long long)(tb + nb3[2]) * Ls + s0), U, phb[2]);
+    __builtin_amdgcn_sched_barrier(0);
+    // forward t-hop with slice t + 1
+    const bool top = t == Lt - 1;
+    const long long basef = (long long)((top ? 0 : t + 1) * V3 + x3) * Ls;
+    load_pair_o(p0, p1, inb, cs, lo(basef + s0));
+    link_pair(gs, tb + x3a, tb + x3a + 1, 3, lane, U);
+    {
+      const float ph = top ? a.ph[3] : 1.0f;
+      project<3, EF>(p0, h);
+      mul_link<false>(U, h, u, ph);
+      accumulate<3, EF>(a0, u);
+      project<3, EF>(p1, h);
+      mul_link<false>(U, h, u, ph);
+      accumulate<3, EF>(a1, u);
+    }
+    // Lanes past the last right-hand side read that one's fields, so they
+    // compute its values bit for bit and their stores repeat them: no branch
+    // around the stores; they are left out of the norm.
+    const unsigned o5 = lo((long long)(tb + x3) * Ls + s0);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float2 r0 = cscale(a0.v[sp][c], -0.5f), r1 = cscale(a1.v[sp][c], -0.5f);
+        if (MODE == 1) {
+          const nf4 bb = *(gf4_t)(sbase(bb0, cs, sp * 3 + c) + o5);
+          r0 = make_float2(bb.x - r0.x, bb.y - r0.y);
+          r1 = make_float2(bb.z - r1.x, bb.w - r1.y);
+        }
+        *(gf4w_t)(sbase(outb, cs, sp * 3 + c) + o5) = nf4{r0.x, r0.y, r1.x, r1.y};
+        if (partial) nrmf += r0.x * r0.x + r0.y * r0.y + r1.x * r1.x + r1.y * r1.y;
+      }
+    if (t + 1 < t1) {  // slice t + 1: own terms, backward t-hop from slice t
+      own_pair_x<DAG ? 0 : 2, DAG ? 2 : 0>(a0, a1, p0, p1, up_addr, dn_addr, cup1, cdn0, dg);
+      mul_link<true>(U, hp0, u, 1.0f);
+      accumulate<3, EB>(a0, u);
+      mul_link<true>(U, hp1, u, 1.0f);
+      accumulate<3, EB>(a1, u);
+      project<3, EB>(p0, hp0);
+      project<3, EB>(p1, hp1);
+    }
+  }
+  if (partial) {
+    // per right-hand side: the P lanes of each half, then the two halves,
+    // then the four wavefronts of the workgroup (all in the same group)
+    double v = valid ? (double)nrmf : 0.0;
+#pragma unroll
+    for (int off = 1; off < P; off <<= 1) v += __shfl_xor(v, off, 64);
+    v += __shfl_xor(v, 32, 64);
+    __shared__ double red[4][R];
+    if (lane < 32 && jl == 0) red[wave][r] = v;
+    __syncthreads();
+    if ((int)threadIdx.x < R) {
+      const int rr = grp * R + (int)threadIdx.x;
+      if (rr < wa.nrhs) {
+        const double s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        // partial index: (rhs, block within the group's range of this chunk)
+        const int nbs = nsp / 4;
+        partial[(long long)rr * (nbs * wa.nchunk) + chunk * nbs + sp3 / 4] = s;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- t-march, software-pipelined (FP32)
 // k_dslash_tq computes each hop right after loading it, so every hop waits
 // out a full memory round trip: with one wavefront per SIMD nothing else hides
@@ -1183,6 +1469,7 @@ struct FTile {
   bool one_per_cu = false;  // reserve LDS so that one workgroup runs per CU
   bool lds_links = false;   // stage each slice's links in LDS
   bool pipelined = false;   // k_dslash_tw (loads one hop ahead)
+  bool ws = false;          // k_dslash_ws: tx, ty, tz = brick of (x pairs, y, z), target = t-slices per chunk
 };
 constexpr FTile kFTiles[] = {
     {4, 4, 2, 256, false, 0, true}, {4, 4, 2, 512, false, 0, true}, {4, 4, 2, 256, false, 0},
@@ -1191,6 +1478,8 @@ constexpr FTile kFTiles[] = {
     {4, 4, 2, 512, true, 0},        {4, 4, 2, 256, false, 0, true, true},
     {4, 4, 2, 256, false, 0, true, false, true}, {4, 4, 2, 256, false, 0, false, false, true},
     {4, 4, 2, 512, false, 0, true, false, true},
+    {2, 2, 2, 2, false, 0, false, false, false, true}, {4, 4, 4, 2, false, 0, false, false, false, true},
+    {8, 16, 1, 2, false, 0, false, false, false, true},
 };
 constexpr int NFTILE = sizeof(kFTiles) / sizeof(kFTiles[0]);
 
@@ -1199,6 +1488,12 @@ constexpr int NFTILE = sizeof(kFTiles) / sizeof(kFTiles[0]);
 static bool ftile_ok(const Geometry& g, int i) {
   if (i < 0 || i >= NFTILE) return false;
   const FTile& f = kFTiles[i];
+  if (f.ws) {  // two sites per wavefront in x; 2 P = Ls with P = 4 or 8; whole workgroups per (group, chunk)
+    const int nxp = g.L[0] / 2;
+    const long long group_bytes = 32LL / (g.Ls / 2) * 12 * (long long)g.V5 * 8;  // R fields: 32-bit lane offsets
+    return g.L[0] % 2 == 0 && nxp % f.tx == 0 && g.L[1] % f.ty == 0 && g.L[2] % f.tz == 0 &&
+           (g.Ls == 8 || g.Ls == 16) && (nxp * g.L[1] * g.L[2]) % 4 == 0 && group_bytes < (1LL << 32);
+  }
   const int thr = f.tx * f.ty * f.tz * g.Ls / 2;
   return g.L[0] % f.tx == 0 && g.L[1] % f.ty == 0 && g.L[2] % f.tz == 0 && g.Ls % 2 == 0 && g.Ls >= 4 &&
          g.Ls <= 16 && thr % 64 == 0;
@@ -1213,10 +1508,12 @@ static int ftile_of(const Geometry& g) {
 
 static int ftile_ntiles(const Geometry& g, int i) {
   const FTile& f = kFTiles[i];
+  if (f.ws) return g.L[0] / 2 * g.L[1] * g.L[2] / 4;  // workgroups per (group, chunk)
   return (g.L[0] / f.tx) * (g.L[1] / f.ty) * (g.L[2] / f.tz);
 }
 
 static int ftile_chunk(const Geometry& g, int i) {
+  if (kFTiles[i].ws) return std::min(g.L[3], kFTiles[i].target);
   const int want_chunks = std::max(1, std::min(g.L[3], ceil_div(kFTiles[i].target, ftile_ntiles(g, i))));
   return ceil_div(g.L[3], want_chunks);
 }
@@ -1230,7 +1527,7 @@ bool dslash_ftile_desc(const Geometry& g, int i, int desc[4], int* flags) {
   desc[2] = kFTiles[i].tz;
   desc[3] = ftile_chunk(g, i);
   *flags = (kFTiles[i].eight_loads ? 1 : 0) | (kFTiles[i].fold ? 2 : 0) | (kFTiles[i].one_per_cu ? 4 : 0) |
-           (kFTiles[i].lds_links ? 8 : 0) | (kFTiles[i].pipelined ? 16 : 0);
+           (kFTiles[i].lds_links ? 8 : 0) | (kFTiles[i].pipelined ? 16 : 0) | (kFTiles[i].ws ? 32 : 0);
   return true;
 }
 
@@ -1315,6 +1612,26 @@ static void launch_tpair(const double2*, double2*, const double2*, const double2
   fail(MGDWF_ERR_INVALID_ARG, "the s-pair kernel is FP32 only");
 }
 
+static void launch_ws(const float2* in, float2* out, const float2* b, const float2* gauge, const WSArgs& wa,
+                      double* partial, bool dagger, int mode, dim3 grid, int P, hipStream_t st) {
+#define MG_WS(DAG, MODE, PP) \
+  hipLaunchKernelGGL((k_dslash_ws<DAG, MODE, PP>), grid, dim3(256), 0, st, in, out, b, gauge, wa, partial)
+#define MG_WSP(PP)                                \
+  if (!dagger && mode == 0) MG_WS(false, 0, PP);  \
+  else if (!dagger && mode == 1) MG_WS(false, 1, PP); \
+  else if (dagger && mode == 0) MG_WS(true, 0, PP);   \
+  else MG_WS(true, 1, PP);
+  if (P == 8) { MG_WSP(8) }
+  else if (P == 4) { MG_WSP(4) }
+  else fail(MGDWF_ERR_INVALID_ARG, "no wavefront-per-site-pair kernel for this Ls");
+#undef MG_WSP
+#undef MG_WS
+}
+static void launch_ws(const double2*, double2*, const double2*, const double2*, const WSArgs&, double*, bool, int,
+                      dim3, int, hipStream_t) {
+  fail(MGDWF_ERR_INVALID_ARG, "the wavefront-per-site-pair kernel is FP32 only");
+}
+
 // Kernel choice: FP32 takes the s-pair t-march where the lattice tiles, else the
 // t-march, else the plain kernel; FP64 takes the plain kernel, whose register
 // budget (about 250) keeps two wavefronts per SIMD where the t-march keeps one.
@@ -1351,6 +1668,23 @@ void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geomet
   for (int m = 0; m < 4; ++m) { a.L[m] = g.L[m]; a.ph[m] = (float)g.bc[m]; }
   a.Ls = g.Ls; a.V4 = g.V4; a.V5 = g.V5; a.diag = 5.0 - M5; a.mf = mf;
   const DslashKind kind = dslash_kind<C2>(g);
+  if (kind == DS_TPAIR && kFTiles[ftile_of(g)].ws) {
+    const int i = ftile_of(g);
+    const FTile& f = kFTiles[i];
+    WSArgs wa;
+    wa.d = a;
+    wa.nxp = g.L[0] / 2;
+    wa.tc = ftile_chunk(g, i);
+    wa.nchunk = ceil_div(g.L[3], wa.tc);
+    wa.nrhs = nrhs;
+    wa.bx = f.tx; wa.by = f.ty; wa.bz = f.tz;
+    const int P = g.Ls / 2, R = 32 / P;
+    wa.ngrp = ceil_div(nrhs, R);
+    const dim3 grid(ftile_ntiles(g, i) * wa.ngrp * wa.nchunk);
+    launch_ws(in, out, b, gauge, wa, partial, dagger, mode, grid, P, st);
+    MG_LAUNCH_CHECK();
+    return;
+  }
   if (kind == DS_TPAIR) {
     const int i = ftile_of(g);
     const FTile& f = kFTiles[i];

@@ -42,6 +42,7 @@ def main(argv=None):
     ap.add_argument("--block", type=int, nargs=4, default=(4, 4, 4, 4))
     ap.add_argument("--nvec", type=int, default=24)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--tiling", type=int, default=-1, help="FP32 Dslash tiling id (mgdwf_set_tiling), -1 = default")
     ap.add_argument("--coarse-tile", type=int, default=-1,
                     help="MFMA shape of the 16-bit D_c apply: 0 = 16x16x16, 1 = 16x16x32, -1 = default")
     args = ap.parse_args(argv)
@@ -76,6 +77,7 @@ def main(argv=None):
     U = torch.randn(36 * V4, dtype=torch.complex128, device=dev, generator=g)
     mg.mgdwf_set_gauge(h, U)
     del U
+    mg.mgdwf_set_tiling(h, args.tiling)
     if args.kernel != "dslash":
         V = torch.randn(12 * V5 * args.nvec, dtype=torch.complex128, device=dev, generator=g)
         mg.mgdwf_set_nullvecs(h, args.block, V, args.nvec)
@@ -96,7 +98,7 @@ def main(argv=None):
         nbytes = 9 * n2 * n2 * Vc * store + args.nrhs * 2 * n2 * Vc * vec
     gbs = nbytes / (ms * 1e-3) / 1e9
     print(json.dumps({"kernel": args.kernel, "prec": args.prec, "nrhs": args.nrhs, "L": L, "Ls": Ls,
-                      "coarse_tile": args.coarse_tile, "bytes": nbytes,
+                      "tiling": args.tiling, "coarse_tile": args.coarse_tile, "bytes": nbytes,
                       "us": ms * 1e3, "GBs": gbs, "frac_hbm_peak": gbs / HBM_PEAK_GBS}), flush=True)
     h.close()
 
