@@ -21,6 +21,10 @@ Algorithms for Domain-Wall Fermions", Lattice 2011):
 * ``solvers``   -- minimal-residual smoother, GCR / flexible GCR, CG on the
                    normal equations, the five-step V-cycle (Sec. 2 and Sec. 3).
 * ``setup``     -- adaptive near-null vector search (Sec. 2, adaptive setup).
+* ``squared``   -- the multigrid on the squared operator D^+D that the paper
+                   ran (Sec. 3 first paragraph, Sec. 4): basis of D^+D's
+                   near-null vectors, A_c = P^+ D^+D P (33-offset stencil),
+                   MR smoothing on D^+D, CG on A_c.
 * ``dense``     -- explicit matrices on tiny lattices (pins only).
 * ``nullnet``   -- forward/backward of the gauge-covariant proposal network.
 
