@@ -107,6 +107,17 @@ typedef struct {
                              unused D_c^+ apply.  With 1 and 2 the V-cycle's
                              launches before and after the coarse solve are
                              graph replays too.                               */
+  int32_t squared;        /* 0: the 9-point D_c = P^+ D P on the gamma5 R5-
+                             closed basis.  1: the paper's own multigrid on the
+                             squared operator D^+D (Sec. 3 first paragraph,
+                             Sec. 4): nvec adaptive vectors (no reflections),
+                             A_c = P^+ D^+D P (33-point stencil, Hermitian),
+                             V-cycle on D^+D with minimal-residual smoothing
+                             (two applications of D per step), CG on A_c,
+                             entered with D^+ r so that it preconditions the
+                             same flexible GCR on D x = b.  Needs every block
+                             extent >= 2 and an F64 or F32 coarse level; the
+                             coarse solve runs as launched kernels.            */
 } mgdwf_mg_params;
 
 /* Outer flexible GCR (Sec. 3).  Every restart recomputes the true residual
@@ -196,7 +207,18 @@ mgdwf_status mgdwf_prolong(mgdwf_handle h, const double* coarse, double* fine, i
 /* Build D_c = R D P as the 9-point stencil of dense 2Nv x 2Nv blocks (FP64),
  * plus its FP32, FP16 and BF16 copies with one scale per block. */
 mgdwf_status mgdwf_build_coarse(mgdwf_handle h);
-/* Copy the FP64 coarse operator out (canonical layout, complex128). */
+/* Build the squared operator's coarse operator A_c = P^+ D^+ D P (Sec. 3,
+ * Sec. 4) on the installed basis: a stencil over the 33 offsets o = self,
+ * +mu / -mu (index 1 + 2 mu / 2 + 2 mu), then for mu < nu the diagonals
+ * (+mu+nu, +mu-nu, -mu+nu, -mu-nu), with (A_c y)(X) = sum_o Ac[X][o] y(X + o).
+ * Every block extent must be >= 2 (MGDWF_ERR_INVALID_ARG otherwise).  It
+ * replaces the 9-point operator for apply_coarse, get_coarse_op and solves
+ * with squared = 1. */
+mgdwf_status mgdwf_build_coarse_squared(mgdwf_handle h);
+/* Offsets of the coarse operator built last: 9 (D_c), 33 (A_c), -1 if none. */
+int32_t mgdwf_coarse_stencil_size(mgdwf_handle h);
+/* Copy the FP64 coarse operator out (canonical layout, complex128):
+ * [X4][d][row][col] over the 9 or 33 offsets of the operator built last. */
 mgdwf_status mgdwf_get_coarse_op(mgdwf_handle h, double* Dc);
 /* out = D_c in (dagger 0) or D_c^+ in (dagger 1), nrhs canonical coarse
  * vectors, computed with the operator stored in `prec` (F16/BF16 use MFMA with
@@ -206,8 +228,8 @@ mgdwf_status mgdwf_apply_coarse(mgdwf_handle h, const double* in, double* out, i
 
 /* ---- setup and solve (steps a8-a11): Sec. 2, Sec. 3 -------------------- */
 
-/* Adaptive setup (Sec. 2): starting from nvec/2 random vectors V0 (canonical,
- * device; the random numbers are inputs), sweep 0 runs sweep0_iters CG
+/* Adaptive setup (Sec. 2): starting from nvec/2 random vectors V0 (nvec when
+ * p->squared; canonical, device; the random numbers are inputs), sweep 0 runs sweep0_iters CG
  * iterations on D^+D v = 0 from each; every later sweep applies the current
  * multigrid to the same problem: sweep_iters flexible-GCR steps with the
  * FP64 V-cycle on D x = 0 starting from x = v, and v becomes the x they leave

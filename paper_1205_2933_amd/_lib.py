@@ -42,7 +42,8 @@ class mgdwf_mg_params(ctypes.Structure):
                 ("sweep0_iters", ctypes.c_int32), ("sweep_iters", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("coarse_tol", ctypes.c_double), ("coarse_maxiter", ctypes.c_int32),
-                ("fine_prec", ctypes.c_int), ("coarse_prec", ctypes.c_int), ("coarse_graph", ctypes.c_int32)]
+                ("fine_prec", ctypes.c_int), ("coarse_prec", ctypes.c_int), ("coarse_graph", ctypes.c_int32),
+                ("squared", ctypes.c_int32)]
 
 
 class mgdwf_solve_params(ctypes.Structure):
@@ -118,6 +119,8 @@ def _load() -> ctypes.CDLL:
         "mgdwf_prolong": ([H, P, P, i32, ctypes.c_int], ctypes.c_int),
         "mgdwf_build_coarse": ([H], ctypes.c_int),
         "mgdwf_get_coarse_op": ([H, P], ctypes.c_int),
+        "mgdwf_build_coarse_squared": ([H], ctypes.c_int),
+        "mgdwf_coarse_stencil_size": ([H], ctypes.c_int32),
         "mgdwf_apply_coarse": ([H, P, P, i32, ctypes.c_int, i32], ctypes.c_int),
         "mgdwf_setup": ([H, ctypes.POINTER(mgdwf_mg_params), P, ctypes.POINTER(mgdwf_setup_report)], ctypes.c_int),
         "mgdwf_set_mg_params": ([H, ctypes.POINTER(mgdwf_mg_params)], ctypes.c_int),
@@ -278,8 +281,16 @@ def mgdwf_build_coarse(h: Handle):
     _check(h.h, _lib.mgdwf_build_coarse(h.h))
 
 
+def mgdwf_build_coarse_squared(h: Handle):
+    _check(h.h, _lib.mgdwf_build_coarse_squared(h.h))
+
+
+def mgdwf_coarse_stencil_size(h: Handle) -> int:
+    return int(_lib.mgdwf_coarse_stencil_size(h.h))
+
+
 def mgdwf_get_coarse_op(h: Handle, Dc: torch.Tensor):
-    n = h.ncoarse // (2 * h.nvec) * 9 * (2 * h.nvec) ** 2
+    n = h.ncoarse // (2 * h.nvec) * mgdwf_coarse_stencil_size(h) * (2 * h.nvec) ** 2
     _check(h.h, _lib.mgdwf_get_coarse_op(h.h, _dev(Dc, n, "Dc")))
 
 
@@ -290,7 +301,7 @@ def mgdwf_apply_coarse(h: Handle, inp: torch.Tensor, out: torch.Tensor, dagger=F
 
 def make_mg_params(block, nvec, sweeps=1, sweep0_iters=100, sweep_iters=4, nu_pre=4, nu_post=4,
                    coarse_tol=0.1, coarse_maxiter=100, fine_prec="f64", coarse_prec="f64",
-                   coarse_graph=True) -> mgdwf_mg_params:
+                   coarse_graph=True, squared=False) -> mgdwf_mg_params:
     p = mgdwf_mg_params()
     p.block[:] = list(block)
     p.nvec, p.sweeps, p.sweep0_iters, p.sweep_iters = nvec, sweeps, sweep0_iters, sweep_iters
@@ -298,12 +309,14 @@ def make_mg_params(block, nvec, sweeps=1, sweep0_iters=100, sweep_iters=4, nu_pr
     p.fine_prec, p.coarse_prec = PREC[fine_prec], PREC[coarse_prec]
     # True / 1: graph replays; "persistent" / 2: one persistent coarse kernel; False / 0: plain launches
     p.coarse_graph = 2 if coarse_graph in ("persistent", 2) else (1 if coarse_graph else 0)
+    p.squared = 1 if squared else 0
     return p
 
 
 def mgdwf_setup(h: Handle, params: mgdwf_mg_params, V0: torch.Tensor) -> dict:
     rep = mgdwf_setup_report()
-    _check(h.h, _lib.mgdwf_setup(h.h, ctypes.byref(params), _dev(V0, h.nfine * (params.nvec // 2), "V0"),
+    nstart = params.nvec if params.squared else params.nvec // 2
+    _check(h.h, _lib.mgdwf_setup(h.h, ctypes.byref(params), _dev(V0, h.nfine * nstart, "V0"),
                                  ctypes.byref(rep)))
     h.block, h.nvec = tuple(params.block), params.nvec
     return rep.as_dict()

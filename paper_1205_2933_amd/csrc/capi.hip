@@ -59,7 +59,16 @@ CoarseGeometry make_coarse(const Geometry& g, const int32_t block[4], int nvec) 
 
 void check_params(const mgdwf_ctx* c, const mgdwf_mg_params* p) {
   need(p != nullptr, MGDWF_ERR_INVALID_ARG, "null parameters");
-  need(p->nvec >= 2 && p->nvec % 2 == 0, MGDWF_ERR_INVALID_ARG, "nvec must be even (vectors are paired with their reflections)");
+  need(p->squared == 0 || p->squared == 1, MGDWF_ERR_INVALID_ARG, "squared must be 0 or 1");
+  if (p->squared) {
+    need(p->nvec >= 1, MGDWF_ERR_INVALID_ARG, "nvec must be >= 1");
+    need(p->coarse_prec == MGDWF_F64 || p->coarse_prec == MGDWF_F32, MGDWF_ERR_INVALID_ARG,
+         "the squared-operator coarse level runs in F64 or F32");
+    for (int m = 0; m < 4; ++m)
+      need(p->block[m] >= 2, MGDWF_ERR_INVALID_ARG, "the squared-operator coarse stencil needs block extents >= 2");
+  } else {
+    need(p->nvec >= 2 && p->nvec % 2 == 0, MGDWF_ERR_INVALID_ARG, "nvec must be even (vectors are paired with their reflections)");
+  }
   need(p->sweeps >= 1 && p->sweeps <= 8, MGDWF_ERR_INVALID_ARG, "sweeps must be in 1..8");
   need(p->sweep0_iters >= 0 && p->sweep_iters >= 1, MGDWF_ERR_INVALID_ARG, "bad sweep iteration counts");
   need(p->nu_pre >= 0 && p->nu_post >= 0 && p->nu_pre <= 16 && p->nu_post <= 16, MGDWF_ERR_INVALID_ARG,
@@ -90,6 +99,29 @@ void install_basis(mgdwf_ctx* c, const int block[4], int nvec) {
   c->have_basis = true;
 }
 
+void build_coarse_squared(mgdwf_ctx* c) {
+  need(c->have_basis, MGDWF_ERR_STATE, "no basis installed");
+  const CoarseGeometry& cg = c->cg;
+  for (int m = 0; m < 4; ++m)
+    need(cg.block[m] >= 2, MGDWF_ERR_INVALID_ARG, "the squared-operator coarse stencil needs block extents >= 2");
+  const long long field = c->fine_len();
+  c->have_coarse = false;
+  c->Asq.m64.alloc(sq_coarse_entries(cg) * sizeof(double2));
+  double2* work9 = c->buf<double2>("dc_work9", 9 * field);
+  double2* zwork9 = c->buf<double2>("dc_zwork9", 9 * field);
+  double2* cwork = c->buf<double2>("dc_cwork", 9LL * cg.Vc * cg.n2);
+  double* partial = c->buf<double>("dc_partial", restrict_partial_doubles(cg, 9));
+  build_sq_coarse_op(c->V64.as<double2>(), c->U64.as<double2>(), c->Asq.m64.as<double2>(), work9, zwork9, cwork,
+                     partial, c->g, cg, c->M5, c->mf, c->st);
+  c->Asq.m32.alloc(sq_coarse_entries(cg) * sizeof(float2));
+  sq_to_f32(c->Asq.m64.as<double2>(), c->Asq.m32.as<float2>(), cg, c->st);
+  MG_HIP(hipStreamSynchronize(c->st));
+  c->ws.erase("dc_work9");
+  c->ws.erase("dc_zwork9");
+  c->coarse_kind = 1;
+  c->have_coarse = true;
+}
+
 void build_coarse(mgdwf_ctx* c) {
   need(c->have_basis, MGDWF_ERR_STATE, "no basis installed");
   const CoarseGeometry& cg = c->cg;
@@ -104,6 +136,7 @@ void build_coarse(mgdwf_ctx* c) {
   MG_HIP(hipStreamSynchronize(c->st));
   // the build workspaces are large; give them back
   c->ws.erase("dc_work9");
+  c->coarse_kind = 0;
   c->have_coarse = true;
 }
 
@@ -292,11 +325,29 @@ mgdwf_status mgdwf_build_coarse(mgdwf_handle h) {
     h->clear_graphs(); build_coarse(h); });
 }
 
+mgdwf_status mgdwf_build_coarse_squared(mgdwf_handle h) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    h->clear_graphs();
+    build_coarse_squared(h);
+  });
+}
+
+int32_t mgdwf_coarse_stencil_size(mgdwf_handle h) {
+  if (!h || !h->have_coarse) return -1;
+  return h->coarse_kind == 1 ? 33 : 9;
+}
+
 mgdwf_status mgdwf_get_coarse_op(mgdwf_handle h, double* Dc) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     need(Dc != nullptr, MGDWF_ERR_INVALID_ARG, "null output");
     need(h->have_coarse, MGDWF_ERR_STATE, "coarse operator not built");
+    if (h->coarse_kind == 1) {
+      sq_canonical(h->Asq.m64.as<double2>(), reinterpret_cast<double2*>(Dc), h->cg, h->st);
+      MG_HIP(hipStreamSynchronize(h->st));
+      return;
+    }
     long long nblk = 9LL * h->cg.Vc;
     long long tot = nblk * h->cg.n2 * h->cg.n2;
     hipLaunchKernelGGL(k_dc_canonical, dim3(ceil_div(tot, 256)), dim3(256), 0, h->st, h->Dc.m64.as<double2>(),
@@ -314,6 +365,20 @@ mgdwf_status mgdwf_apply_coarse(mgdwf_handle h, const double* in, double* out, i
     need(h->have_coarse, MGDWF_ERR_STATE, "coarse operator not built");
     need(prec >= MGDWF_F64 && prec <= MGDWF_BF16, MGDWF_ERR_INVALID_ARG, "bad coarse precision");
     const long long n = h->coarse_len() * nrhs;
+    if (h->coarse_kind == 1) {  // A_c is Hermitian: the same stencil either way
+      need(prec == MGDWF_F64 || prec == MGDWF_F32, MGDWF_ERR_INVALID_ARG, "the squared coarse operator is F64 or F32");
+      if (prec == MGDWF_F64) {
+        sq_apply64(h->Asq.m64.as<double2>(), reinterpret_cast<const double2*>(in), reinterpret_cast<double2*>(out),
+                   h->cg, nrhs, h->st);
+      } else {
+        float2* a = h->buf<float2>("cio_a32", n);
+        float2* b = h->buf<float2>("cio_b32", n);
+        convert<double2, float2>(reinterpret_cast<const double2*>(in), a, n, h->st);
+        sq_apply32(h->Asq.m32.as<float2>(), a, b, h->cg, nrhs, h->st);
+        convert<float2, double2>(b, reinterpret_cast<double2*>(out), n, h->st);
+      }
+      return;
+    }
     const CoarseStore& s = dagger ? h->DcH : h->Dc;
     if (prec == MGDWF_F64) {
       coarse_apply64(s, reinterpret_cast<const double2*>(in), reinterpret_cast<double2*>(out), h->cg, nrhs, h->st);
@@ -336,7 +401,7 @@ mgdwf_status mgdwf_setup(mgdwf_handle h, const mgdwf_mg_params* p, const double*
     need(V0 != nullptr, MGDWF_ERR_INVALID_ARG, "null starting vectors");
     need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
     if (report) std::memset(report, 0, sizeof(*report));
-    const int nh = p->nvec / 2;
+    const int nh = p->squared ? p->nvec : p->nvec / 2;
     double2* W = h->buf<double2>("setup_w", h->fine_len() * nh);
     pack_fermion_f64(reinterpret_cast<const double2*>(V0), W, h->g, nh, h->st);
     mg_setup(h, *p, W, report);
@@ -350,6 +415,9 @@ mgdwf_status mgdwf_set_mg_params(mgdwf_handle h, const mgdwf_mg_params* p) {
     check_params(h, p);
     need(h->have_coarse, MGDWF_ERR_STATE, "no basis / coarse operator installed");
     need(p->nvec == h->cg.Nv, MGDWF_ERR_INVALID_ARG, "nvec differs from the installed basis");
+    need(p->squared == h->coarse_kind, MGDWF_ERR_STATE,
+         p->squared ? "squared = 1 needs mgdwf_build_coarse_squared (or a squared setup) first"
+                    : "squared = 0 needs the 9-point operator (mgdwf_build_coarse) first");
     for (int m = 0; m < 4; ++m) need(p->block[m] == h->cg.block[m], MGDWF_ERR_INVALID_ARG, "block differs from the installed basis");
     h->mp = *p;
     h->have_params = true;
@@ -409,7 +477,7 @@ mgdwf_status mgdwf_trim(mgdwf_handle h) {
 int64_t mgdwf_memory_bytes(mgdwf_handle h) {
   if (!h) return -1;
   long long n = (long long)(h->U64.bytes + h->U32.bytes + h->V64.bytes + h->V32.bytes);
-  for (const mgdwf::CoarseStore* cs : {&h->Dc, &h->DcH})
+  for (const mgdwf::CoarseStore* cs : {&h->Dc, &h->DcH, &h->Asq})
     n += (long long)(cs->m64.bytes + cs->m32.bytes + cs->re16.bytes + cs->im16.bytes + cs->sc16.bytes +
                      cs->reb.bytes + cs->imb.bytes + cs->scb.bytes);
   for (const auto& kv : h->ws) n += (long long)kv.second.bytes;
@@ -511,6 +579,14 @@ mgdwf_status mgdwf_time_kernel(mgdwf_handle h, mgdwf_kernel k, mgdwf_prec prec, 
             else
               prolong_op<float2, float2>(h->V32.as<float2>(), h->buf<float2>("t_c32", nc), h->buf<float2>("t_a32", nf),
                                          false, h->g, h->cg, nrhs, h->st);
+          } else if (k == MGDWF_K_COARSE && h->coarse_kind == 1) {
+            need(prec == MGDWF_F64 || prec == MGDWF_F32, MGDWF_ERR_INVALID_ARG, "the squared coarse operator is F64 or F32");
+            if (prec == MGDWF_F64)
+              sq_apply64(h->Asq.m64.as<double2>(), h->buf<double2>("t_c", nc), h->buf<double2>("t_d", nc), h->cg, nrhs,
+                         h->st);
+            else
+              sq_apply32(h->Asq.m32.as<float2>(), h->buf<float2>("t_c32", nc), h->buf<float2>("t_d32", nc), h->cg,
+                         nrhs, h->st);
           } else if (k == MGDWF_K_COARSE) {
             if (prec == MGDWF_F64)
               coarse_apply64(h->Dc, h->buf<double2>("t_c", nc), h->buf<double2>("t_d", nc), h->cg, nrhs, h->st);

@@ -32,7 +32,7 @@ void restrict_op(const C2* V, const C2* x, CC2* coarse, double* partial, const G
                  const CoarseGeometry& cg, int nrhs, hipStream_t st);
 // from dslash.hip
 void dslash_split(const double2* in, double2* out9, const double2* gauge, const Geometry& g, const int block[4],
-                  double M5, double mf, int chi, hipStream_t st);
+                  double M5, double mf, int chi, hipStream_t st, bool dagger = false);
 
 namespace {
 

@@ -23,6 +23,8 @@ struct mgdwf_ctx {
   mgdwf::DevBuf Vnull;       // the near-null vectors the basis was built from (FP64, internal layout)
   int nnull = 0;             // how many: nvec/2 after a setup, nvec after set_nullvecs
   mgdwf::CoarseStore Dc, DcH;  // coarse operator and its adjoint stencil, all precisions
+  mgdwf::CoarseStore Asq;      // squared-operator coarse operator (33 offsets; FP64 and FP32 copies)
+  int coarse_kind = 0;         // which coarse operator is built: 0 the 9-point D_c, 1 the squared A_c
 
   mgdwf_mg_params mp{};
   bool have_params = false;

@@ -225,8 +225,9 @@ __global__ __launch_bounds__(256) void k_dslash(const C2* __restrict__ in, C2* _
   }
 }
 
-// Face-split operator for the coarse-operator build (FP64): the nine pieces of
-// D applied to P_chi psi (the chirality-chi spins of psi):
+// Face-split operator for the coarse-operator builds (FP64): the nine pieces
+// of D (or of D^+ with DAG) applied to P_chi psi (the chirality-chi spins of
+// psi; all spins when chi < 0):
 //   out[0]          diagonal, fifth-dimension hop and every 4D hop that stays
 //                   inside the site's block;
 //   out[1 + 2 mu]   the +mu hop of sites on the upper block face;
@@ -251,10 +252,10 @@ __device__ __forceinline__ void load_masked(Spinor<double2>& p, const double2* _
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      if ((sp >> 1) != chi) p.v[sp][c] = make_double2(0.0, 0.0);
+      if (chi >= 0 && (sp >> 1) != chi) p.v[sp][c] = make_double2(0.0, 0.0);
 }
 
-template <int MU>
+template <int MU, bool DAG>
 __device__ __forceinline__ void split_dir(Spinor<double2>& self, double2* __restrict__ out, const double2* __restrict__ in,
                                           const double2* __restrict__ gauge, const SplitArgs& a, long long i5, int x4,
                                           int s, const int co[4], const int stride[4]) {
@@ -273,16 +274,17 @@ __device__ __forceinline__ void split_dir(Spinor<double2>& self, double2* __rest
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int c = 0; c < 3; ++c) f.v[sp][c] = make_double2(0.0, 0.0);
-    if (dir == 0) {  // -1/2 (1 - g_mu) U_mu(x) psi(x + mu)
+    constexpr int EF = DAG ? 1 : -1, EB = DAG ? -1 : 1;
+    if (dir == 0) {  // -1/2 (1 -+ g_mu) U_mu(x) psi(x + mu)
       load_masked(p, in, V5, (long long)xf * a.Ls + s, a.chi);
-      project<MU, -1>(p, h);
+      project<MU, EF>(p, h);
       transport<false>(gauge, MU, V4, x4, h, u);
-      accumulate<MU, -1>(f, u);
-    } else {         // -1/2 (1 + g_mu) U_mu(x - mu)^+ psi(x - mu)
+      accumulate<MU, EF>(f, u);
+    } else {         // -1/2 (1 +- g_mu) U_mu(x - mu)^+ psi(x - mu)
       load_masked(p, in, V5, (long long)xb * a.Ls + s, a.chi);
-      project<MU, 1>(p, h);
+      project<MU, EB>(p, h);
       transport<true>(gauge, MU, V4, xb, h, u);
-      accumulate<MU, 1>(f, u);
+      accumulate<MU, EB>(f, u);
     }
     const double sc = -0.5 * (dir == 0 ? phf : phb);
     const bool face = dir == 0 ? upper_face : lower_face;
@@ -302,6 +304,7 @@ __device__ __forceinline__ void split_dir(Spinor<double2>& self, double2* __rest
   }
 }
 
+template <bool DAG>
 __global__ __launch_bounds__(256) void k_dslash_split(const double2* __restrict__ in, double2* __restrict__ out,
                                                       const double2* __restrict__ gauge, SplitArgs a) {
   const long long i5 = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -329,14 +332,15 @@ __global__ __launch_bounds__(256) void k_dslash_split(const double2* __restrict_
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       double2 r = cscale(p.v[sp][c], a.diag);
-      if (sp >= 2) r = cadd(r, cscale(pu.v[sp][c], cup));  // D: P_- couples to s+1
-      else r = cadd(r, cscale(pd.v[sp][c], cdn));          //    P_+ couples to s-1
+      // D: P_- couples to s+1 and P_+ to s-1; D^+ the other way round
+      if ((sp >= 2) != DAG) r = cadd(r, cscale(pu.v[sp][c], cup));
+      else r = cadd(r, cscale(pd.v[sp][c], cdn));
       self.v[sp][c] = r;
     }
-  split_dir<0>(self, out, in, gauge, a, i5, x4, s, co, stride);
-  split_dir<1>(self, out, in, gauge, a, i5, x4, s, co, stride);
-  split_dir<2>(self, out, in, gauge, a, i5, x4, s, co, stride);
-  split_dir<3>(self, out, in, gauge, a, i5, x4, s, co, stride);
+  split_dir<0, DAG>(self, out, in, gauge, a, i5, x4, s, co, stride);
+  split_dir<1, DAG>(self, out, in, gauge, a, i5, x4, s, co, stride);
+  split_dir<2, DAG>(self, out, in, gauge, a, i5, x4, s, co, stride);
+  split_dir<3, DAG>(self, out, in, gauge, a, i5, x4, s, co, stride);
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -1733,11 +1737,14 @@ void dslash(const C2* in, C2* out, const C2* b, const C2* gauge, const Geometry&
 }
 
 void dslash_split(const double2* in, double2* out9, const double2* gauge, const Geometry& g, const int block[4],
-                  double M5, double mf, int chi, hipStream_t st) {
+                  double M5, double mf, int chi, hipStream_t st, bool dagger) {
   SplitArgs a;
   for (int m = 0; m < 4; ++m) { a.L[m] = g.L[m]; a.b[m] = block[m]; a.ph[m] = (float)g.bc[m]; }
   a.Ls = g.Ls; a.V4 = g.V4; a.V5 = g.V5; a.diag = 5.0 - M5; a.mf = mf; a.chi = chi;
-  hipLaunchKernelGGL(k_dslash_split, dim3(ceil_div(g.V5, 256)), dim3(256), 0, st, in, out9, gauge, a);
+  if (dagger)
+    hipLaunchKernelGGL(k_dslash_split<true>, dim3(ceil_div(g.V5, 256)), dim3(256), 0, st, in, out9, gauge, a);
+  else
+    hipLaunchKernelGGL(k_dslash_split<false>, dim3(ceil_div(g.V5, 256)), dim3(256), 0, st, in, out9, gauge, a);
   MG_LAUNCH_CHECK();
 }
 

@@ -30,6 +30,8 @@ constexpr int S_DOT = 8;                                          // multidot bl
 constexpr int S_QN = 48;                                          // |q_k|^2 at S_QN+k, <q_k, r> after it
 constexpr int S_RIN = 70, S_R64 = 71, S_B = 72, S_TMP = 73;       // FGCR residuals
 constexpr int S_GRR_A = 80, S_GRR_B = 81, S_GPAP = 82;            // CG on the normal equations
+constexpr int S_SQ = 84;                                          // squared smoother: |p|^2, <p, r>
+constexpr int S_CPQ = 88;                                         // coarse CG: |p|^2, <p, A_c p>
 constexpr int S_MR = 96;                                          // MR step i: |p_i|^2, |q_i|^2 at S_MR + 2i, +1
 
 template <class C2> struct Prec;
@@ -334,6 +336,120 @@ struct TwoLevel {
   }
 };
 
+// ---------------------------------------------------------------- squared V-cycle
+// The multigrid on N = D^+ D that the paper ran (Sec. 3, first paragraph;
+// Sec. 4): z = M b = V(D^+ b), V the five-step V-cycle of Sec. 2 on N with
+// minimal-residual smoothing on N, the Galerkin coarse operator
+// A_c = P^+ N P (33-point, Hermitian) solved by CG, and the residual after
+// the coarse correction recomputed with N.  M approximates N^-1 D^+ = D^-1,
+// so it preconditions the same flexible GCR on D x = b.
+inline void sq_op(mgdwf_ctx* c, const double2* x, double2* y, int nrhs) {
+  sq_apply64(c->Asq.m64.as<double2>(), x, y, c->cg, nrhs, c->st);
+  c->coarse_applies += 1;
+}
+inline void sq_op(mgdwf_ctx* c, const float2* x, float2* y, int nrhs) {
+  sq_apply32(c->Asq.m32.as<float2>(), x, y, c->cg, nrhs, c->st);
+  c->coarse_applies += 1;
+}
+
+template <class F2>
+struct TwoLevelSq {
+  mgdwf_ctx* c;
+  int nrhs;
+  mgdwf_mg_params p;
+  long long nf, nc;
+  F2 *g, *ra, *rb, *t, *q, *r1, *r3;
+  F2 *cb, *cx, *cr, *cp, *cq;
+  double* sl;
+  double* vpart;
+
+  TwoLevelSq(mgdwf_ctx* ctx, int n_rhs, const mgdwf_mg_params& prm) : c(ctx), nrhs(n_rhs), p(prm) {
+    nf = c->fine_len();
+    nc = c->coarse_len();
+    const std::string tg = Prec<F2>::tag;
+    g = c->buf<F2>("sq_g" + tg, nf * nrhs);
+    ra = c->buf<F2>("sq_ra" + tg, nf * nrhs);
+    rb = c->buf<F2>("sq_rb" + tg, nf * nrhs);
+    t = c->buf<F2>("sq_t" + tg, nf * nrhs);
+    q = c->buf<F2>("sq_q" + tg, nf * nrhs);
+    r1 = c->buf<F2>("sq_r1" + tg, nf * nrhs);
+    r3 = c->buf<F2>("sq_r3" + tg, nf * nrhs);
+    cb = c->buf<F2>("sq_cb" + tg, nc * nrhs);
+    cx = c->buf<F2>("sq_cx" + tg, nc * nrhs);
+    cr = c->buf<F2>("sq_cr" + tg, nc * nrhs);
+    cp = c->buf<F2>("sq_cp" + tg, nc * nrhs);
+    cq = c->buf<F2>("sq_cq" + tg, nc * nrhs);
+    sl = c->buf<double>("slots", (size_t)nrhs * NSLOT);
+    vpart = c->buf<double>("vpart", (size_t)VEC_BLOCKS * nrhs * (2 * 16 + 3));
+  }
+
+  // nu minimal-residual steps on N x = f along the residual itself (q = N r,
+  // alpha = <q, r>/|q|^2), x from 0 or added to (add_x); the last residual
+  // goes to rout (which must differ from f and from ra, rb) unless rout is
+  // null.  Two applications of D per step.
+  void smooth(const F2* f, F2* x, F2* rout, int nu, bool add_x) {
+    const F2* rin = f;
+    for (int i = 0; i < nu; ++i) {
+      fine_op<F2>(c, rin, t, nullptr, false, 0, nrhs, -1);  // t = D r
+      fine_op<F2>(c, t, q, nullptr, true, 0, nrhs, -1);     // q = D^+ t = N r
+      norm_into<F2>(c, q, rin, nf, nrhs, S_SQ);             // |q|^2, <q, r>
+      F2* rnew = (i + 1 == nu && rout) ? rout : (rin == ra ? rb : ra);
+      mrh_update<F2>(x, rnew, rin, q, nf, nrhs, sl, S_SQ + 1, S_SQ, i == 0 && !add_x, c->st);
+      rin = rnew;
+    }
+  }
+
+  // CG on A_c x = b from x = 0, to |r| <= tol |b| tested every 8 iterations, or maxiter
+  void coarse_solve(const F2* b, F2* x) {
+    copy(c, b, cr, nc * nrhs);
+    copy(c, b, cp, nc * nrhs);
+    norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR0);
+    norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR_A);
+    int cur = S_CRR_A, nxt = S_CRR_B;
+    const double tol2 = p.coarse_tol * p.coarse_tol;
+    for (int it = 0; it < p.coarse_maxiter;) {
+      sq_op(c, cp, cq, nrhs);                                               // q = A_c p
+      norm_into<F2>(c, cp, cq, nc, nrhs, S_CPQ);                            // <p, q> at S_CPQ + 1
+      mr_update<F2>(x, cr, cp, cq, nc, nrhs, sl, cur, S_CPQ + 1, it == 0, vpart, c->st);  // x += a p, r -= a q
+      finalize_rhs(vpart, vec_blocks(nc), 1, sl, nxt, nrhs, c->st);          // |r|^2
+      cg_dir<F2>(cp, cr, nc, nrhs, sl, nxt, cur, nullptr, c->st);           // p = r + beta p
+      std::swap(cur, nxt);
+      ++it;
+      if (it % 8 == 0 && it < p.coarse_maxiter) {
+        std::vector<double> h = read_slots(c, nrhs);
+        bool done = true;
+        for (int r = 0; r < nrhs; ++r)
+          if (!(h[r * NSLOT + cur] <= tol2 * h[r * NSLOT + S_CRR0])) done = false;
+        if (done) break;
+      }
+    }
+  }
+
+  void apply(const F2* b, F2* z) {
+    const F2* V = basis_of<F2>(c);
+    c->phase_mark(0);
+    fine_op<F2>(c, b, g, nullptr, true, 0, nrhs, -1);                      // g = D^+ b
+    if (p.nu_pre > 0) {
+      smooth(g, z, r1, p.nu_pre, false);                                    // x1 = S1(N, g), r1 = g - N x1
+    } else {
+      copy(c, g, r1, nf * nrhs);
+      zero<F2>(z, nf * nrhs, c->st);
+    }
+    restrict_op<F2, F2>(V, r1, cb, c->buf<double>("rpart", restrict_partial_doubles(c->cg, nrhs)), c->g, c->cg,
+                        nrhs, c->st);                                       // g2 = R r1
+    c->phase_mark(1);
+    coarse_solve(cb, cx);                                                   // x2 = CG(A_c, g2)
+    c->phase_mark(2);
+    prolong_op<F2, F2>(V, cx, z, true, c->g, c->cg, nrhs, c->st);          // x1 + P x2
+    if (p.nu_post > 0) {
+      fine_op<F2>(c, z, t, nullptr, false, 0, nrhs, -1);                    // g3 = g - N (x1 + P x2)
+      fine_op<F2>(c, t, r3, g, true, 1, nrhs, -1);
+      smooth(r3, z, nullptr, p.nu_post, true);                              // z += S3(N, g3)
+    }
+    c->phase_mark(3);
+  }
+};
+
 // ---------------------------------------------------------------- FGCR cycle
 // Up to `kmax` flexible GCR steps on D e = r (inner precision F2), e from 0.
 // Stops early when every |r|^2 <= stop2[rhs].  Returns the steps taken.
@@ -345,8 +461,8 @@ struct TwoLevel {
 // end as sum_j c_j z_j over the unmodified z_j (c = T b, T the unit upper
 // triangular map from z to z~).  Same iterates as updating z~ and e in place,
 // without streaming z and e through every step.
-template <class F2>
-int fgcr_cycle(mgdwf_ctx* c, TwoLevel<F2>& M, F2* r, F2* e, int nrhs, int kmax, const std::vector<double>& stop2,
+template <class F2, class MG>
+int fgcr_cycle(mgdwf_ctx* c, MG& M, F2* r, F2* e, int nrhs, int kmax, const std::vector<double>& stop2,
                std::vector<double>* rin2_out) {
   using cd = std::complex<double>;
   const long long nf = c->fine_len();
@@ -442,7 +558,7 @@ int fgcr_cycle(mgdwf_ctx* c, TwoLevel<F2>& M, F2* r, F2* e, int nrhs, int kmax, 
 
 // ---------------------------------------------------------------- public (C++) API
 
-template <class F2>
+template <class F2, class MG>
 static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const mgdwf_solve_params& sp,
                        mgdwf_solve_report* rep) {
   const long long nf = c->fine_len();
@@ -450,7 +566,7 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
   double2* r64 = c->buf<double2>("sol_r64", nf * nrhs);
   F2* rin = c->buf<F2>(std::string("sol_rin") + Prec<F2>::tag, nf * nrhs);
   F2* e = c->buf<F2>(std::string("sol_e") + Prec<F2>::tag, nf * nrhs);
-  TwoLevel<F2> M(c, nrhs, c->mp);
+  MG M(c, nrhs, c->mp);
   const long long fa0 = c->fine_applies, ca0 = c->coarse_applies, gs0 = c->gs_repeats, pf0 = c->persist_fallbacks;
   c->harvest_phases();
   const double ph0[3] = {c->phase_s[0], c->phase_s[1], c->phase_s[2]};
@@ -490,7 +606,7 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
     std::vector<double> stop2(nrhs);
     for (int r = 0; r < nrhs; ++r) stop2[r] = 0.25 * sp.tol * sp.tol * b2[r];
     int kmax = std::min(restart, sp.max_outer - outer);
-    int k = fgcr_cycle<F2>(c, M, rin, e, nrhs, kmax, stop2, nullptr);
+    int k = fgcr_cycle<F2, MG>(c, M, rin, e, nrhs, kmax, stop2, nullptr);
     add_to<F2, double2>(x64, e, nf * nrhs, c->st);
     outer += k;
     ++restarts;
@@ -519,19 +635,30 @@ static void solve_impl(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const
   if (!converged) fail(MGDWF_ERR_NOT_CONVERGED, "solve did not reach the requested tolerance");
 }
 
-void vcycle_apply(mgdwf_ctx* c, const double2* b64, double2* z64, int nrhs) {
+template <class F2, class MG>
+static void vcycle_apply_impl(mgdwf_ctx* c, const double2* b64, double2* z64, int nrhs) {
   const long long n = c->fine_len() * nrhs;
-  c->buf<double>("slots", (size_t)nrhs * NSLOT);
-  if (c->mp.fine_prec == MGDWF_F64) {
-    TwoLevel<double2> M(c, nrhs, c->mp);
+  MG M(c, nrhs, c->mp);
+  if constexpr (std::is_same<F2, double2>::value) {
     M.apply(b64, z64);
   } else {
     float2* b32 = c->buf<float2>("vca_b32", n);
     float2* z32 = c->buf<float2>("vca_z32", n);
     convert<double2, float2>(b64, b32, n, c->st);
-    TwoLevel<float2> M(c, nrhs, c->mp);
     M.apply(b32, z32);
     convert<float2, double2>(z32, z64, n, c->st);
+  }
+}
+
+void vcycle_apply(mgdwf_ctx* c, const double2* b64, double2* z64, int nrhs) {
+  c->buf<double>("slots", (size_t)nrhs * NSLOT);
+  const bool f64 = c->mp.fine_prec == MGDWF_F64;
+  if (c->mp.squared) {
+    if (f64) vcycle_apply_impl<double2, TwoLevelSq<double2>>(c, b64, z64, nrhs);
+    else vcycle_apply_impl<float2, TwoLevelSq<float2>>(c, b64, z64, nrhs);
+  } else {
+    if (f64) vcycle_apply_impl<double2, TwoLevel<double2>>(c, b64, z64, nrhs);
+    else vcycle_apply_impl<float2, TwoLevel<float2>>(c, b64, z64, nrhs);
   }
   c->harvest_phases();
 }
@@ -540,10 +667,12 @@ void mg_solve(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const mgdwf_so
               mgdwf_solve_report* rep) {
   if (c->mp.fine_prec == MGDWF_F64) {
     if (c->mp.coarse_prec != MGDWF_F64) fail(MGDWF_ERR_INVALID_ARG, "an FP64 fine level needs an FP64 coarse level");
-    solve_impl<double2>(c, b64, x64, nrhs, sp, rep);
+    if (c->mp.squared) solve_impl<double2, TwoLevelSq<double2>>(c, b64, x64, nrhs, sp, rep);
+    else solve_impl<double2, TwoLevel<double2>>(c, b64, x64, nrhs, sp, rep);
   } else if (c->mp.fine_prec == MGDWF_F32) {
     if (c->mp.coarse_prec == MGDWF_F64) fail(MGDWF_ERR_INVALID_ARG, "an FP32 fine level takes an F32/F16/BF16 coarse level");
-    solve_impl<float2>(c, b64, x64, nrhs, sp, rep);
+    if (c->mp.squared) solve_impl<float2, TwoLevelSq<float2>>(c, b64, x64, nrhs, sp, rep);
+    else solve_impl<float2, TwoLevel<float2>>(c, b64, x64, nrhs, sp, rep);
   } else {
     fail(MGDWF_ERR_INVALID_ARG, "fine precision must be F64 or F32");
   }
@@ -594,10 +723,13 @@ static double median_null_residual(mgdwf_ctx* c, double2* v, int nrhs) {
 
 void install_basis(mgdwf_ctx* c, const int block[4], int nvec);  // capi.cpp
 void build_coarse(mgdwf_ctx* c);                                 // capi.cpp
+void build_coarse_squared(mgdwf_ctx* c);                         // capi.cpp
 
-// Adaptive setup (paper Sec. 2): W holds nh = nvec/2 internal FP64 fields on entry.
+// Adaptive setup (paper Sec. 2): W holds nh internal FP64 fields on entry,
+// nh = nvec / 2 (each paired with its reflection) or, for the squared
+// operator, nh = nvec (the basis is the vectors themselves).
 void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_report* rep) {
-  const int nh = p.nvec / 2;
+  const int nh = p.squared ? p.nvec : p.nvec / 2;
   const long long nf = c->fine_len();
   auto t0 = std::chrono::steady_clock::now();
   int nsw = 0;
@@ -606,10 +738,16 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
   auto rebuild = [&]() {
     // basis fields: the nh vectors and their fifth-dimension reflections
     c->cg.Nv = p.nvec;
+    c->V64.alloc(nf * p.nvec * sizeof(double2));
+    if (p.squared) {
+      copy(c, W, c->V64.as<double2>(), nf * p.nvec);
+      install_basis(c, p.block, p.nvec);
+      build_coarse_squared(c);
+      return;
+    }
     double2* V = c->buf<double2>("setup_vfull", nf * p.nvec);
     copy(c, W, V, nf * nh);
     reflect5<double2>(W, V + nf * nh, c->g, nh, c->st);
-    c->V64.alloc(nf * p.nvec * sizeof(double2));
     copy(c, V, c->V64.as<double2>(), nf * p.nvec);
     install_basis(c, p.block, p.nvec);
     build_coarse(c);
@@ -625,14 +763,20 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
     // sweep_iters flexible-GCR steps with the current V-cycle on D x = 0 from
     // x = W, i.e. e from 0 on D e = -D W and then W <- W + e, so W keeps what
     // the current multigrid fails to remove; then normalise and rebuild
-    TwoLevel<double2> M(c, nh, sweep);
     double2* r = c->buf<double2>("setup_r", nf * nh);
     double2* e = c->buf<double2>("setup_e", nf * nh);
     double2* z = c->buf<double2>("setup_zero", nf * nh);
     zero<double2>(z, nf * nh, c->st);
     fine_op<double2>(c, W, r, z, false, 1, nh, -1);  // r = 0 - D W
     std::vector<double> stop2(nh, -1.0);             // never met: exactly sweep_iters steps
-    fgcr_cycle<double2>(c, M, r, e, nh, std::max(1, std::min(p.sweep_iters, 16)), stop2, nullptr);
+    const int kmax = std::max(1, std::min(p.sweep_iters, 16));
+    if (p.squared) {
+      TwoLevelSq<double2> M(c, nh, sweep);
+      fgcr_cycle<double2>(c, M, r, e, nh, kmax, stop2, nullptr);
+    } else {
+      TwoLevel<double2> M(c, nh, sweep);
+      fgcr_cycle<double2>(c, M, r, e, nh, kmax, stop2, nullptr);
+    }
     add_to<double2, double2>(W, e, nf * nh, c->st);
     normalise(c, W, nh);
     rebuild();
@@ -646,7 +790,8 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
   c->have_params = true;
   // the setup's work fields are large (several per vector): give them back
   for (auto it = c->ws.begin(); it != c->ws.end();) {
-    if (it->first.rfind("cg_", 0) == 0 || it->first.rfind("setup_", 0) == 0 || it->first.rfind("dc_", 0) == 0)
+    if (it->first.rfind("cg_", 0) == 0 || it->first.rfind("setup_", 0) == 0 || it->first.rfind("dc_", 0) == 0 ||
+        it->first.rfind("sq_", 0) == 0)
       it = c->ws.erase(it);
     else
       ++it;

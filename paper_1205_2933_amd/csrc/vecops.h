@@ -37,6 +37,11 @@ void lincomb_c(C2* x, const C2* const* ps, int nv, long long n, int nrhs, const 
 template <class C2>
 void gcr_update(C2* e, C2* r, const C2* z, const C2* q, long long n, int nrhs, const double* sl, int cr, int nq,
                 bool first, double* partial, hipStream_t st);
+// x = (first ? 0 : x) + alpha rin, rnew = rin - alpha p, alpha = <p, rin>/|p|^2 from
+// slots cr (complex) and nq: a minimal-residual step on a Hermitian operator
+template <class C2>
+void mrh_update(C2* x, C2* rnew, const C2* rin, const C2* p, long long n, int nrhs, const double* sl, int cr, int nq,
+                bool first, hipStream_t st);
 template <class C2>
 void scale_by_rsqrt_slot(C2* y, const C2* x, long long n, int nrhs, const double* sl, int den, hipStream_t st);
 template <class A2, class B2>
@@ -95,5 +100,16 @@ bool coarse_cgne_persistent(const CoarseStore& D, const CoarseStore& DH, mgdwf_p
                             float2* r, float2* p, void* work, long long* count, const CoarseGeometry& cg, int nrhs,
                             double tol, int maxiter, double wait_seconds, int device, hipStream_t st);
 int persistent_cgne_error(const void* work, const CoarseGeometry& cg, int nrhs, hipStream_t st);
+
+// squared.hip: A_c = P^+ D^+ D P, 33 offsets [X][o] of column-major 2Nv x 2Nv
+// blocks (o: self, +-mu, then the diagonals +-mu +-nu, mu < nu)
+size_t sq_coarse_entries(const CoarseGeometry& cg);
+void build_sq_coarse_op(const double2* Vhat, const double2* gauge, double2* Ac, double2* work9, double2* zwork9,
+                        double2* cwork, double* partial, const Geometry& g, const CoarseGeometry& cg, double M5,
+                        double mf, hipStream_t st);
+void sq_to_f32(const double2* Ac, float2* Ac32, const CoarseGeometry& cg, hipStream_t st);
+void sq_canonical(const double2* Ac, double2* out, const CoarseGeometry& cg, hipStream_t st);
+void sq_apply64(const double2* Ac, const double2* x, double2* y, const CoarseGeometry& cg, int nrhs, hipStream_t st);
+void sq_apply32(const float2* Ac32, const float2* x, float2* y, const CoarseGeometry& cg, int nrhs, hipStream_t st);
 
 }  // namespace mgdwf

@@ -265,6 +265,28 @@ __global__ __launch_bounds__(256) void k_gcr_update(C2* __restrict__ e, C2* __re
   }
 }
 
+// Minimal-residual step on a Hermitian operator N with the direction r itself:
+// x = (first ? 0 : x) + alpha rin, rnew = rin - alpha p, p = N rin,
+// alpha = <p, rin> / |p|^2 (complex <p, rin> at slots cr, cr + 1, |p|^2 at nq).
+// rnew must not alias rin.
+template <class C2>
+__global__ __launch_bounds__(256) void k_mrh_update(C2* __restrict__ x, C2* __restrict__ rnew,
+                                                    const C2* __restrict__ rin, const C2* __restrict__ p, long long n,
+                                                    const double* __restrict__ sl, int cr_, int nq, int first) {
+  using T = typename real_of<C2>::type;
+  const int rhs = blockIdx.y;
+  const long long off = rhs * n;
+  const double d = slot(sl, rhs, nq);
+  const double inv = d > 0.0 ? 1.0 / d : 0.0;
+  const C2 alpha = cmk<C2>((T)(slot(sl, rhs, cr_) * inv), (T)(slot(sl, rhs, cr_ + 1) * inv));
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const C2 rv = rin[off + i];
+    const C2 xv = first ? cmk<C2>(0, 0) : x[off + i];
+    x[off + i] = cadd(xv, cmul(alpha, rv));
+    rnew[off + i] = csub(rv, cmul(alpha, p[off + i]));
+  }
+}
+
 // x = sum_m c[rhs][m] p_m with complex coefficients c (FP64, [rhs][16]), m < nv
 template <class C2>
 __global__ __launch_bounds__(256) void k_lincomb_c(C2* __restrict__ x, const C2* const* __restrict__ ps, int nv,
@@ -430,6 +452,14 @@ void gcr_update(C2* e, C2* r, const C2* z, const C2* q, long long n, int nrhs, c
 }
 
 template <class C2>
+void mrh_update(C2* x, C2* rnew, const C2* rin, const C2* p, long long n, int nrhs, const double* sl, int cr, int nq,
+                bool first, hipStream_t st) {
+  hipLaunchKernelGGL(k_mrh_update<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, x, rnew, rin, p, n, sl, cr, nq,
+                     first ? 1 : 0);
+  MG_LAUNCH_CHECK();
+}
+
+template <class C2>
 void scale_by_rsqrt_slot(C2* y, const C2* x, long long n, int nrhs, const double* sl, int den, hipStream_t st) {
   hipLaunchKernelGGL(k_scale_slot<C2>, dim3(vec_blocks(n), nrhs), dim3(256), 0, st, y, x, n, sl, den);
   MG_LAUNCH_CHECK();
@@ -474,6 +504,8 @@ void reflect5(const C2* in, C2* out, const Geometry& g, int nf, hipStream_t st) 
   template void gcr_update<C2>(C2*, C2*, const C2*, const C2*, long long, int, const double*, int, int, bool,   \
                                double*, hipStream_t);                                                            \
   template void scale_by_rsqrt_slot<C2>(C2*, const C2*, long long, int, const double*, int, hipStream_t);       \
+  template void mrh_update<C2>(C2*, C2*, const C2*, const C2*, long long, int, const double*, int, int, bool,    \
+                               hipStream_t);                                                                    \
   template void zero<C2>(C2*, long long, hipStream_t);                                                           \
   template void reflect5<C2>(const C2*, C2*, const Geometry&, int, hipStream_t);
 MG_INST(double2)
