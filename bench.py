@@ -194,6 +194,65 @@ def ragged_leg(mg, h_main, B_main, log):
     return out
 
 
+SQ_NVEC, SQ_SWEEP0, SQ_NU, SQ_CTOL = 24, 200, 5, 0.3
+
+
+def sq_params(mg, fine, coarse):
+    """The squared-operator multigrid (the paper's own): 24 adaptive vectors
+    (48 coarse dof per site), 5 + 5 MR steps on D^+D, coarse CG to 0.3."""
+    return mg.make_mg_params(BLOCK, SQ_NVEC, sweeps=1, sweep0_iters=SQ_SWEEP0, nu_pre=SQ_NU, nu_post=SQ_NU,
+                             coarse_tol=SQ_CTOL, coarse_maxiter=400, fine_prec=fine, coarse_prec=coarse, squared=True)
+
+
+def squared_leg(mg, U_dev, B_main, log):
+    """The multigrid on the squared operator D^+D that the paper ran: A_c =
+    P^+ D^+D P (33-point), MR smoothing on D^+D, CG on A_c, preconditioning the
+    same FP64-refined flexible GCR on D x = b.  Setup from random starts, then
+    one warm-up and one timed 12-RHS mixed-precision step (FP32 fine and
+    coarse level), and one FP64 single-RHS solve."""
+    import torch
+
+    from inputs import random_starts
+
+    h = mg.Handle(L_MAIN, LS, M5, MF)
+    mg.mgdwf_set_gauge(h, U_dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    srep = mg.mgdwf_setup(h, sq_params(mg, "f64", "f64"), torch.from_numpy(random_starts(L_MAIN, LS, SQ_NVEC, 21)).cuda())
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    mg.mgdwf_set_mg_params(h, sq_params(mg, "f32", "f32"))
+    X = torch.zeros_like(B_main)
+    mg.mgdwf_solve(h, B_main, X, nrhs=12, tol=1e-10, max_outer=400, restart=8)  # warm-up: workspaces
+    X.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = mg.mgdwf_solve(h, B_main, X, nrhs=12, tol=1e-10, max_outer=400, restart=8)
+    torch.cuda.synchronize()
+    s12 = (time.perf_counter() - t) / 12
+    del X
+    mg.mgdwf_set_mg_params(h, sq_params(mg, "f64", "f64"))
+    x1 = torch.zeros_like(B_main[0])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r64 = mg.mgdwf_solve(h, B_main[0].contiguous(), x1, nrhs=1, tol=1e-10, max_outer=400, restart=8)[0]
+    torch.cuda.synchronize()
+    s64 = time.perf_counter() - t
+    h.close()
+    torch.cuda.empty_cache()
+    r0 = reps[0]
+    out = {"nvec": SQ_NVEC, "coarse_dof_per_site": 2 * SQ_NVEC, "sweep0_iters": SQ_SWEEP0, "nu": [SQ_NU, SQ_NU],
+           "coarse_tol": SQ_CTOL, "setup_s": setup_s, "null_residual": srep["null_residual"],
+           "mixed_12rhs_s_per_rhs": s12, "mixed_outer_iters": r0["outer_iters"],
+           "mixed_fine_applies_per_rhs": r0["fine_applies"], "mixed_coarse_applies_per_rhs": r0["coarse_applies"],
+           "mixed_max_true_relres": max(r["true_relres"] for r in reps),
+           "mixed_phases_s": r0["phase_seconds"],
+           "fp64_s_per_rhs": s64, "fp64_outer_iters": r64["outer_iters"], "fp64_fine_applies": r64["fine_applies"],
+           "note": "coarse operator P^+ D^+D P (33-point stencil), FP32 coarse level, coarse solve as launched kernels"}
+    log(f"squared-operator multigrid {out}")
+    return out
+
+
 def mass_leg(mg, U_dev, B_main, log):
     """Iteration count versus quark mass (m_f = 0.01, 0.003, 0.001) on the main
     gauge field (eps = 0.3) and on a rougher one (eps = 0.6, seed 13), both with
@@ -231,6 +290,21 @@ def mass_leg(mg, U_dev, B_main, log):
                    "mg_outer_iters": r["outer_iters"], "mg_true_relres": r["true_relres"],
                    "mg_fine_applies": r["fine_applies"], "mg_s": mg_s, "cgne_iters": c["outer_iters"],
                    "cgne_fine_applies": c["fine_applies"], "cgne_s": cg_s}
+            # the squared-operator multigrid (the paper's) on the same field, mass and source
+            h.close()
+            h = mg.Handle(L_MAIN, LS, M5, mf)
+            mg.mgdwf_set_gauge(h, U_dev if eps == 0.3 else U06)
+            mg.mgdwf_setup(h, sq_params(mg, "f64", "f64"),
+                           torch.from_numpy(random_starts(L_MAIN, LS, SQ_NVEC, 21)).cuda())
+            mg.mgdwf_set_mg_params(h, sq_params(mg, "f32", "f32"))
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rs = mg.mgdwf_solve(h, b, x, nrhs=1, tol=1e-10, max_outer=400, restart=8, allow_not_converged=True)[0]
+            torch.cuda.synchronize()
+            row.update({"sq_mg_outer_iters": rs["outer_iters"], "sq_mg_fine_applies": rs["fine_applies"],
+                        "sq_mg_true_relres": rs["true_relres"], "sq_mg_s": time.perf_counter() - t,
+                        "cgne_over_sq_mg_fine_applies": c["fine_applies"] / rs["fine_applies"]})
             log(f"mass scan {row}")
             out.append(row)
             h.close()
@@ -362,6 +436,7 @@ def main():
     ap.add_argument("--no-ragged", action="store_true", help="skip the 48-solve ragged batch")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup comparison")
     ap.add_argument("--no-mass-scan", action="store_true", help="skip the iteration count versus m_f")
+    ap.add_argument("--no-squared", action="store_true", help="skip the squared-operator multigrid step")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -568,6 +643,10 @@ def main():
                      "algorithmic_bytes": bytes32_12, "launch_us": ms32_12 * 1e3, "traffic": counted_traffic(tiling["id"])},
     }
     # the legs below change the main handle's setup, so they come last
+    if not args.no_squared:
+        mg.mgdwf_trim(h)
+        torch.cuda.empty_cache()
+        out["squared_operator_mg"] = squared_leg(mg, U_dev, B, log)
     if not args.no_mass_scan:
         mg.mgdwf_trim(h)
         torch.cuda.empty_cache()
