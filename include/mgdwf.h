@@ -226,6 +226,20 @@ mgdwf_status mgdwf_get_coarse_op(mgdwf_handle h, double* Dc);
 mgdwf_status mgdwf_apply_coarse(mgdwf_handle h, const double* in, double* out, int32_t dagger,
                                 mgdwf_prec prec, int32_t nrhs);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation and kernels as mgdwf_apply_coarse, allocating nothing.  Reduced
+ * precisions stage the FP32 input and output (and the 16-bit packed input)
+ * in a static 16 MiB device array that the library holds on every GPU it
+ * runs on until the process ends: 2 x (nrhs Vc 2Nv x 8 B, rounded up to 256 B)
+ * plus, for F16/BF16, nrhs Vc (4 Nv x 2 B + 4 B) + 256 B must fit, else
+ * MGDWF_ERR_INVALID_ARG (F64 needs no scratch).  Every call on one GPU
+ * shares that array: calls that overlap on the same GPU (on different
+ * streams or from different threads) race and must be ordered by the
+ * caller.  Stream ordered and asynchronous, like mgdwf_apply_coarse. */
+mgdwf_status mgdwf_apply_coarse_noalloc(mgdwf_handle h, const double* in, double* out, int32_t dagger,
+                                        mgdwf_prec prec, int32_t nrhs);
+
 /* ---- setup and solve (steps a8-a11): Sec. 2, Sec. 3 -------------------- */
 
 /* Adaptive setup (Sec. 2): starting from nvec/2 random vectors V0 (nvec when

@@ -122,6 +122,7 @@ def _load() -> ctypes.CDLL:
         "mgdwf_build_coarse_squared": ([H], ctypes.c_int),
         "mgdwf_coarse_stencil_size": ([H], ctypes.c_int32),
         "mgdwf_apply_coarse": ([H, P, P, i32, ctypes.c_int, i32], ctypes.c_int),
+        "mgdwf_apply_coarse_noalloc": ([H, P, P, i32, ctypes.c_int, i32], ctypes.c_int),
         "mgdwf_setup": ([H, ctypes.POINTER(mgdwf_mg_params), P, ctypes.POINTER(mgdwf_setup_report)], ctypes.c_int),
         "mgdwf_set_mg_params": ([H, ctypes.POINTER(mgdwf_mg_params)], ctypes.c_int),
         "mgdwf_solve": ([H, P, P, i32, ctypes.POINTER(mgdwf_solve_params), ctypes.POINTER(mgdwf_solve_report)],
@@ -297,6 +298,12 @@ def mgdwf_get_coarse_op(h: Handle, Dc: torch.Tensor):
 def mgdwf_apply_coarse(h: Handle, inp: torch.Tensor, out: torch.Tensor, dagger=False, prec="f64", nrhs=1):
     n = h.ncoarse * nrhs
     _check(h.h, _lib.mgdwf_apply_coarse(h.h, _dev(inp, n, "in"), _dev(out, n, "out"), int(dagger), PREC[prec], nrhs))
+
+
+def mgdwf_apply_coarse_noalloc(h: Handle, inp: torch.Tensor, out: torch.Tensor, dagger=False, prec="f64", nrhs=1):
+    n = h.ncoarse * nrhs
+    _check(h.h, _lib.mgdwf_apply_coarse_noalloc(h.h, _dev(inp, n, "in"), _dev(out, n, "out"), int(dagger), PREC[prec],
+                                                nrhs))
 
 
 def make_mg_params(block, nvec, sweeps=1, sweep0_iters=100, sweep_iters=4, nu_pre=4, nu_post=4,

@@ -2,6 +2,8 @@
 // conversion at the boundary, and conversion of C++ errors to status codes.
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -14,6 +16,27 @@ using namespace mgdwf;
 namespace {
 
 thread_local std::string g_create_error;
+
+// Static scratch for mgdwf_apply_coarse_noalloc: every GPU the library runs
+// on holds one copy until the process ends.  In host code `scratch` names a
+// host-side stand-in, not a device address: its address on each device is
+// taken once per device with hipGetSymbolAddress (with that device current)
+// and kept; only that address is ever handed to kernels or copies.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_addr;
+
+void* scratch_address(int device) {  // `device` is the current device
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr) fail(MGDWF_ERR_HIP, "hipGetSymbolAddress of the scratch array failed");
+  g_scratch_addr[device] = p;
+  return p;
+}
 
 template <class F>
 mgdwf_status guarded(mgdwf_ctx* c, F&& f) {
@@ -181,6 +204,12 @@ mgdwf_status mgdwf_create(const mgdwf_action* a, void* hip_stream, mgdwf_handle*
     if (hipGetDevice(&c->device) != hipSuccess) {
       delete c;
       fail(MGDWF_ERR_HIP, "no HIP device");
+    }
+    try {
+      c->scratch = scratch_address(c->device);
+    } catch (...) {
+      delete c;
+      throw;
     }
     *out = c;
   });
@@ -390,6 +419,43 @@ mgdwf_status mgdwf_apply_coarse(mgdwf_handle h, const double* in, double* out, i
                      h->g.ctile, h->st);
       convert<float2, double2>(b, reinterpret_cast<double2*>(out), n, h->st);
     }
+  });
+}
+
+mgdwf_status mgdwf_apply_coarse_noalloc(mgdwf_handle h, const double* in, double* out, int32_t dagger,
+                                        mgdwf_prec prec, int32_t nrhs) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(in && out && nrhs >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
+    need(h->have_coarse, MGDWF_ERR_STATE, "coarse operator not built");
+    need(prec >= MGDWF_F64 && prec <= MGDWF_BF16, MGDWF_ERR_INVALID_ARG, "bad coarse precision");
+    const bool sq = h->coarse_kind == 1;
+    if (sq)
+      need(prec == MGDWF_F64 || prec == MGDWF_F32, MGDWF_ERR_INVALID_ARG, "the squared coarse operator is F64 or F32");
+    if (!sq && (prec == MGDWF_F16 || prec == MGDWF_BF16))
+      need(h->cg.n2 % 16 == 0 && h->cg.n2 <= 64, MGDWF_ERR_INVALID_ARG,
+           "16-bit coarse operator needs nvec divisible by 8 (and 2 nvec <= 64)");
+    const long long n = h->coarse_len() * nrhs;
+    const double2* x = reinterpret_cast<const double2*>(in);
+    double2* y = reinterpret_cast<double2*>(out);
+    if (prec == MGDWF_F64) {  // works on the caller's buffers directly: no scratch
+      if (sq) sq_apply64(h->Asq.m64.as<double2>(), x, y, h->cg, nrhs, h->st);
+      else coarse_apply64(dagger ? h->DcH : h->Dc, x, y, h->cg, nrhs, h->st);
+      return;
+    }
+    // scratch: the FP32 input and output, then the 16-bit packed input
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t vec = up((size_t)n * sizeof(float2));
+    const size_t pack = (!sq && prec != MGDWF_F32) ? coarse_pack_bytes(h->cg, nrhs) : 0;
+    need(2 * vec + pack <= kScratchBytes, MGDWF_ERR_INVALID_ARG,
+         "coarse vectors too large for the 16 MiB no-allocation scratch (use mgdwf_apply_coarse)");
+    char* s = static_cast<char*>(h->scratch);
+    float2* a = reinterpret_cast<float2*>(s);
+    float2* b = reinterpret_cast<float2*>(s + vec);
+    convert<double2, float2>(x, a, n, h->st);
+    if (sq) sq_apply32(h->Asq.m32.as<float2>(), a, b, h->cg, nrhs, h->st);
+    else coarse_apply32(dagger ? h->DcH : h->Dc, prec, a, b, h->cg, nrhs, s + 2 * vec, h->g.ctile, h->st);
+    convert<float2, double2>(b, y, n, h->st);
   });
 }
 

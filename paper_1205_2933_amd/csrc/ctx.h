@@ -13,6 +13,7 @@ struct mgdwf_ctx {
   double M5 = 0.0, mf = 0.0;
   hipStream_t st = nullptr;
   int device = 0;
+  void* scratch = nullptr;  // device address of this GPU's static scratch array (no-allocation entry point)
 
   mgdwf::DevBuf U64, U32;  // links, FP64 and FP32 (the FP32 buffer holds a site-major copy after the first)
   bool have_gauge = false;
