@@ -315,6 +315,15 @@ def mass_leg(mg, U_dev, B_main, log):
 N_TRAIN, N_EVAL = 200, 8
 
 
+L_C5 = (24, 24, 24, 48)
+
+
+def c5_field():
+    """The learned leg's inference lattice 24^3 x 48 (eps 0.3, seed 16, 2 APE steps)."""
+    from inputs import prepare_gauge
+    return prepare_gauge(L_C5, 0.3, 16, ape_steps=2)
+
+
 def training_fields():
     """The learned leg's 8^4 x 8 lattices (eps ~ U[0.2, 0.6] from seed 999,
     seeds 1000+i, 2 APE steps); generated on the host while the GPU runs the
@@ -328,19 +337,19 @@ def training_fields():
     return [prepare_gauge((8, 8, 8, 8), float(eps[i]), 1000 + i, ape_steps=2) for i in range(N_TRAIN + N_EVAL)]
 
 
-def learned_leg(mg, h_main, B_main, full_setup_s, full_null, fields_future, log):
+def learned_leg(mg, h_main, fields_future, c5_future, log):
     """Learned near-null proposals: train the gauge-covariant network on the
     adaptive-setup bases of 200 seeded 8^4 x 8 lattices (eps ~ U[0.2, 0.6], 2
     APE; each lattice's full setup, then 20 Adam steps on it, streaming),
-    then on the main lattice compare (a) its full setup (400 CG iterations
-    from random starts), (b) the network's proposals + a 100-iteration
-    refinement, (c) random starts + the same 100 iterations; the full setup
-    is the fallback when (b)'s null residual exceeds twice (c)'s or its solve
-    needs 25 % more outer iterations than (a)'s.  Also times the network's
-    inference on 24^3 x 48 x 16."""
+    then on the inference lattice 24^3 x 48 x 16 (eps 0.3, seed 16, 2 APE,
+    m_f = 0.001) compare (a) the full setup (400 CG iterations from random
+    starts), (b) the network's proposals + a 100-iteration refinement,
+    (c) random starts + the same 100 iterations, each followed by a
+    mixed-precision solve of one point source; the full setup is the fallback
+    when (b)'s null residual exceeds twice (c)'s or its solve needs 25 % more
+    outer iterations than (a)'s."""
     import torch
 
-    from inputs import random_su3_field
     from paper_1205_2933_amd import learned as ln
 
     t0 = time.perf_counter()
@@ -370,50 +379,67 @@ def learned_leg(mg, h_main, B_main, full_setup_s, full_null, fields_future, log)
     del fields
     log(f"trained: held-out loss {loss0:.4f} -> {loss1:.4f} in {train_s:.1f} s")
 
+    out = {"train_lattices": f"{n_train} x 8^4x8, eps ~ U[0.2, 0.6] (seed 999), 2 APE; 20 Adam steps each",
+           "train_steps": 20 * n_train, "train_s_incl_target_setups": train_s, "gauge_wait_s": gauge_wait_s,
+           "held_out_loss_before": loss0, "held_out_loss_after": loss1,
+           "inference_lattice": "24^3x48x16, eps 0.3 (seed 16), 2 APE, m_f 0.001"}
+    mg.mgdwf_trim(h_main)
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    Uc5 = c5_future.result()
+    out["c5_gauge_wait_s"] = time.perf_counter() - t0
+    h = mg.Handle(L_C5, LS, M5, MF)
+    mg.mgdwf_set_gauge(h, torch.from_numpy(Uc5).cuda())
+    del Uc5
+    # one point source (spin 0, colour 0 at the origin, on the wall s = Ls - 1)
+    b = torch.zeros(h.nfine, dtype=torch.complex128, device="cuda")
+    b[(LS - 1) * 12] = 1.0
+
     def solve_iters():
-        mg.mgdwf_set_mg_params(h_main, mg_params(mg, "f32", "f16"))
-        x = torch.zeros_like(B_main[0])
-        r = mg.mgdwf_solve(h_main, B_main[0].contiguous(), x, nrhs=1, tol=1e-10, max_outer=400, restart=8,
-                           allow_not_converged=True)[0]
-        return r["outer_iters"], r["true_relres"] < 1e-10
+        mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f16"))
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = mg.mgdwf_solve(h, b, x, nrhs=1, tol=1e-10, max_outer=400, restart=8, allow_not_converged=True)[0]
+        torch.cuda.synchronize()
+        return r["outer_iters"], r["true_relres"] < 1e-10, time.perf_counter() - t
 
     short = mg.make_mg_params(BLOCK, NVEC, sweeps=1, sweep0_iters=100, sweep_iters=4, nu_pre=12, nu_post=12,
                               coarse_tol=0.1, coarse_maxiter=400, fine_prec="f64", coarse_prec="f64")
-    out = {"train_lattices": f"{n_train} x 8^4x8, eps ~ U[0.2, 0.6] (seed 999), 2 APE; 20 Adam steps each",
-           "train_steps": 20 * n_train, "train_s_incl_target_setups": train_s, "gauge_wait_s": gauge_wait_s,
-           "held_out_loss_before": loss0, "held_out_loss_after": loss1}
-    it_full, _ = solve_iters()
-    out["full_setup"] = {"sweep0_iters": 400, "setup_s": full_setup_s, "null_residual": full_null,
-                         "mg_iters": it_full}
-    # the same short sweep from random starts: the reference of the fallback check
+    # (a) the full setup from random starts
     torch.cuda.synchronize()
     t = time.perf_counter()
-    rep = mg.mgdwf_setup(h_main, short, ln.random_starts(h_main, NVEC // 2, 21))
+    rep = ln.targets(h, mg_params(mg, "f64", "f64"), 12)
+    torch.cuda.synchronize()
+    full_s = time.perf_counter() - t
+    it_full, conv, s_full = solve_iters()
+    out["full_setup"] = {"sweep0_iters": 400, "setup_s": full_s, "null_residual": rep["null_residual"][-1],
+                         "mg_iters": it_full, "converged": conv, "solve_s": s_full}
+    # (c) the same short sweep from random starts: the reference of the fallback check
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rep = mg.mgdwf_setup(h, short, ln.random_starts(h, NVEC // 2, 21))
     torch.cuda.synchronize()
     st = time.perf_counter() - t
-    it, conv = solve_iters()
+    it, conv, s_r = solve_iters()
     ref_null = rep["null_residual"][-1]
     out["random_short_setup"] = {"sweep0_iters": 100, "setup_s": st, "null_residual": ref_null,
-                                 "mg_iters": it, "converged": conv}
-    r = ln.learned_setup(net, h_main, short, mg_params(mg, "f64", "f64"), seed=11, reference_null=ref_null)
-    it, conv = solve_iters()
+                                 "mg_iters": it, "converged": conv, "solve_s": s_r}
+    # (b) the network's proposals and the same short sweep, with the fallback
+    r = ln.learned_setup(net, h, short, mg_params(mg, "f64", "f64"), seed=11, reference_null=ref_null)
+    it, conv, s_l = solve_iters()
     fb = r["fallback"]
     if not fb and ln.needs_fallback(it, it_full):
         t = time.perf_counter()
-        ln.targets(h_main, mg_params(mg, "f64", "f64"), 12)
+        ln.targets(h, mg_params(mg, "f64", "f64"), 12)
         torch.cuda.synchronize()
         r["setup_s"] += time.perf_counter() - t
         fb = True
-        it, conv = solve_iters()
+        it, conv, s_l = solve_iters()
     out["learned_setup"] = {"sweep0_iters": 100, "setup_s": r["setup_s"], "null_residual": r["null_residual"],
-                            "fallback": fb, "mg_iters": it, "converged": conv,
-                            "setup_speedup_vs_full": full_setup_s / r["setup_s"]}
-    # inference throughput at 24^3 x 48 x 16
-    L = (24, 24, 24, 48)
-    U = random_su3_field(L, 0.3, 77)
-    h = mg.Handle(L, 16, M5, MF)
-    mg.mgdwf_set_gauge(h, torch.from_numpy(U).cuda())
-    del U
+                            "fallback": fb, "mg_iters": it, "converged": conv, "solve_s": s_l,
+                            "setup_speedup_vs_full": full_s / r["setup_s"]}
+    # inference alone: the network's 12 proposals on the 24^3 x 48 x 16 lattice
     ln.propose(net, h, 1)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -422,6 +448,7 @@ def learned_leg(mg, h_main, B_main, full_setup_s, full_null, fields_future, log)
     out["inference_24c48_s"] = time.perf_counter() - t
     del V
     h.close()
+    torch.cuda.empty_cache()
     log(f"learned {out}")
     return out
 
@@ -449,11 +476,12 @@ def main():
     from inputs import point_sources, prepare_gauge, random_starts
     log("imports done")
 
-    fields_future = None
+    fields_future = c5_future = None
     if not args.no_learned:
         from concurrent.futures import ThreadPoolExecutor
-        pool = ThreadPoolExecutor(1)
+        pool = ThreadPoolExecutor(2)
         fields_future = pool.submit(training_fields)
+        c5_future = pool.submit(c5_field)
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
@@ -658,7 +686,7 @@ def main():
             mem("ragged leg failed")
             out["ragged_batch"] = {"error": str(e)}
     if not args.no_learned:
-        out["learned_setup"] = learned_leg(mg, h, B, setup_s, srep["null_residual"][-1], fields_future, log)
+        out["learned_setup"] = learned_leg(mg, h, fields_future, c5_future, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(counts, x_check, b_check)

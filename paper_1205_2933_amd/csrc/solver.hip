@@ -733,7 +733,13 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
   const long long nf = c->fine_len();
   auto t0 = std::chrono::steady_clock::now();
   int nsw = 0;
-  cgnr_null(c, W, nh, p.sweep0_iters);
+  // The vectors are independent: their CG runs and sweeps take them in
+  // groups, so the workspaces (six fields per vector for CG, about forty for
+  // a V-cycle-preconditioned sweep) stay bounded on large lattices; every
+  // per-vector sum is the same as in one batch.
+  const double field_bytes = (double)nf * sizeof(double2);
+  const int g0 = std::max(1, std::min(nh, std::min(4, (int)(48e9 / (6.0 * field_bytes)))));
+  for (int k0 = 0; k0 < nh; k0 += g0) cgnr_null(c, W + (long long)k0 * nf, std::min(g0, nh - k0), p.sweep0_iters);
   normalise(c, W, nh);
   auto rebuild = [&]() {
     // basis fields: the nh vectors and their fifth-dimension reflections
@@ -763,21 +769,26 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
     // sweep_iters flexible-GCR steps with the current V-cycle on D x = 0 from
     // x = W, i.e. e from 0 on D e = -D W and then W <- W + e, so W keeps what
     // the current multigrid fails to remove; then normalise and rebuild
-    double2* r = c->buf<double2>("setup_r", nf * nh);
-    double2* e = c->buf<double2>("setup_e", nf * nh);
-    double2* z = c->buf<double2>("setup_zero", nf * nh);
-    zero<double2>(z, nf * nh, c->st);
-    fine_op<double2>(c, W, r, z, false, 1, nh, -1);  // r = 0 - D W
-    std::vector<double> stop2(nh, -1.0);             // never met: exactly sweep_iters steps
-    const int kmax = std::max(1, std::min(p.sweep_iters, 16));
-    if (p.squared) {
-      TwoLevelSq<double2> M(c, nh, sweep);
-      fgcr_cycle<double2>(c, M, r, e, nh, kmax, stop2, nullptr);
-    } else {
-      TwoLevel<double2> M(c, nh, sweep);
-      fgcr_cycle<double2>(c, M, r, e, nh, kmax, stop2, nullptr);
+    const int gs = std::max(1, std::min(nh, (int)(64e9 / (40.0 * field_bytes))));
+    for (int k0 = 0; k0 < nh; k0 += gs) {
+      const int ng = std::min(gs, nh - k0);
+      double2* Wg = W + (long long)k0 * nf;
+      double2* r = c->buf<double2>("setup_r", nf * ng);
+      double2* e = c->buf<double2>("setup_e", nf * ng);
+      double2* z = c->buf<double2>("setup_zero", nf * ng);
+      zero<double2>(z, nf * ng, c->st);
+      fine_op<double2>(c, Wg, r, z, false, 1, ng, -1);  // r = 0 - D W
+      std::vector<double> stop2(ng, -1.0);              // never met: exactly sweep_iters steps
+      const int kmax = std::max(1, std::min(p.sweep_iters, 16));
+      if (p.squared) {
+        TwoLevelSq<double2> M(c, ng, sweep);
+        fgcr_cycle<double2>(c, M, r, e, ng, kmax, stop2, nullptr);
+      } else {
+        TwoLevel<double2> M(c, ng, sweep);
+        fgcr_cycle<double2>(c, M, r, e, ng, kmax, stop2, nullptr);
+      }
+      add_to<double2, double2>(Wg, e, nf * ng, c->st);
     }
-    add_to<double2, double2>(W, e, nf * nh, c->st);
     normalise(c, W, nh);
     rebuild();
     if (rep && nsw < 8) rep->null_residual[nsw] = median_null_residual(c, W, nh);
