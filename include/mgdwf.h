@@ -269,6 +269,22 @@ mgdwf_status mgdwf_solve(mgdwf_handle h, const double* b, double* x, int32_t nrh
  * to FP32 and return the result as complex128).  Returns after completion. */
 mgdwf_status mgdwf_apply_vcycle(mgdwf_handle h, const double* in, double* out, int32_t nrhs);
 
+/* ---- low modes and the coarse space (Sec. 2, Fig. 1) ------------------ */
+
+/* Lowest nev eigenpairs of D^+D, by m Lanczos steps (nev <= m <= 256) on
+ * (D^+D)^-1 with full reorthogonalisation; each step is two solves of D with
+ * the installed multigrid to solve_tol (D^-1 G D^-1 G, G = gamma5 R5, since
+ * D^+ = G D G).  v0: start vector (canonical, device; the random numbers are
+ * an input).  evals: host, nev eigenvalues ascending.  evecs: device,
+ * canonical [nev][fermion], unit norm, may be NULL.  resid: host,
+ * |D^+D y - lambda y| / lambda per pair, may be NULL.  Needs a setup
+ * (or set_nullvecs + build + set_mg_params). */
+mgdwf_status mgdwf_low_modes(mgdwf_handle h, const double* v0, int32_t nev, int32_t m, double solve_tol,
+                             double* evals, double* evecs, double* resid);
+/* frac[i] = |P R e_i|^2 / |e_i|^2 (host, n entries) for n fields e (canonical,
+ * device): how much of each lies in the coarse space of the installed basis. */
+mgdwf_status mgdwf_coarse_coverage(mgdwf_handle h, const double* e, int32_t n, double* frac);
+
 /* Release every workspace the handle has grown (solver, setup and timing
  * buffers); later calls allocate what they need again.  The gauge field, the
  * basis and D_c are kept. */
@@ -347,7 +363,7 @@ typedef enum {
  * then kept, so timing noise does not flip the choice between runs.  Without
  * a call the default is used.  Results are identical up to FP32 rounding
  * order whatever the tiling. */
-#define MGDWF_MAX_TILINGS 20
+#define MGDWF_MAX_TILINGS 32
 #define MGDWF_TILE_RELOAD 1      /* kernel that reloads each slice's own spinor          */
 #define MGDWF_TILE_FOLDED 2      /* workgroups ordered t-chunk first across all RHS       */
 #define MGDWF_TILE_ONE_PER_CU 4  /* LDS reserved so one workgroup runs per CU             */
@@ -356,6 +372,8 @@ typedef enum {
 #define MGDWF_TILE_SITE_PAIR 32  /* one wavefront per two sites (x pair) x right-hand     */
                                  /* sides x Ls; links loaded once per site pair; tile =   */
                                  /* brick of (x pairs, y, z) items, 4th = t-slices/chunk  */
+#define MGDWF_TILE_LDS_NEIGHBOURS 64 /* the tile's slice, links and fifth-dimension         */
+                                     /* neighbours in LDS; only face neighbours from memory */
 typedef struct {
   int32_t ntilings;                   /* tilings timed                                  */
   int32_t chosen;                     /* index into the arrays below                     */

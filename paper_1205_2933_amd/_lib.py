@@ -72,7 +72,7 @@ class mgdwf_setup_report(ctypes.Structure):
                 "seconds": self.seconds}
 
 
-MGDWF_MAX_TILINGS = 20
+MGDWF_MAX_TILINGS = 32
 
 
 class mgdwf_tune_report(ctypes.Structure):
@@ -128,6 +128,8 @@ def _load() -> ctypes.CDLL:
         "mgdwf_solve": ([H, P, P, i32, ctypes.POINTER(mgdwf_solve_params), ctypes.POINTER(mgdwf_solve_report)],
                         ctypes.c_int),
         "mgdwf_apply_vcycle": ([H, P, P, i32], ctypes.c_int),
+        "mgdwf_low_modes": ([H, P, i32, i32, ctypes.c_double, P, P, P], ctypes.c_int),
+        "mgdwf_coarse_coverage": ([H, P, i32, P], ctypes.c_int),
         "mgdwf_trim": ([H], ctypes.c_int),
         "mgdwf_memory_bytes": ([H], ctypes.c_int64),
         "mgdwf_solve_batch": ([ctypes.POINTER(H), i32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i32),
@@ -346,6 +348,23 @@ def mgdwf_solve(h: Handle, b: torch.Tensor, x: torch.Tensor, nrhs=1, tol=1e-10, 
 def mgdwf_apply_vcycle(h: Handle, inp: torch.Tensor, out: torch.Tensor, nrhs=1):
     n = h.nfine * nrhs
     _check(h.h, _lib.mgdwf_apply_vcycle(h.h, _dev(inp, n, "in"), _dev(out, n, "out"), nrhs))
+
+
+def mgdwf_low_modes(h: Handle, v0: torch.Tensor, nev: int, m: int, solve_tol=1e-12, want_vectors=True):
+    """(eigenvalues ascending, eigenvectors [nev] device tensor or None, relative residuals)."""
+    ev = (ctypes.c_double * nev)()
+    rs = (ctypes.c_double * nev)()
+    vecs = torch.empty((nev,) + tuple(h.L[::-1]) + (h.Ls, 4, 3), dtype=torch.complex128, device="cuda") \
+        if want_vectors else None
+    _check(h.h, _lib.mgdwf_low_modes(h.h, _dev(v0, h.nfine, "v0"), nev, m, float(solve_tol), ev,
+                                     _dev(vecs, h.nfine * nev, "evecs") if want_vectors else None, rs))
+    return list(ev), vecs, list(rs)
+
+
+def mgdwf_coarse_coverage(h: Handle, e: torch.Tensor, n: int) -> list:
+    fr = (ctypes.c_double * n)()
+    _check(h.h, _lib.mgdwf_coarse_coverage(h.h, _dev(e, h.nfine * n, "e"), n, fr))
+    return list(fr)
 
 
 def mgdwf_trim(h: Handle):

@@ -1213,6 +1213,295 @@ __global__ __launch_bounds__(256, 2) void k_dslash_ws(const float2* __restrict__
   }
 }
 
+// ---------------------------------------------------------------- t-march, spatial neighbours through LDS (FP32)
+// k_dslash_tq brings every spatial neighbour, both fifth-dimension
+// neighbours and every link through the vector-memory data path: per s-pair
+// thread and t-slice about 1.9 KB returned to registers for 0.4 KB of
+// algorithmic traffic, and that path (TD ~92 % busy) set its speed while L2
+// and HBM had headroom.  Here the workgroup keeps its tile's slice t in LDS:
+// each thread writes its own spinor pair there (the forward t-hop of the
+// previous slice already loaded it), the slice's links are staged there once
+// (each multiplied by its boundary phase, which is exact and belongs to the
+// link: the forward hop of x and the backward hop of x + mu cross the same
+// face), and the x, y, z neighbours inside the tile, the s - 1 and s + 2
+// values of the fifth-dimension hop and all links are read from LDS.  Only
+// neighbours across the tile faces and slice t + 1 are loaded from memory
+// (the neighbouring tiles run on the same XCD at the same time, so the faces
+// are L2 hits); those are addressed as a scalar base per component plus a
+// 32-bit lane offset, as in k_dslash_ws.  With a 4 x 4 x 2 tile that is about 0.6 KB per thread and
+// slice.  One LDS buffer, two barriers per slice; 60 KB per workgroup at
+// 4 x 4 x 2, so two workgroups share a CU.
+// LDS pointers typed as such, so a neighbour read is a ds_read and is never
+// merged with the memory path of a face neighbour into one flat load
+typedef float xf2 __attribute__((ext_vector_type(2)));
+typedef const nf4 __attribute__((address_space(3)))* lds_f4_t;
+typedef nf4 __attribute__((address_space(3)))* lds_f4w_t;
+typedef const xf2 __attribute__((address_space(3)))* lds_f2_t;
+
+__device__ __forceinline__ void lds_pair(Spinor<float2>& p0, Spinor<float2>& p1, lds_f4_t sp, int cst) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const nf4 v = sp[k * cst];
+    p0.v[k / 3][k % 3] = make_float2(v.x, v.y);
+    p1.v[k / 3][k % 3] = make_float2(v.z, v.w);
+  }
+}
+
+template <bool DAGU>
+__device__ __forceinline__ void mul_link_1(const float2 U[3][3], const float2 h[2][3], float2 u[2][3]) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (DAGU) cfmac(s, U[b][a], h[r][b]);
+        else cfma(s, U[a][b], h[r][b]);
+      }
+      u[r][a] = s;
+    }
+}
+
+// Materialises the accumulators where it stands: the optimiser would
+// otherwise sink every hop's arithmetic below the last hop's load branches,
+// with six hops' neighbour spinors live at once (hundreds of spilled registers).
+__device__ __forceinline__ void pin_acc(Spinor<float2>& a) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    float& re = a.v[k / 3][k % 3].x;
+    float& im = a.v[k / 3][k % 3].y;
+    asm volatile("" : "+v"(re), "+v"(im));
+  }
+}
+
+// One spatial hop of an s-pair: the neighbour from LDS when it is in the
+// tile (sp), else from memory (row j5 of in); link (phase included) from LDS.
+template <int MU, int EPS, bool DAGU>
+__device__ __forceinline__ void hop_x(Spinor<float2>& a0, Spinor<float2>& a1, bool inside, lds_f4_t sp, int cst,
+                                      const char* inb, long long cs, unsigned off, lds_f2_t Ul, int ustride) {
+  Spinor<float2> q0, q1;
+  float2 U[3][3], h[2][3], u[2][3];
+  if (inside) lds_pair(q0, q1, sp, cst);
+  else load_pair_o(q0, q1, inb, cs, off);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const xf2 v = Ul[q * ustride];
+    U[q / 3][q % 3] = make_float2(v.x, v.y);
+  }
+  project<MU, EPS>(q0, h);
+  mul_link_1<DAGU>(U, h, u);
+  accumulate<MU, EPS>(a0, u);
+  project<MU, EPS>(q1, h);
+  mul_link_1<DAGU>(U, h, u);
+  accumulate<MU, EPS>(a1, u);
+  pin_acc(a0);
+  pin_acc(a1);
+}
+
+// Own terms of an s-pair (diagonal and fifth-dimension hop) with the s0 - 1
+// and s0 + 2 values read from LDS: row jm's second and row jq's first s-value.
+__device__ __forceinline__ void own_pair_x(Spinor<float2>& a0, Spinor<float2>& a1, const Spinor<float2>& p0,
+                                           const Spinor<float2>& p1, lds_f4_t row_m, lds_f4_t row_q,
+                                           int cst, int s0, int Ls, float dg, float mf, int up0, int dn0) {
+  const float cdn0 = s0 == 0 ? mf : -1.f;       // s0 - 1 across the wall
+  const float cup1 = s0 + 2 == Ls ? mf : -1.f;  // s0 + 2 across the wall
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int k = sp * 3 + c;
+      float2 r0 = cscale(p0.v[sp][c], dg), r1 = cscale(p1.v[sp][c], dg);
+      if (sp == up0 || sp == up0 + 1) {
+        const nf4 v = row_q[k * cst];
+        r0 = csub(r0, p1.v[sp][c]);                                  // s0 <- s0 + 1
+        r1 = cadd(r1, cscale(make_float2(v.x, v.y), cup1));          // s0 + 1 <- s0 + 2
+      }
+      if (sp == dn0 || sp == dn0 + 1) {
+        const nf4 v = row_m[k * cst];
+        r0 = cadd(r0, cscale(make_float2(v.z, v.w), cdn0));          // s0 <- s0 - 1
+        r1 = csub(r1, p0.v[sp][c]);                                  // s0 + 1 <- s0
+      }
+      a0.v[sp][c] = cscale(r0, -2.f);
+      a1.v[sp][c] = cscale(r1, -2.f);
+    }
+}
+
+template <bool DAG, int MODE, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX * TY * TZ * 8, TX * TY * TZ >= 64 ? 1 : 2) void k_dslash_tx(
+    const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ b,
+    const float2* __restrict__ gauge, TMArgs ta, double* __restrict__ partial) {
+  constexpr int NS = TX * TY * TZ;
+  constexpr int NF0 = TY * TZ, NF1 = TX * TZ, NF2 = TX * TY;
+  __shared__ float4 sP[12 * NS * 8];                    // slice t: [component][site][s-pair]
+  __shared__ float2 sU[36 * NS + 9 * (NF0 + NF1 + NF2)];  // as in k_dslash_tq's staged links
+  const DslashArgs& a = ta.d;
+  const int ntiles = ta.ntx * ta.nty * ta.ntz;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  int chunk, tile, rhs, pidx;
+  if (ta.fold) {
+    const int per_chunk = ta.nrhs * ntiles;
+    chunk = bid / per_chunk;
+    const int r2 = bid - chunk * per_chunk;
+    rhs = r2 / ntiles;
+    tile = r2 - rhs * ntiles;
+    pidx = rhs * (gridDim.x / ta.nrhs) + chunk * ntiles + tile;
+  } else {
+    chunk = bid / ntiles;
+    tile = bid - chunk * ntiles;
+    rhs = blockIdx.y;
+    pidx = blockIdx.y * gridDim.x + blockIdx.x;
+  }
+  const int tx = tile % ta.ntx, ty = (tile / ta.ntx) % ta.nty, tz = tile / (ta.ntx * ta.nty);
+  const int Ls = a.Ls, np = Ls >> 1;
+  const int site = threadIdx.x / np, jp = threadIdx.x - site * np;
+  const int s0 = 2 * jp;
+  const int lc[3] = {site % TX, (site / TX) % TY, site / (TX * TY)};
+  const int x = tx * TX + lc[0], y = ty * TY + lc[1], z = tz * TZ + lc[2];
+  const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2], Lt = a.L[3];
+  const long long V5 = a.V5, V4 = a.V4;
+  const int V3 = Lx * Ly * Lz;
+  const long long roff = (long long)rhs * 12 * V5;
+  const char* inb = reinterpret_cast<const char*>(in + roff);
+  const char* outb = reinterpret_cast<const char*>(out + roff);
+  const char* bb0 = MODE == 1 ? reinterpret_cast<const char*>(b + roff) : nullptr;
+  const long long cs = V5 * (long long)sizeof(float2);  // component stride in bytes
+  const int x3 = (z * Ly + y) * Lx + x;
+  constexpr int TS[3] = {1, TX, TX * TY};
+  constexpr int TE[3] = {TX, TY, TZ};
+  const int cst = NS * np;  // component stride of sP in float4
+  const int me = site * np + jp;
+  int nf3[3], nb3[3], sf[3], sb3[3], lf[3], lb[3], ub[3];
+  bool inF[3], inB[3];
+  {
+    const int co[3] = {x, y, z};
+    const int Lm[3] = {Lx, Ly, Lz};
+    const int st[3] = {1, Lx, Lx * Ly};
+    const int fo[3] = {36 * NS, 36 * NS + 9 * NF0, 36 * NS + 9 * (NF0 + NF1)};
+    const int fi[3] = {lc[1] + TY * lc[2], lc[0] + TX * lc[2], lc[0] + TX * lc[1]};
+    const int nfc[3] = {NF0, NF1, NF2};
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      const bool top = co[mu] == Lm[mu] - 1, bot = co[mu] == 0;
+      nf3[mu] = top ? x3 - (Lm[mu] - 1) * st[mu] : x3 + st[mu];
+      nb3[mu] = bot ? x3 + (Lm[mu] - 1) * st[mu] : x3 - st[mu];
+      inF[mu] = lc[mu] + 1 < TE[mu];
+      inB[mu] = lc[mu] > 0;
+      sf[mu] = inF[mu] ? me + TS[mu] * np : me;
+      sb3[mu] = inB[mu] ? me - TS[mu] * np : me;
+      lf[mu] = mu * 9 * NS + site;
+      if (inB[mu]) { lb[mu] = mu * 9 * NS + site - TS[mu]; ub[mu] = NS; }
+      else { lb[mu] = fo[mu] + fi[mu]; ub[mu] = nfc[mu]; }
+    }
+  }
+  const int jm = jp == 0 ? np - 1 : jp - 1, jq = jp + 1 == np ? 0 : jp + 1;
+  const lds_f4_t lP = (lds_f4_t)(void*)sP;
+  const lds_f2_t lU = (lds_f2_t)(void*)sU;
+  constexpr int EF = DAG ? 1 : -1;
+  constexpr int EB = DAG ? -1 : 1;
+  const int up0 = DAG ? 0 : 2;   // spins coupled to s+1
+  const int dn0 = DAG ? 2 : 0;   // spins coupled to s-1
+  const float dg = (float)a.diag, mf = (float)a.mf;
+  const int t0 = chunk * ta.tc;
+  const int t1 = min(t0 + ta.tc, Lt);
+  const int bx = tx * TX, by = ty * TY, bz = tz * TZ;
+  float2 hp0[2][3], hp1[2][3], U[3][3], h[2][3], u[2][3];
+  Spinor<float2> p0, p1, a0, a1;
+  {  // half spinor of slice t0 - 1 for the backward t-hop, its link (phase included), slice t0
+    const int tm = t0 == 0 ? Lt - 1 : t0 - 1;
+    load_pair_o(p0, p1, inb, cs, (unsigned)((tm * V3 + x3) * Ls + s0) * 8u);
+    project<3, EB>(p0, hp0);
+    project<3, EB>(p1, hp1);
+    load_link(gauge, 3, V4, tm * V3 + x3, U);
+    if (t0 == 0) {
+      const float ph = a.ph[3];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) U[q / 3][q % 3] = cscale(U[q / 3][q % 3], ph);
+    }
+    load_pair_o(p0, p1, inb, cs, (unsigned)((t0 * V3 + x3) * Ls + s0) * 8u);
+  }
+  float nrmf = 0.f;
+  for (int t = t0; t < t1; ++t) {
+    const int x4 = t * V3 + x3;
+    const int tb = t * V3;
+    __syncthreads();  // every thread is done with the previous slice's LDS
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const float2 v0 = p0.v[k / 3][k % 3], v1 = p1.v[k / 3][k % 3];
+      ((lds_f4w_t)(void*)sP)[k * cst + me] = nf4{v0.x, v0.y, v1.x, v1.y};
+    }
+    for (int i = threadIdx.x; i < 36 * NS; i += blockDim.x) {  // own sites, mu = x, y, z, t
+      const int mab = i / NS, q = i - mab * NS, mu = mab / 9;
+      const int xx = bx + q % TX, yy = by + (q / TX) % TY, zz = bz + q / (TX * TY);
+      const bool cross = mu == 0 ? xx == Lx - 1 : (mu == 1 ? yy == Ly - 1 : (mu == 2 ? zz == Lz - 1 : t == Lt - 1));
+      sU[i] = cscale(gauge[(long long)mab * V4 + tb + (zz * Ly + yy) * Lx + xx], cross ? a.ph[mu] : 1.0f);
+    }
+    for (int i = threadIdx.x; i < 9 * (NF0 + NF1 + NF2); i += blockDim.x) {  // minus faces: U_mu(x - mu)
+      int mu, r;
+      if (i < 9 * NF0) { mu = 0; r = i; }
+      else if (i < 9 * (NF0 + NF1)) { mu = 1; r = i - 9 * NF0; }
+      else { mu = 2; r = i - 9 * (NF0 + NF1); }
+      const int nf = mu == 0 ? NF0 : (mu == 1 ? NF1 : NF2);
+      const int ab = r / nf, f = r - ab * nf;
+      int xx, yy, zz;
+      bool cross;
+      if (mu == 0) { cross = bx == 0; xx = cross ? Lx - 1 : bx - 1; yy = by + f % TY; zz = bz + f / TY; }
+      else if (mu == 1) { cross = by == 0; xx = bx + f % TX; yy = cross ? Ly - 1 : by - 1; zz = bz + f / TX; }
+      else { cross = bz == 0; xx = bx + f % TX; yy = by + f / TX; zz = cross ? Lz - 1 : bz - 1; }
+      sU[36 * NS + (mu == 0 ? 0 : (mu == 1 ? 9 * NF0 : 9 * (NF0 + NF1))) + r] =
+          cscale(gauge[(long long)(mu * 9 + ab) * V4 + tb + (zz * Ly + yy) * Lx + xx], cross ? a.ph[mu] : 1.0f);
+    }
+    __syncthreads();
+    // own terms, backward t-hop (half spinor and link carried from slice t - 1)
+    own_pair_x(a0, a1, p0, p1, lP + site * np + jm, lP + site * np + jq, cst, s0, Ls, dg, mf, up0, dn0);
+    mul_link_1<true>(U, hp0, u);
+    accumulate<3, EB>(a0, u);
+    mul_link_1<true>(U, hp1, u);
+    accumulate<3, EB>(a1, u);
+    project<3, EB>(p0, hp0);
+    project<3, EB>(p1, hp1);
+    hop_x<0, EF, false>(a0, a1, inF[0], lP + sf[0], cst, inb, cs, (unsigned)((tb + nf3[0]) * Ls + s0) * 8u, lU + lf[0], NS);
+    hop_x<0, EB, true>(a0, a1, inB[0], lP + sb3[0], cst, inb, cs, (unsigned)((tb + nb3[0]) * Ls + s0) * 8u, lU + lb[0], ub[0]);
+    hop_x<1, EF, false>(a0, a1, inF[1], lP + sf[1], cst, inb, cs, (unsigned)((tb + nf3[1]) * Ls + s0) * 8u, lU + lf[1], NS);
+    hop_x<1, EB, true>(a0, a1, inB[1], lP + sb3[1], cst, inb, cs, (unsigned)((tb + nb3[1]) * Ls + s0) * 8u, lU + lb[1], ub[1]);
+    hop_x<2, EF, false>(a0, a1, inF[2], lP + sf[2], cst, inb, cs, (unsigned)((tb + nf3[2]) * Ls + s0) * 8u, lU + lf[2], NS);
+    hop_x<2, EB, true>(a0, a1, inB[2], lP + sb3[2], cst, inb, cs, (unsigned)((tb + nb3[2]) * Ls + s0) * 8u, lU + lb[2], ub[2]);
+    // forward t-hop with slice t + 1 (its own slice next); the link is the
+    // next slice's backward t-hop link
+    const bool top = t == Lt - 1;
+    load_pair_o(p0, p1, inb, cs, (unsigned)(((top ? 0 : t + 1) * V3 + x3) * Ls + s0) * 8u);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const xf2 v = lU[(27 + q) * NS + site];
+      U[q / 3][q % 3] = make_float2(v.x, v.y);
+    }
+    project<3, EF>(p0, h);
+    mul_link_1<false>(U, h, u);
+    accumulate<3, EF>(a0, u);
+    project<3, EF>(p1, h);
+    mul_link_1<false>(U, h, u);
+    accumulate<3, EF>(a1, u);
+    const unsigned o5 = (unsigned)(x4 * Ls + s0) * 8u;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float2 r0 = cscale(a0.v[sp][c], -0.5f), r1 = cscale(a1.v[sp][c], -0.5f);
+        if (MODE == 1) {
+          const nf4 bb = *(gf4_t)(sbase(bb0, cs, sp * 3 + c) + o5);
+          r0 = make_float2(bb.x - r0.x, bb.y - r0.y);
+          r1 = make_float2(bb.z - r1.x, bb.w - r1.y);
+        }
+        *(gf4w_t)(sbase(outb, cs, sp * 3 + c) + o5) = nf4{r0.x, r0.y, r1.x, r1.y};
+        if (partial) nrmf += r0.x * r0.x + r0.y * r0.y + r1.x * r1.x + r1.y * r1.y;
+      }
+  }
+  if (partial) {
+    const double sum = block_sum_dyn((double)nrmf);
+    if (threadIdx.x == 0) partial[pidx] = sum;
+  }
+}
+
 // ---------------------------------------------------------------- t-march, software-pipelined (FP32)
 // k_dslash_tq computes each hop right after loading it, so every hop waits
 // out a full memory round trip: with one wavefront per SIMD nothing else hides
@@ -1474,6 +1763,7 @@ struct FTile {
   bool lds_links = false;   // stage each slice's links in LDS
   bool pipelined = false;   // k_dslash_tw (loads one hop ahead)
   bool ws = false;          // k_dslash_ws: tx, ty, tz = brick of (x pairs, y, z), target = t-slices per chunk
+  bool xchg = false;        // k_dslash_tx: spatial neighbours inside the tile through LDS
 };
 constexpr FTile kFTiles[] = {
     {4, 4, 2, 256, false, 0, true}, {4, 4, 2, 512, false, 0, true}, {4, 4, 2, 256, false, 0},
@@ -1484,6 +1774,9 @@ constexpr FTile kFTiles[] = {
     {4, 4, 2, 512, false, 0, true, false, true},
     {2, 2, 2, 2, false, 0, false, false, false, true}, {4, 4, 4, 2, false, 0, false, false, false, true},
     {8, 16, 1, 2, false, 0, false, false, false, true},
+    {4, 4, 2, 256, false, 0, false, false, false, false, true}, {4, 4, 2, 512, false, 0, false, false, false, false, true},
+    {4, 4, 2, 1024, false, 1, false, false, false, false, true}, {8, 4, 2, 256, false, 0, false, false, false, false, true},
+    {4, 4, 4, 256, false, 0, false, false, false, false, true},
 };
 constexpr int NFTILE = sizeof(kFTiles) / sizeof(kFTiles[0]);
 
@@ -1499,6 +1792,7 @@ static bool ftile_ok(const Geometry& g, int i) {
            (g.Ls == 8 || g.Ls == 16) && (nxp * g.L[1] * g.L[2]) % 4 == 0 && group_bytes < (1LL << 32);
   }
   const int thr = f.tx * f.ty * f.tz * g.Ls / 2;
+  if (f.xchg && (long long)g.V5 * 8 >= (1LL << 32)) return false;  // 32-bit lane offsets
   return g.L[0] % f.tx == 0 && g.L[1] % f.ty == 0 && g.L[2] % f.tz == 0 && g.Ls % 2 == 0 && g.Ls >= 4 &&
          g.Ls <= 16 && thr % 64 == 0;
 }
@@ -1531,7 +1825,8 @@ bool dslash_ftile_desc(const Geometry& g, int i, int desc[4], int* flags) {
   desc[2] = kFTiles[i].tz;
   desc[3] = ftile_chunk(g, i);
   *flags = (kFTiles[i].eight_loads ? 1 : 0) | (kFTiles[i].fold ? 2 : 0) | (kFTiles[i].one_per_cu ? 4 : 0) |
-           (kFTiles[i].lds_links ? 8 : 0) | (kFTiles[i].pipelined ? 16 : 0) | (kFTiles[i].ws ? 32 : 0);
+           (kFTiles[i].lds_links ? 8 : 0) | (kFTiles[i].pipelined ? 16 : 0) | (kFTiles[i].ws ? 32 : 0) |
+           (kFTiles[i].xchg ? 64 : 0);
   return true;
 }
 
@@ -1574,6 +1869,21 @@ static void launch_tpair(const float2* in, float2* out, const float2* b, const f
     return;
   }
   constexpr int P1 = 96 * 1024;
+  if (f.xchg) {
+#define MG_TX(X, Y, Z)                                                                                       \
+  if (f.tx == X && f.ty == Y && f.tz == Z) {                                                                 \
+    if (!dagger && mode == 0) hipLaunchKernelGGL((k_dslash_tx<false, 0, X, Y, Z>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
+    else if (!dagger && mode == 1) hipLaunchKernelGGL((k_dslash_tx<false, 1, X, Y, Z>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
+    else if (dagger && mode == 0) hipLaunchKernelGGL((k_dslash_tx<true, 0, X, Y, Z>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
+    else hipLaunchKernelGGL((k_dslash_tx<true, 1, X, Y, Z>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
+    return;                                                                                                  \
+  }
+    MG_TX(4, 4, 2)
+    MG_TX(8, 4, 2)
+    MG_TX(4, 4, 4)
+#undef MG_TX
+    fail(MGDWF_ERR_INVALID_ARG, "no LDS-exchange kernel for this Dslash tiling");
+  }
   if (f.pipelined && f.tx == 4 && f.ty == 4 && f.tz == 2) {
 #define MG_TW(DAG, MODE, PAD) \
   hipLaunchKernelGGL((k_dslash_tw<DAG, MODE, 4, 4, 2, PAD>), grid, blk, 0, st, in, out, b, gauge, ta, partial)

@@ -252,3 +252,100 @@ def test_dslash_f32_site_pair_in_the_solver(cuda):
     for r in range(3):
         assert np.linalg.norm(bs[r] - dwf.apply_dwf(xs[r], U, 1.8, mf)) / np.linalg.norm(bs[r]) < 1e-10
     h.close()
+
+
+@pytest.mark.parametrize("case", [((8, 8, 4, 6), 16, 3, (1, -1, 1, -1)), ((8, 4, 4, 5), 8, 2, (1, 1, -1, 1)),
+                                  ((4, 4, 2, 3), 16, 2, (-1, 1, 1, -1)), ((16, 16, 16, 8), 16, 12, (1, 1, 1, -1))],
+                         ids=lambda c: f"L{'x'.join(map(str, c[0]))}_Ls{c[1]}_n{c[2]}")
+def test_dslash_f32_lds_exchange_tilings(cuda, case):
+    """The FP32 t-march that keeps its tile's slice, links (phases folded in)
+    and fifth-dimension neighbours in LDS and loads only face neighbours from
+    memory, on every tile / t-chunk it admits, D and D^+, against the oracle:
+    odd t extents (short last chunk), antiperiodic directions, a tile as wide
+    as the lattice (4 x 4 x 2 on 4 x 4 x 2 x 3: every face neighbour wraps),
+    and the production 12 right-hand sides at Ls = 16."""
+    import paper_1205_2933_amd as mg
+    L, Ls, nrhs, bc = case
+    U = prepare_gauge(L, 0.4, 43)
+    psi = gaussian_fermion(L, Ls, 44, n=nrhs)
+    h = mg.Handle(L, Ls, 1.8, 0.01, bc)
+    mg.mgdwf_set_gauge(h, dev(U))
+    rep = mg.mgdwf_tune(h, nrhs=nrhs, iters=1)
+    tx = [(tid, tile) for tid, tile, fl in zip(rep["id"], rep["tile"], rep["flags"]) if fl & 64]
+    assert tx, rep
+    refs = {dg: [dwf.apply_dwf(psi[r], U, 1.8, 0.01, bc, dagger=dg) for r in range(nrhs)] for dg in (False, True)}
+    for tid, tile in tx:
+        print(f"LDS-exchange tiling {tid} {tile}", flush=True)
+        mg.mgdwf_set_tiling(h, tid)
+        for dg in (False, True):
+            out = torch.empty_like(dev(psi))
+            mg.mgdwf_apply_dwf(h, dev(psi), out, dagger=dg, prec="f32", nrhs=nrhs)
+            torch.cuda.synchronize()
+            o = out.cpu().numpy()
+            for r in range(nrhs):
+                assert rel(o[r], refs[dg][r]) < 2e-6, (tid, tile, dg, r)
+    mg.mgdwf_set_tiling(h, -1)
+    h.close()
+
+
+def test_dslash_lds_exchange_integer_inputs_are_bit_exact(cuda):
+    """Indexing of the LDS-exchange kernel bit for bit (Gaussian-integer links
+    and fields, M5 = 1, m_f = 1/2, antiperiodic t and z): every tile it admits
+    on 8 x 8 x 4 x 4 x 16 gives exactly the oracle's D and D^+."""
+    import paper_1205_2933_amd as mg
+    L, Ls, bc = (8, 8, 4, 4), 16, (1, 1, -1, -1)
+    U, psi = _integer_inputs(L, Ls, 6, n=2)
+    h = mg.Handle(L, Ls, 1.0, 0.5, bc)
+    mg.mgdwf_set_gauge(h, dev(U))
+    rep = mg.mgdwf_tune(h, nrhs=2, iters=1)
+    tx = [tid for tid, fl in zip(rep["id"], rep["flags"]) if fl & 64]
+    assert len(tx) >= 3
+    refs = {dg: [dwf.apply_dwf(psi[r], U, 1.0, 0.5, bc, dagger=dg) for r in range(2)] for dg in (False, True)}
+    for tid in tx:
+        mg.mgdwf_set_tiling(h, tid)
+        for dg in (False, True):
+            out = torch.empty_like(dev(psi))
+            mg.mgdwf_apply_dwf(h, dev(psi), out, dagger=dg, prec="f32", nrhs=2)
+            torch.cuda.synchronize()
+            o = out.cpu().numpy()
+            for r in range(2):
+                assert np.array_equal(o[r], refs[dg][r]), (tid, dg, r)
+    h.close()
+
+
+def test_dslash_lds_exchange_in_the_solver(cuda):
+    """The LDS-exchange kernel's residual mode (b - D x) and per-RHS norms as
+    the V-cycle uses them: one mixed-precision V-cycle application with it
+    equals the default tiling's up to FP32 rounding, and a solve with it
+    reaches 1e-10 against the oracle's D."""
+    import paper_1205_2933_amd as mg
+    from inputs import random_starts
+    L, Ls, mf, block = (4, 4, 4, 4), 8, 0.01, (2, 2, 2, 2)
+    U = prepare_gauge(L, 0.3, 11)
+    h = mg.Handle(L, Ls, 1.8, mf)
+    mg.mgdwf_set_gauge(h, dev(U))
+    p = mg.make_mg_params(block, 16, sweeps=1, sweep0_iters=100, coarse_tol=1e-30, coarse_maxiter=16,
+                          fine_prec="f32", coarse_prec="f32")
+    mg.mgdwf_setup(h, p, dev(random_starts(L, Ls, 8, 21)))
+    b = dev(gaussian_fermion(L, Ls, 31, n=3))
+    z0 = torch.empty_like(b)
+    mg.mgdwf_set_tiling(h, -1)
+    mg.mgdwf_apply_vcycle(h, b, z0, nrhs=3)
+    rep = mg.mgdwf_tune(h, nrhs=3, iters=1)
+    tx = [tid for tid, fl in zip(rep["id"], rep["flags"]) if fl & 64]
+    assert tx
+    mg.mgdwf_set_tiling(h, tx[0])
+    z1 = torch.empty_like(b)
+    mg.mgdwf_apply_vcycle(h, b, z1, nrhs=3)
+    e = float(torch.linalg.norm(z1 - z0) / torch.linalg.norm(z0))
+    print("V-cycle LDS-exchange vs default tiling", e, flush=True)
+    assert e < 1e-5
+    mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, coarse_tol=0.1, coarse_maxiter=200, fine_prec="f32",
+                                                coarse_prec="f16"))
+    x = torch.zeros_like(b)
+    reps = mg.mgdwf_solve(h, b, x, nrhs=3, tol=1e-10, max_outer=400, restart=8)
+    xs, bs = x.cpu().numpy(), b.cpu().numpy()
+    for r in range(3):
+        assert reps[r]["true_relres"] < 1e-10
+        assert np.linalg.norm(bs[r] - dwf.apply_dwf(xs[r], U, 1.8, mf)) / np.linalg.norm(bs[r]) < 1e-10
+    h.close()
