@@ -253,6 +253,51 @@ def squared_leg(mg, U_dev, B_main, log):
     return out
 
 
+def low_modes_leg(mg, log):
+    """Low modes and the coarse space (paper Sec. 2, Fig. 1 right) on the
+    small shape: 4^4 x Ls=8, m_f = 0.01, eps = 0.3 links, 2^4 blocks.  The
+    lowest 40 eigenpairs of D^+D by 120 Lanczos steps on (D^+D)^-1 (each two
+    FP64 squared-operator multigrid solves to 1e-12), and the fraction |P R e|^2 / |e|^2 of
+    each inside three coarse spaces of 32 dof per block: the 9-point setup's
+    (8 adaptive vectors and their reflections), the squared setup's (16
+    adaptive vectors) and the one cut from the lowest 16 modes."""
+    import numpy as np
+    import torch
+
+    from inputs import gaussian_fermion, prepare_gauge, random_starts
+
+    Lq, Lsq, mfq, blk = (4, 4, 4, 4), 8, 0.01, (2, 2, 2, 2)
+    t0 = time.perf_counter()
+    U = torch.from_numpy(prepare_gauge(Lq, 0.3, 11)).cuda()
+    kw = dict(sweeps=1, sweep0_iters=100, nu_pre=4, nu_post=4, coarse_tol=0.1, coarse_maxiter=200,
+              fine_prec="f64", coarse_prec="f64")
+    h9 = mg.Handle(Lq, Lsq, M5, mfq)
+    mg.mgdwf_set_gauge(h9, U)
+    mg.mgdwf_setup(h9, mg.make_mg_params(blk, 16, **kw), torch.from_numpy(random_starts(Lq, Lsq, 8, 21)).cuda())
+    hs = mg.Handle(Lq, Lsq, M5, mfq)
+    mg.mgdwf_set_gauge(hs, U)
+    mg.mgdwf_setup(hs, mg.make_mg_params(blk, 16, squared=True, **kw),
+                   torch.from_numpy(random_starts(Lq, Lsq, 16, 21)).cuda())
+    t = time.perf_counter()
+    ev, E, res = mg.mgdwf_low_modes(hs, torch.from_numpy(gaussian_fermion(Lq, Lsq, 31)).cuda(), 40, 120,
+                                    solve_tol=1e-12)
+    lanczos_s = time.perf_counter() - t
+    cov = {"nine_point_setup": mg.mgdwf_coarse_coverage(h9, E, 40),
+           "squared_setup": mg.mgdwf_coarse_coverage(hs, E, 40)}
+    mg.mgdwf_set_nullvecs(hs, blk, E[:16].contiguous(), 16)
+    cov["lowest_16_modes"] = mg.mgdwf_coarse_coverage(hs, E, 40)
+    h9.close()
+    hs.close()
+    out = {"lattice": "4^4 x Ls=8, m_f=0.01, eps=0.3, 2^4 blocks", "lanczos_steps": 120, "lanczos_s": lanczos_s,
+           "eigenvalues": ev, "max_eig_residual": max(res),
+           "coverage": {k: [round(x, 6) for x in v] for k, v in cov.items()},
+           "summary": {k: {"modes_0_15_min": float(np.min(v[:16])), "modes_16_39_mean": float(np.mean(v[16:])),
+                           "modes_16_39_min": float(np.min(v[16:]))} for k, v in cov.items()},
+           "seconds": time.perf_counter() - t0}
+    log(f"low modes: lambda {ev[0]:.3e} .. {ev[-1]:.3e}, residual {max(res):.1e}, summary {out['summary']}")
+    return out
+
+
 def mass_leg(mg, U_dev, B_main, log):
     """Iteration count versus quark mass (m_f = 0.01, 0.003, 0.001) on the main
     gauge field (eps = 0.3) and on a rougher one (eps = 0.6, seed 13), both with
@@ -396,13 +441,20 @@ def learned_leg(mg, h_main, fields_future, c5_future, log):
     b[(LS - 1) * 12] = 1.0
 
     def solve_iters():
+        mg.mgdwf_trim(h)  # the setup's workspaces go first
+        mem("learned leg, before a 24^3x48 solve")
         mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f16"))
         x = torch.zeros_like(b)
         torch.cuda.synchronize()
         t = time.perf_counter()
         r = mg.mgdwf_solve(h, b, x, nrhs=1, tol=1e-10, max_outer=400, restart=8, allow_not_converged=True)[0]
         torch.cuda.synchronize()
-        return r["outer_iters"], r["true_relres"] < 1e-10, time.perf_counter() - t
+        el = time.perf_counter() - t
+        del x
+        mg.mgdwf_trim(h)  # the solve's workspaces (about 60 GB here) go before the next setup
+        torch.cuda.empty_cache()
+        mem("learned leg, after a 24^3x48 solve")
+        return r["outer_iters"], r["true_relres"] < 1e-10, el
 
     short = mg.make_mg_params(BLOCK, NVEC, sweeps=1, sweep0_iters=100, sweep_iters=4, nu_pre=12, nu_post=12,
                               coarse_tol=0.1, coarse_maxiter=400, fine_prec="f64", coarse_prec="f64")
@@ -464,6 +516,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-setup comparison")
     ap.add_argument("--no-mass-scan", action="store_true", help="skip the iteration count versus m_f")
     ap.add_argument("--no-squared", action="store_true", help="skip the squared-operator multigrid step")
+    ap.add_argument("--no-low-modes", action="store_true", help="skip the low-mode coverage on the 4^4 lattice")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -675,6 +728,8 @@ def main():
         mg.mgdwf_trim(h)
         torch.cuda.empty_cache()
         out["squared_operator_mg"] = squared_leg(mg, U_dev, B, log)
+    if not args.no_low_modes:
+        out["low_mode_coverage"] = low_modes_leg(mg, log)
     if not args.no_mass_scan:
         mg.mgdwf_trim(h)
         torch.cuda.empty_cache()
@@ -686,7 +741,11 @@ def main():
             mem("ragged leg failed")
             out["ragged_batch"] = {"error": str(e)}
     if not args.no_learned:
-        out["learned_setup"] = learned_leg(mg, h, fields_future, c5_future, log)
+        try:
+            out["learned_setup"] = learned_leg(mg, h, fields_future, c5_future, log)
+        except (mg.MgdwfError, AssertionError) as e:
+            mem("learned leg failed")
+            out["learned_setup"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(counts, x_check, b_check)

@@ -274,7 +274,8 @@ mgdwf_status mgdwf_apply_vcycle(mgdwf_handle h, const double* in, double* out, i
 /* Lowest nev eigenpairs of D^+D, by m Lanczos steps (nev <= m <= 256) on
  * (D^+D)^-1 with full reorthogonalisation; each step is two solves of D with
  * the installed multigrid to solve_tol (D^-1 G D^-1 G, G = gamma5 R5, since
- * D^+ = G D G).  v0: start vector (canonical, device; the random numbers are
+ * D^+ = G D G; flexible GCR restarted every 16, at most 2000 iterations;
+ * MGDWF_ERR_NOT_CONVERGED if a solve misses solve_tol).  v0: start vector (canonical, device; the random numbers are
  * an input).  evals: host, nev eigenvalues ascending.  evecs: device,
  * canonical [nev][fermion], unit norm, may be NULL.  resid: host,
  * |D^+D y - lambda y| / lambda per pair, may be NULL.  Needs a setup
@@ -355,7 +356,7 @@ typedef enum {
   MGDWF_K_COARSE = 3     /* D_c apply                               */
 } mgdwf_kernel;
 
-/* Autotuning of the FP32 Dslash: every tiling of the t-march kernel that
+/* Autotuning of the FP32 Dslash: every tiling of the t-march kernels that
  * the lattice admits is timed (mgdwf_time_kernel's method, `iters` launches at
  * nrhs right-hand sides, D and D^+ alternating) and the fastest is kept on the
  * handle for every later FP32 fine-operator application, unless it is less
@@ -374,6 +375,9 @@ typedef enum {
                                  /* brick of (x pairs, y, z) items, 4th = t-slices/chunk  */
 #define MGDWF_TILE_LDS_NEIGHBOURS 64 /* the tile's slice, links and fifth-dimension         */
                                      /* neighbours in LDS; only face neighbours from memory */
+#define MGDWF_TILE_ASYNC_LINKS 256   /* with 64: the next slice's links copied to LDS      */
+                                     /* (global_load_lds) during this slice; results      */
+                                     /* stream past L2; 4th = t-slices at the tune's nrhs   */
 typedef struct {
   int32_t ntilings;                   /* tilings timed                                  */
   int32_t chosen;                     /* index into the arrays below                     */

@@ -230,7 +230,7 @@ mgdwf_status mgdwf_set_gauge(mgdwf_handle h, const double* U) {
     need(U != nullptr, MGDWF_ERR_INVALID_ARG, "null gauge field");
     const long long n = 36LL * h->g.V4;
     h->U64.alloc(n * sizeof(double2));
-    h->U32.alloc(2 * n * sizeof(float2));  // component-major links, then a site-major copy
+    h->U32.alloc(3 * n * sizeof(float2));  // component-major links, a site-major copy, a phase-folded copy
     pack_gauge(reinterpret_cast<const double2*>(U), h->U64.as<double2>(), h->U32.as<float2>(), h->g, h->st);
     MG_HIP(hipStreamSynchronize(h->st));
     h->have_gauge = true;
@@ -530,6 +530,38 @@ mgdwf_status mgdwf_apply_vcycle(mgdwf_handle h, const double* in, double* out, i
   });
 }
 
+mgdwf_status mgdwf_low_modes(mgdwf_handle h, const double* v0, int32_t nev, int32_t m, double solve_tol,
+                             double* evals, double* evecs, double* resid) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(v0 && evals, MGDWF_ERR_INVALID_ARG, "null argument");
+    need(nev >= 1 && m >= nev && m <= 256, MGDWF_ERR_INVALID_ARG, "need 1 <= nev <= m <= 256");
+    need(solve_tol > 0.0 && solve_tol <= 1e-3, MGDWF_ERR_INVALID_ARG, "solve_tol must be in (0, 1e-3]");
+    need(h->have_coarse && h->have_params, MGDWF_ERR_STATE, "the Lanczos steps solve with the multigrid: set it up first");
+    const long long nf = h->fine_len();
+    double2* a = h->buf<double2>("io_a", nf);
+    pack_fermion_f64(reinterpret_cast<const double2*>(v0), a, h->g, 1, h->st);
+    double2* ev = evecs ? h->buf<double2>("lm_evecs", (size_t)nev * nf) : nullptr;
+    low_modes(h, a, nev, m, solve_tol, evals, ev, resid);
+    if (evecs) unpack_fermion_f64(ev, reinterpret_cast<double2*>(evecs), h->g, nev, h->st);
+    MG_HIP(hipStreamSynchronize(h->st));
+    for (auto it = h->ws.begin(); it != h->ws.end();)  // the Krylov basis is large: give it back
+      it = it->first.rfind("lm_", 0) == 0 ? h->ws.erase(it) : std::next(it);
+    ++h->ws_gen;  // captured graphs keyed on the old workspaces are not replayed
+  });
+}
+
+mgdwf_status mgdwf_coarse_coverage(mgdwf_handle h, const double* e, int32_t n, double* frac) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(e && frac && n >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
+    need(h->have_basis, MGDWF_ERR_STATE, "no basis installed");
+    double2* a = h->buf<double2>("io_a", h->fine_len() * n);
+    pack_fermion_f64(reinterpret_cast<const double2*>(e), a, h->g, n, h->st);
+    coarse_coverage(h, a, n, frac);
+  });
+}
+
 mgdwf_status mgdwf_trim(mgdwf_handle h) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
@@ -715,7 +747,7 @@ mgdwf_status mgdwf_tune(mgdwf_handle h, int32_t nrhs, int32_t iters, mgdwf_tune_
       Geometry g = h->g;
       g.ftile = i;
       int desc[4], flags = 0;
-      if (!dslash_ftile_desc(g, i, desc, &flags)) continue;
+      if (!dslash_ftile_desc(g, i, nrhs, desc, &flags)) continue;
       auto run = [&](int n) {
         for (int k = 0; k < n; ++k)
           dslash_ex<float2>(a, b, nullptr, h->U32.as<float2>(), g, h->M5, h->mf, (k & 1) != 0, 0, nrhs, nullptr,
@@ -801,7 +833,7 @@ mgdwf_status mgdwf_set_tiling(mgdwf_handle h, int32_t id) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     int desc[4], flags = 0;
-    need(id == -1 || dslash_ftile_desc(h->g, id, desc, &flags), MGDWF_ERR_INVALID_ARG,
+    need(id == -1 || dslash_ftile_desc(h->g, id, 1, desc, &flags), MGDWF_ERR_INVALID_ARG,
          "tiling does not apply to this lattice");
     h->g.ftile = id;
     h->clear_graphs();

@@ -67,9 +67,12 @@ void unpack_fermion_f64(const double2* field, double2* canon, const Geometry& g,
 
 // canonical gauge ((x4*4 + mu)*9 + ab) -> internal ((mu*9 + ab)*V4 + x4), FP64 and FP32
 __global__ void k_pack_gauge(const double2* __restrict__ canon, double2* __restrict__ g64,
-                             float2* __restrict__ g32, int V4) {
+                             float2* __restrict__ g32, Geometry g) {
+  const int V4 = g.V4;
   int x4 = blockIdx.x * blockDim.x + threadIdx.x;
   if (x4 >= V4) return;
+  const int co[4] = {x4 % g.L[0], (x4 / g.L[0]) % g.L[1], (x4 / (g.L[0] * g.L[1])) % g.L[2],
+                     x4 / (g.L[0] * g.L[1] * g.L[2])};
   for (int j = 0; j < 36; ++j) {
     double2 v = canon[(long long)x4 * 36 + j];
     long long o = (long long)j * V4 + x4;
@@ -78,11 +81,16 @@ __global__ void k_pack_gauge(const double2* __restrict__ canon, double2* __restr
     // second FP32 copy, site major ([x4][mu][a][b], the canonical order): the
     // 36 entries of a site are contiguous for the wavefront-per-site kernel
     g32[36LL * V4 + (long long)x4 * 36 + j] = make_float2((float)v.x, (float)v.y);
+    // third, component major with the boundary phase folded into the links
+    // of each direction's last slice (every hop across that face uses them)
+    const int mu = j / 9;
+    const float ph = co[mu] == g.L[mu] - 1 ? (float)g.bc[mu] : 1.0f;
+    g32[72LL * V4 + o] = make_float2(ph * (float)v.x, ph * (float)v.y);
   }
 }
 
 void pack_gauge(const double2* canon, double2* g64, float2* g32, const Geometry& g, hipStream_t st) {
-  hipLaunchKernelGGL(k_pack_gauge, dim3(ceil_div(g.V4, 256)), dim3(256), 0, st, canon, g64, g32, g.V4);
+  hipLaunchKernelGGL(k_pack_gauge, dim3(ceil_div(g.V4, 256)), dim3(256), 0, st, canon, g64, g32, g);
   MG_LAUNCH_CHECK();
 }
 

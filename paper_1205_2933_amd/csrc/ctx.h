@@ -15,7 +15,7 @@ struct mgdwf_ctx {
   int device = 0;
   void* scratch = nullptr;  // device address of this GPU's static scratch array (no-allocation entry point)
 
-  mgdwf::DevBuf U64, U32;  // links, FP64 and FP32 (the FP32 buffer holds a site-major copy after the first)
+  mgdwf::DevBuf U64, U32;  // links, FP64 and FP32 (the FP32 buffer: component major, site major, phase folded)
   bool have_gauge = false;
 
   mgdwf::CoarseGeometry cg{};

@@ -1275,6 +1275,140 @@ __device__ __forceinline__ void pin_acc(Spinor<float2>& a) {
   }
 }
 
+// The links a tile's slice t needs, into LDS: U_mu(x) of its sites for mu =
+// x, y, z, t ([mu * 9 + ab][site]) and U_mu(x - mu) on the three minus faces,
+// each multiplied by the boundary phase of the face it crosses.  Entries go in
+// pairs of x-neighbours (one 16-byte load; on the x face, whose pairs are
+// y-neighbours, two 8-byte loads), and every thread issues its loads before
+// writing any (batches of four pairs), so a slice costs one memory round trip
+// rather than one per loop pass.  Needs even TX and TY (x extent even too).
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void stage_links(float2* sU, const float2* __restrict__ gauge, const DslashArgs& a,
+                                            long long V4, int tb, int t, int bx, int by, int bz) {
+  constexpr int NS = TX * TY * TZ;
+  constexpr int NF0 = TY * TZ, NF1 = TX * TZ, NF2 = TX * TY;
+  static_assert(TX % 2 == 0 && TY % 2 == 0, "link pairs need even TX and TY");
+  constexpr int NU = (36 * NS + 9 * (NF0 + NF1 + NF2)) / 2;
+  constexpr int B = 4;
+  const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2], Lt = a.L[3];
+  for (int base = 0; base < NU; base += B * (int)blockDim.x) {
+    float2 v0[B], v1[B];
+    float f0[B], f1[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int u = base + j * (int)blockDim.x + (int)threadIdx.x;
+      v0[j] = v1[j] = make_float2(0.f, 0.f);
+      f0[j] = f1[j] = 1.f;
+      if (u < 18 * NS) {
+        const int i = 2 * u, mab = i / NS, q = i - mab * NS, mu = mab / 9;
+        const int xx = bx + q % TX, yy = by + (q / TX) % TY, zz = bz + q / (TX * TY);
+        const float4 w = *reinterpret_cast<const float4*>(gauge + (long long)mab * V4 + tb + (zz * Ly + yy) * Lx + xx);
+        v0[j] = make_float2(w.x, w.y);
+        v1[j] = make_float2(w.z, w.w);
+        if (mu == 0) f1[j] = xx + 1 == Lx - 1 ? a.ph[0] : 1.f;  // xx is even: only the second can be on the face
+        else {
+          const bool cross = mu == 1 ? yy == Ly - 1 : (mu == 2 ? zz == Lz - 1 : t == Lt - 1);
+          f0[j] = f1[j] = cross ? a.ph[mu] : 1.f;
+        }
+      } else if (u < NU) {
+        const int r0 = 2 * (u - 18 * NS);
+        int mu, r;
+        if (r0 < 9 * NF0) { mu = 0; r = r0; }
+        else if (r0 < 9 * (NF0 + NF1)) { mu = 1; r = r0 - 9 * NF0; }
+        else { mu = 2; r = r0 - 9 * (NF0 + NF1); }
+        const int nf = mu == 0 ? NF0 : (mu == 1 ? NF1 : NF2);
+        const int ab = r / nf, f = r - ab * nf;
+        const long long cb = (long long)(mu * 9 + ab) * V4 + tb;
+        bool cross;
+        if (mu == 0) {
+          cross = bx == 0;
+          const int xx = cross ? Lx - 1 : bx - 1;
+          v0[j] = gauge[cb + ((bz + f / TY) * Ly + by + f % TY) * Lx + xx];
+          v1[j] = gauge[cb + ((bz + (f + 1) / TY) * Ly + by + (f + 1) % TY) * Lx + xx];
+        } else {
+          int xx = bx + f % TX, yy, zz;
+          if (mu == 1) { cross = by == 0; yy = cross ? Ly - 1 : by - 1; zz = bz + f / TX; }
+          else { cross = bz == 0; yy = by + f / TX; zz = cross ? Lz - 1 : bz - 1; }
+          const float4 w = *reinterpret_cast<const float4*>(gauge + cb + (zz * Ly + yy) * Lx + xx);
+          v0[j] = make_float2(w.x, w.y);
+          v1[j] = make_float2(w.z, w.w);
+        }
+        f0[j] = f1[j] = cross ? a.ph[mu] : 1.f;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int u = base + j * (int)blockDim.x + (int)threadIdx.x;
+      if (u < NU) {
+        sU[2 * u] = cscale(v0[j], f0[j]);
+        sU[2 * u + 1] = cscale(v1[j], f1[j]);
+      }
+    }
+  }
+}
+
+// As stage_links, from the phase-folded link copy (gauge + 72 V4: links on
+// the last slice of a direction already multiplied by its boundary phase)
+// and with direct global-to-LDS copies (global_load_lds): each lane's 16 or 4
+// bytes land at a wavefront-uniform LDS base + lane x size without passing
+// through registers, so the copies for slice t + 1 are in flight during slice
+// t's arithmetic.  The caller waits (vmcnt) before the barrier that precedes
+// their use.  Own links and the y and z faces go in 16-byte x-pairs, the x
+// face (pairs are y-neighbours there) in 4-byte words.
+typedef __attribute__((address_space(3))) void* lds_void_t;
+
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void stage_links_async(float2* sU, const float2* __restrict__ gp, const DslashArgs& a,
+                                                  long long V4, int tb, int bx, int by, int bz) {
+  constexpr int NS = TX * TY * TZ;
+  constexpr int NF0 = TY * TZ, NF1 = TX * TZ, NF2 = TX * TY;
+  static_assert(TX % 2 == 0, "link pairs need even TX");
+  constexpr int NOWN = 18 * NS;              // 16-byte units of own links
+  constexpr int NYZ = 9 * (NF1 + NF2) / 2;   // 16-byte units of the y and z faces
+  constexpr int NXW = 2 * 9 * NF0;           // 4-byte words of the x face
+  const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
+  const int lane = (int)threadIdx.x & 63;
+  const int w0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), nw = (int)blockDim.x >> 6;
+  for (int g0 = w0 * 64; g0 < NOWN; g0 += nw * 64) {
+    const int u = g0 + lane;
+    if (u < NOWN) {
+      const int i = 2 * u, mab = i / NS, q = i - mab * NS;
+      const int xx = bx + q % TX, yy = by + (q / TX) % TY, zz = bz + q / (TX * TY);
+      __builtin_amdgcn_global_load_lds((const void*)(gp + (long long)mab * V4 + tb + (zz * Ly + yy) * Lx + xx),
+                                       (lds_void_t)(void*)(sU + 2 * g0), 16, 0, 0);
+    }
+  }
+  float2* sYZ = sU + 36 * NS + 9 * NF0;
+  for (int g0 = w0 * 64; g0 < NYZ; g0 += nw * 64) {
+    const int u = g0 + lane;
+    if (u < NYZ) {
+      const int r0 = 2 * u;
+      const int mu = r0 < 9 * NF1 ? 1 : 2;
+      const int r = mu == 1 ? r0 : r0 - 9 * NF1;
+      const int nf = mu == 1 ? NF1 : NF2;
+      const int ab = r / nf, f = r - ab * nf;
+      const int xx = bx + f % TX;
+      int yy, zz;
+      if (mu == 1) { yy = by == 0 ? Ly - 1 : by - 1; zz = bz + f / TX; }
+      else { yy = by + f / TX; zz = bz == 0 ? Lz - 1 : bz - 1; }
+      __builtin_amdgcn_global_load_lds((const void*)(gp + (long long)(mu * 9 + ab) * V4 + tb + (zz * Ly + yy) * Lx + xx),
+                                       (lds_void_t)(void*)(sYZ + 2 * g0), 16, 0, 0);
+    }
+  }
+  float2* sX = sU + 36 * NS;
+  const int xx = bx == 0 ? Lx - 1 : bx - 1;
+  for (int g0 = w0 * 64; g0 < NXW; g0 += nw * 64) {
+    const int d = g0 + lane;
+    if (d < NXW) {
+      const int e = d >> 1, ab = e / NF0, f = e - ab * NF0;
+      const char* src = reinterpret_cast<const char*>(gp + (long long)ab * V4 + tb +
+                                                      ((bz + f / TY) * Ly + by + f % TY) * Lx + xx) + 4 * (d & 1);
+      __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t)(void*)(reinterpret_cast<char*>(sX) + 4 * g0),
+                                       4, 0, 0);
+    }
+  }
+}
+
 // One spatial hop of an s-pair: the neighbour from LDS when it is in the
 // tile (sp), else from memory (row j5 of in); link (phase included) from LDS.
 template <int MU, int EPS, bool DAGU>
@@ -1327,14 +1461,16 @@ __device__ __forceinline__ void own_pair_x(Spinor<float2>& a0, Spinor<float2>& a
     }
 }
 
-template <bool DAG, int MODE, int TX, int TY, int TZ>
+template <bool DAG, int MODE, int TX, int TY, int TZ, bool AL>
 __global__ __launch_bounds__(TX * TY * TZ * 8, TX * TY * TZ >= 64 ? 1 : 2) void k_dslash_tx(
     const float2* __restrict__ in, float2* __restrict__ out, const float2* __restrict__ b,
     const float2* __restrict__ gauge, TMArgs ta, double* __restrict__ partial) {
   constexpr int NS = TX * TY * TZ;
   constexpr int NF0 = TY * TZ, NF1 = TX * TZ, NF2 = TX * TY;
   __shared__ float4 sP[12 * NS * 8];                    // slice t: [component][site][s-pair]
-  __shared__ float2 sU[36 * NS + 9 * (NF0 + NF1 + NF2)];  // as in k_dslash_tq's staged links
+  constexpr int NL = 36 * NS + 9 * (NF0 + NF1 + NF2);
+  __shared__ __align__(16) float2 sU[AL ? 2 : 1][NL];     // as in k_dslash_tq's staged links (AL: two slices)
+  const float2* gp = gauge + 72LL * ta.d.V4;             // phase-folded copy
   const DslashArgs& a = ta.d;
   const int ntiles = ta.ntx * ta.nty * ta.ntz;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -1396,7 +1532,6 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, TX * TY * TZ >= 64 ? 1 : 2) void 
   }
   const int jm = jp == 0 ? np - 1 : jp - 1, jq = jp + 1 == np ? 0 : jp + 1;
   const lds_f4_t lP = (lds_f4_t)(void*)sP;
-  const lds_f2_t lU = (lds_f2_t)(void*)sU;
   constexpr int EF = DAG ? 1 : -1;
   constexpr int EB = DAG ? -1 : 1;
   const int up0 = DAG ? 0 : 2;   // spins coupled to s+1
@@ -1412,8 +1547,13 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, TX * TY * TZ >= 64 ? 1 : 2) void 
     load_pair_o(p0, p1, inb, cs, (unsigned)((tm * V3 + x3) * Ls + s0) * 8u);
     project<3, EB>(p0, hp0);
     project<3, EB>(p1, hp1);
-    load_link(gauge, 3, V4, tm * V3 + x3, U);
-    if (t0 == 0) {
+    if (AL) {
+      load_link(gp, 3, V4, tm * V3 + x3, U);
+      stage_links_async<TX, TY, TZ>(sU[t0 & 1], gp, a, V4, t0 * V3, bx, by, bz);
+    } else {
+      load_link(gauge, 3, V4, tm * V3 + x3, U);
+    }
+    if (!AL && t0 == 0) {
       const float ph = a.ph[3];
 #pragma unroll
       for (int q = 0; q < 9; ++q) U[q / 3][q % 3] = cscale(U[q / 3][q % 3], ph);
@@ -1424,34 +1564,23 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, TX * TY * TZ >= 64 ? 1 : 2) void 
   for (int t = t0; t < t1; ++t) {
     const int x4 = t * V3 + x3;
     const int tb = t * V3;
+    if (AL) __builtin_amdgcn_s_waitcnt(0);  // this wavefront's copies of slice t's links have landed
     __syncthreads();  // every thread is done with the previous slice's LDS
+    const lds_f2_t lU = (lds_f2_t)(void*)sU[AL ? (t & 1) : 0];
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       const float2 v0 = p0.v[k / 3][k % 3], v1 = p1.v[k / 3][k % 3];
       ((lds_f4w_t)(void*)sP)[k * cst + me] = nf4{v0.x, v0.y, v1.x, v1.y};
     }
-    for (int i = threadIdx.x; i < 36 * NS; i += blockDim.x) {  // own sites, mu = x, y, z, t
-      const int mab = i / NS, q = i - mab * NS, mu = mab / 9;
-      const int xx = bx + q % TX, yy = by + (q / TX) % TY, zz = bz + q / (TX * TY);
-      const bool cross = mu == 0 ? xx == Lx - 1 : (mu == 1 ? yy == Ly - 1 : (mu == 2 ? zz == Lz - 1 : t == Lt - 1));
-      sU[i] = cscale(gauge[(long long)mab * V4 + tb + (zz * Ly + yy) * Lx + xx], cross ? a.ph[mu] : 1.0f);
+    if (AL) {
+      // the slice is written: wait for this wavefront's LDS stores (no fence:
+      // nothing else of this wavefront needs to land first) and meet
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+      __builtin_amdgcn_s_barrier();
+    } else {
+      stage_links<TX, TY, TZ>(sU[0], gauge, a, V4, tb, t, bx, by, bz);
+      __syncthreads();
     }
-    for (int i = threadIdx.x; i < 9 * (NF0 + NF1 + NF2); i += blockDim.x) {  // minus faces: U_mu(x - mu)
-      int mu, r;
-      if (i < 9 * NF0) { mu = 0; r = i; }
-      else if (i < 9 * (NF0 + NF1)) { mu = 1; r = i - 9 * NF0; }
-      else { mu = 2; r = i - 9 * (NF0 + NF1); }
-      const int nf = mu == 0 ? NF0 : (mu == 1 ? NF1 : NF2);
-      const int ab = r / nf, f = r - ab * nf;
-      int xx, yy, zz;
-      bool cross;
-      if (mu == 0) { cross = bx == 0; xx = cross ? Lx - 1 : bx - 1; yy = by + f % TY; zz = bz + f / TY; }
-      else if (mu == 1) { cross = by == 0; xx = bx + f % TX; yy = cross ? Ly - 1 : by - 1; zz = bz + f / TX; }
-      else { cross = bz == 0; xx = bx + f % TX; yy = by + f / TX; zz = cross ? Lz - 1 : bz - 1; }
-      sU[36 * NS + (mu == 0 ? 0 : (mu == 1 ? 9 * NF0 : 9 * (NF0 + NF1))) + r] =
-          cscale(gauge[(long long)(mu * 9 + ab) * V4 + tb + (zz * Ly + yy) * Lx + xx], cross ? a.ph[mu] : 1.0f);
-    }
-    __syncthreads();
     // own terms, backward t-hop (half spinor and link carried from slice t - 1)
     own_pair_x(a0, a1, p0, p1, lP + site * np + jm, lP + site * np + jq, cst, s0, Ls, dg, mf, up0, dn0);
     mul_link_1<true>(U, hp0, u);
@@ -1470,6 +1599,10 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, TX * TY * TZ >= 64 ? 1 : 2) void 
     // next slice's backward t-hop link
     const bool top = t == Lt - 1;
     load_pair_o(p0, p1, inb, cs, (unsigned)(((top ? 0 : t + 1) * V3 + x3) * Ls + s0) * 8u);
+    // the next slice's links, copied behind the spinor load (vmcnt is in
+    // order: waiting for the spinor does not wait for them); they land during
+    // this slice's forward hop and stores, and the next barrier waits for them
+    if (AL && t + 1 < t1) stage_links_async<TX, TY, TZ>(sU[(t + 1) & 1], gp, a, V4, tb + V3, bx, by, bz);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       const xf2 v = lU[(27 + q) * NS + site];
@@ -1488,11 +1621,15 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, TX * TY * TZ >= 64 ? 1 : 2) void 
       for (int c = 0; c < 3; ++c) {
         float2 r0 = cscale(a0.v[sp][c], -0.5f), r1 = cscale(a1.v[sp][c], -0.5f);
         if (MODE == 1) {
-          const nf4 bb = *(gf4_t)(sbase(bb0, cs, sp * 3 + c) + o5);
+          const nf4 bb = AL ? __builtin_nontemporal_load((gf4_t)(sbase(bb0, cs, sp * 3 + c) + o5))
+                            : *(gf4_t)(sbase(bb0, cs, sp * 3 + c) + o5);
           r0 = make_float2(bb.x - r0.x, bb.y - r0.y);
           r1 = make_float2(bb.z - r1.x, bb.w - r1.y);
         }
-        *(gf4w_t)(sbase(outb, cs, sp * 3 + c) + o5) = nf4{r0.x, r0.y, r1.x, r1.y};
+        // AL: results and b stream past L2 (read or written once), which then
+        // keeps more of the input slices that neighbouring tiles read as faces
+        if (AL) __builtin_nontemporal_store(nf4{r0.x, r0.y, r1.x, r1.y}, (gf4w_t)(sbase(outb, cs, sp * 3 + c) + o5));
+        else *(gf4w_t)(sbase(outb, cs, sp * 3 + c) + o5) = nf4{r0.x, r0.y, r1.x, r1.y};
         if (partial) nrmf += r0.x * r0.x + r0.y * r0.y + r1.x * r1.x + r1.y * r1.y;
       }
   }
@@ -1764,19 +1901,29 @@ struct FTile {
   bool pipelined = false;   // k_dslash_tw (loads one hop ahead)
   bool ws = false;          // k_dslash_ws: tx, ty, tz = brick of (x pairs, y, z), target = t-slices per chunk
   bool xchg = false;        // k_dslash_tx: spatial neighbours inside the tile through LDS
+  bool alinks = false;      // with xchg: next slice's links copied to LDS directly, during this slice
 };
 constexpr FTile kFTiles[] = {
+    // LDS exchange with asynchronous links first: the default where it applies
+    {8, 4, 2, 768, false, 0, false, false, false, false, true, true},
+    {8, 4, 2, 1536, false, 0, false, false, false, false, true, true},
+    {8, 4, 2, 384, false, 0, false, false, false, false, true, true},
+    {4, 4, 4, 768, false, 0, false, false, false, false, true, true},
+    {4, 4, 2, 1536, false, 0, false, false, false, false, true, true},
+    {4, 4, 2, 3072, false, 0, false, false, false, false, true, true},
+    {8, 4, 2, 3072, false, 1, false, false, false, false, true, true},
+    // t-march kernels loading every neighbour from memory
     {4, 4, 2, 256, false, 0, true}, {4, 4, 2, 512, false, 0, true}, {4, 4, 2, 256, false, 0},
     {4, 4, 2, 512, false, 0},       {8, 2, 2, 512, false, 0},       {8, 4, 2, 256, false, 0},
     {4, 4, 4, 512, false, 0},       {4, 8, 2, 512, false, 0},       {4, 4, 2, 1024, false, 1},
     {4, 4, 2, 512, true, 0},        {4, 4, 2, 256, false, 0, true, true},
     {4, 4, 2, 256, false, 0, true, false, true}, {4, 4, 2, 256, false, 0, false, false, true},
     {4, 4, 2, 512, false, 0, true, false, true},
+    // one wavefront per site pair
     {2, 2, 2, 2, false, 0, false, false, false, true}, {4, 4, 4, 2, false, 0, false, false, false, true},
     {8, 16, 1, 2, false, 0, false, false, false, true},
-    {4, 4, 2, 256, false, 0, false, false, false, false, true}, {4, 4, 2, 512, false, 0, false, false, false, false, true},
-    {4, 4, 2, 1024, false, 1, false, false, false, false, true}, {8, 4, 2, 256, false, 0, false, false, false, false, true},
-    {4, 4, 4, 256, false, 0, false, false, false, false, true},
+    // LDS exchange, links staged synchronously
+    {4, 4, 2, 256, false, 0, false, false, false, false, true},
 };
 constexpr int NFTILE = sizeof(kFTiles) / sizeof(kFTiles[0]);
 
@@ -1810,23 +1957,30 @@ static int ftile_ntiles(const Geometry& g, int i) {
   return (g.L[0] / f.tx) * (g.L[1] / f.ty) * (g.L[2] / f.tz);
 }
 
-static int ftile_chunk(const Geometry& g, int i) {
-  if (kFTiles[i].ws) return std::min(g.L[3], kFTiles[i].target);
-  const int want_chunks = std::max(1, std::min(g.L[3], ceil_div(kFTiles[i].target, ftile_ntiles(g, i))));
+// t-slices per workgroup.  target: site-pair kernel, the chunk itself;
+// LDS-exchange kernels with asynchronous links, the workgroups wanted over
+// all right-hand sides (long chunks when many right-hand sides fill the chip:
+// fewer chunk starts, whose first slice is loaded twice); others, the
+// workgroups wanted per right-hand side.
+static int ftile_chunk(const Geometry& g, int i, int nrhs) {
+  const FTile& f = kFTiles[i];
+  if (f.ws) return std::min(g.L[3], f.target);
+  const int per = f.alinks ? ftile_ntiles(g, i) * std::max(1, nrhs) : ftile_ntiles(g, i);
+  const int want_chunks = std::max(1, std::min(g.L[3], ceil_div(f.target, per)));
   return ceil_div(g.L[3], want_chunks);
 }
 
 int dslash_ftile_count() { return NFTILE; }
 
-bool dslash_ftile_desc(const Geometry& g, int i, int desc[4], int* flags) {
+bool dslash_ftile_desc(const Geometry& g, int i, int nrhs, int desc[4], int* flags) {
   if (!ftile_ok(g, i)) return false;
   desc[0] = kFTiles[i].tx;
   desc[1] = kFTiles[i].ty;
   desc[2] = kFTiles[i].tz;
-  desc[3] = ftile_chunk(g, i);
+  desc[3] = ftile_chunk(g, i, nrhs);
   *flags = (kFTiles[i].eight_loads ? 1 : 0) | (kFTiles[i].fold ? 2 : 0) | (kFTiles[i].one_per_cu ? 4 : 0) |
            (kFTiles[i].lds_links ? 8 : 0) | (kFTiles[i].pipelined ? 16 : 0) | (kFTiles[i].ws ? 32 : 0) |
-           (kFTiles[i].xchg ? 64 : 0);
+           (kFTiles[i].xchg ? 64 : 0) | (kFTiles[i].alinks ? 256 : 0);
   return true;
 }
 
@@ -1870,17 +2024,18 @@ static void launch_tpair(const float2* in, float2* out, const float2* b, const f
   }
   constexpr int P1 = 96 * 1024;
   if (f.xchg) {
-#define MG_TX(X, Y, Z)                                                                                       \
-  if (f.tx == X && f.ty == Y && f.tz == Z) {                                                                 \
-    if (!dagger && mode == 0) hipLaunchKernelGGL((k_dslash_tx<false, 0, X, Y, Z>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
-    else if (!dagger && mode == 1) hipLaunchKernelGGL((k_dslash_tx<false, 1, X, Y, Z>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
-    else if (dagger && mode == 0) hipLaunchKernelGGL((k_dslash_tx<true, 0, X, Y, Z>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
-    else hipLaunchKernelGGL((k_dslash_tx<true, 1, X, Y, Z>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
+#define MG_TX(X, Y, Z, AL)                                                                                   \
+  if (f.tx == X && f.ty == Y && f.tz == Z && f.alinks == AL) {                                               \
+    if (!dagger && mode == 0) hipLaunchKernelGGL((k_dslash_tx<false, 0, X, Y, Z, AL>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
+    else if (!dagger && mode == 1) hipLaunchKernelGGL((k_dslash_tx<false, 1, X, Y, Z, AL>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
+    else if (dagger && mode == 0) hipLaunchKernelGGL((k_dslash_tx<true, 0, X, Y, Z, AL>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
+    else hipLaunchKernelGGL((k_dslash_tx<true, 1, X, Y, Z, AL>), grid, blk, 0, st, in, out, b, gauge, ta, partial); \
     return;                                                                                                  \
   }
-    MG_TX(4, 4, 2)
-    MG_TX(8, 4, 2)
-    MG_TX(4, 4, 4)
+    MG_TX(4, 4, 2, false)
+    MG_TX(4, 4, 2, true)
+    MG_TX(8, 4, 2, true)
+    MG_TX(4, 4, 4, true)
 #undef MG_TX
     fail(MGDWF_ERR_INVALID_ARG, "no LDS-exchange kernel for this Dslash tiling");
   }
@@ -1960,11 +2115,11 @@ static DslashKind dslash_kind(const Geometry& g) {
 }
 
 template <class C2>
-int dslash_nblocks(const Geometry& g) {
+int dslash_nblocks(const Geometry& g, int nrhs) {
   switch (dslash_kind<C2>(g)) {
     case DS_TPAIR: {
       const int i = ftile_of(g);
-      return ftile_ntiles(g, i) * ceil_div(g.L[3], ftile_chunk(g, i));
+      return ftile_ntiles(g, i) * ceil_div(g.L[3], ftile_chunk(g, i, nrhs));
     }
     case DS_TMARCH:
       return (g.L[0] / TMX) * (g.L[1] / TMY) * (g.L[2] / TMZ) * ceil_div(g.L[3], tmarch_chunk(g));
@@ -1972,8 +2127,8 @@ int dslash_nblocks(const Geometry& g) {
       return ceil_div(g.V5, 256);
   }
 }
-template int dslash_nblocks<double2>(const Geometry&);
-template int dslash_nblocks<float2>(const Geometry&);
+template int dslash_nblocks<double2>(const Geometry&, int);
+template int dslash_nblocks<float2>(const Geometry&, int);
 
 template <class C2>
 void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geometry& g, double M5,
@@ -1988,7 +2143,7 @@ void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geomet
     WSArgs wa;
     wa.d = a;
     wa.nxp = g.L[0] / 2;
-    wa.tc = ftile_chunk(g, i);
+    wa.tc = ftile_chunk(g, i, nrhs);
     wa.nchunk = ceil_div(g.L[3], wa.tc);
     wa.nrhs = nrhs;
     wa.bx = f.tx; wa.by = f.ty; wa.bz = f.tz;
@@ -2005,10 +2160,11 @@ void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geomet
     TMArgs ta;
     ta.d = a;
     ta.ntx = g.L[0] / f.tx; ta.nty = g.L[1] / f.ty; ta.ntz = g.L[2] / f.tz;
-    ta.tc = ftile_chunk(g, i);
+    ta.tc = ftile_chunk(g, i, nrhs);
     ta.fold = f.fold;
     ta.nrhs = nrhs;
-    const dim3 grid = f.fold ? dim3(dslash_nblocks<C2>(g) * nrhs, 1) : dim3(dslash_nblocks<C2>(g), nrhs);
+    const int nb = dslash_nblocks<C2>(g, nrhs);
+    const dim3 grid = f.fold ? dim3(nb * nrhs, 1) : dim3(nb, nrhs);
     launch_tpair(in, out, b, gauge, ta, partial, dagger, mode, grid, dim3(f.tx * f.ty * f.tz * g.Ls / 2), i, st);
     MG_LAUNCH_CHECK();
     return;
@@ -2018,7 +2174,7 @@ void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geomet
     ta.d = a;
     ta.ntx = g.L[0] / TMX; ta.nty = g.L[1] / TMY; ta.ntz = g.L[2] / TMZ;
     ta.tc = tmarch_chunk(g);
-    dim3 grid(dslash_nblocks<C2>(g), nrhs), blk(TMS * g.Ls);
+    dim3 grid(dslash_nblocks<C2>(g, nrhs), nrhs), blk(TMS * g.Ls);
 #define MG_TM(DAG, MODE) \
   hipLaunchKernelGGL((k_dslash_tm<C2, DAG, MODE>), grid, blk, 0, st, in, out, b, gauge, ta, partial)
     if (!dagger && mode == 0) MG_TM(false, 0);
@@ -2029,7 +2185,7 @@ void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geomet
     MG_LAUNCH_CHECK();
     return;
   }
-  dim3 grid(dslash_nblocks<C2>(g), nrhs), blk(256);
+  dim3 grid(dslash_nblocks<C2>(g, nrhs), nrhs), blk(256);
 #define MG_DS(DAG, MODE) \
   hipLaunchKernelGGL((k_dslash<C2, DAG, MODE>), grid, blk, 0, st, in, out, b, gauge, a, partial)
   if (!dagger && mode == 0) MG_DS(false, 0);

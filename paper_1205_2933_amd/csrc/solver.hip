@@ -76,7 +76,7 @@ template <> const float2* basis_of<float2>(mgdwf_ctx* c) { return c->V32.as<floa
 template <class F2>
 void fine_op(mgdwf_ctx* c, const F2* in, F2* out, const F2* b, bool dag, int mode, int nrhs, int dst) {
   double* partial = nullptr;
-  const int nb = dslash_nblocks<F2>(c->g);
+  const int nb = dslash_nblocks<F2>(c->g, nrhs);
   if (dst >= 0) partial = c->buf<double>("dpart", (size_t)nb * nrhs);
   dslash_ex<F2>(in, out, b, gauge_of<F2>(c), c->g, c->M5, c->mf, dag, mode, nrhs, partial, c->st);
   if (dst >= 0) finalize_rhs(partial, nb, 1, c->buf<double>("slots", (size_t)nrhs * NSLOT), dst, nrhs, c->st);

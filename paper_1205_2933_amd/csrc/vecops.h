@@ -55,14 +55,14 @@ void reflect5(const C2* in, C2* out, const Geometry& g, int nf, hipStream_t st);
 
 // dslash.hip
 template <class C2>
-int dslash_nblocks(const Geometry& g);
+int dslash_nblocks(const Geometry& g, int nrhs);
 template <class C2>
 void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geometry& g, double M5, double mf,
                bool dagger, int mode, int nrhs, double* partial, hipStream_t st);
-// FP32 tilings: how many, and (x, y, z tile, t-slices per workgroup) of entry
-// i if it applies to g, with its MGDWF_TILE_* flags.
+// FP32 tilings: how many, and (x, y, z tile, t-slices per workgroup at nrhs
+// right-hand sides) of entry i if it applies to g, with its MGDWF_TILE_* flags.
 int dslash_ftile_count();
-bool dslash_ftile_desc(const Geometry& g, int i, int desc[4], int* flags);
+bool dslash_ftile_desc(const Geometry& g, int i, int nrhs, int desc[4], int* flags);
 
 // transfer.hip
 size_t restrict_partial_doubles(const CoarseGeometry& cg, int nrhs);
