@@ -42,19 +42,29 @@ def counted_traffic(tiling_id):
     """HBM bytes per launch of the FP32 Dslash at 12 RHS, from the committed
     FETCH_SIZE / WRITE_SIZE counter summary -- or None when the kernel source
     has changed since the counters were taken, or when the autotuner picked
-    another tiling than the default one the counters were taken on."""
+    another tiling than the one the counters were taken on."""
     import hashlib
-    if tiling_id != 0:
-        return None
     try:
         fields = dict(line.split(":", 1) for line in open(COUNTER_SUMMARY) if line.startswith("- ") and ":" in line)
         fields = {k[2:].strip(): v.strip().strip("`") for k, v in fields.items()}
         src = hashlib.sha256(open(DSLASH_SRC, "rb").read()).hexdigest()
-        if fields.get("dslash.hip sha256") != src:
+        if fields.get("dslash.hip sha256") != src or int(fields.get("tiling id", -1)) != tiling_id:
             return None
         return float(fields["traffic bytes per launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def dslash_kernel_name(flags):
+    """The FP32 Dslash kernel a tiling's MGDWF_TILE_* flags select."""
+    if flags & 64:
+        return "k_dslash_tx" + (" (LDS exchange, links copied to LDS a slice ahead)" if flags & 256 else
+                                " (LDS exchange)")
+    if flags & 32:
+        return "k_dslash_ws (wavefront per site pair)"
+    if flags & 16:
+        return "k_dslash_tw (t-march, pipelined)"
+    return "k_dslash_tq (t-march)" if not flags & 1 else "k_dslash_tp (t-march, reloads)"
 
 
 def log(msg):
@@ -719,7 +729,8 @@ def main():
         "coarse_apply_f32_us": msC * 1e3,
         "dslash_tiling": tiling,
         "precision": precision,
-        "roofline": {"bound": "hbm", "kernel": "k_dslash_tq (FP32 Dslash, 12 RHS per launch, autotuned tiling)",
+        "roofline": {"bound": "hbm", "kernel": dslash_kernel_name(tiling["flags"]) +
+                     f", FP32, 12 RHS per launch, tiling {tiling['id']} {tiling['tile']}",
                      "achieved": gbs32_12, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs32_12 / HBM_PEAK_GBS,
                      "algorithmic_bytes": bytes32_12, "launch_us": ms32_12 * 1e3, "traffic": counted_traffic(tiling["id"])},
     }

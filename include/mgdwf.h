@@ -378,6 +378,9 @@ typedef enum {
 #define MGDWF_TILE_ASYNC_LINKS 256   /* with 64: the next slice's links copied to LDS      */
                                      /* (global_load_lds) during this slice; results      */
                                      /* stream past L2; 4th = t-slices at the tune's nrhs   */
+#define MGDWF_TILE_XCD_UNITS 512     /* workgroups in units of (RHS, z-slab), each unit on  */
+                                     /* one XCD (its faces in that XCD's L2) when nrhs and  */
+                                     /* the z tiles allow whole rounds of eight units       */
 typedef struct {
   int32_t ntilings;                   /* tilings timed                                  */
   int32_t chosen;                     /* index into the arrays below                     */

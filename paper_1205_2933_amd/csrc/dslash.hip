@@ -364,7 +364,9 @@ struct TMArgs {
   int ntx, nty, ntz;  // tiles per direction
   int tc;             // t-slices per chunk
   int fold = 0;       // 1: one-dimensional grid over (t-chunk, rhs, tile), t-chunk outermost
+                      // 2: one-dimensional grid of XCD units (one t-chunk; see k_dslash_tx)
   int nrhs = 1;
+  int zs = 1;         // fold 2: z-slabs per right-hand side
 };
 
 __device__ __forceinline__ double block_sum_dyn(double v) {
@@ -1475,7 +1477,19 @@ __global__ __launch_bounds__(TX * TY * TZ * 8, TX * TY * TZ >= 64 ? 1 : 2) void 
   const int ntiles = ta.ntx * ta.nty * ta.ntz;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   int chunk, tile, rhs, pidx;
-  if (ta.fold) {
+  if (ta.fold == 2) {
+    // XCD units: unit u = (rhs, z-slab of ntiles / zs tiles) goes whole to
+    // XCD u % 8 (workgroups are dealt to the eight XCDs in turn), so x, y and
+    // most z faces are read from the XCD's own L2; each XCD runs its units
+    // one after another.  One t-chunk.
+    const int S = ntiles / ta.zs;
+    const int xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int u = xcd + 8 * (j / S);
+    rhs = u / ta.zs;
+    tile = (u - rhs * ta.zs) * S + j % S;
+    chunk = 0;
+    pidx = rhs * ntiles + tile;
+  } else if (ta.fold) {
     const int per_chunk = ta.nrhs * ntiles;
     chunk = bid / per_chunk;
     const int r2 = bid - chunk * per_chunk;
@@ -1905,6 +1919,7 @@ struct FTile {
 };
 constexpr FTile kFTiles[] = {
     // LDS exchange with asynchronous links first: the default where it applies
+    {8, 4, 2, 768, false, 2, false, false, false, false, true, true},
     {8, 4, 2, 768, false, 0, false, false, false, false, true, true},
     {8, 4, 2, 1536, false, 0, false, false, false, false, true, true},
     {8, 4, 2, 384, false, 0, false, false, false, false, true, true},
@@ -1912,6 +1927,8 @@ constexpr FTile kFTiles[] = {
     {4, 4, 2, 1536, false, 0, false, false, false, false, true, true},
     {4, 4, 2, 3072, false, 0, false, false, false, false, true, true},
     {8, 4, 2, 3072, false, 1, false, false, false, false, true, true},
+    {4, 4, 4, 768, false, 2, false, false, false, false, true, true},
+    {4, 4, 2, 1536, false, 2, false, false, false, false, true, true},
     // t-march kernels loading every neighbour from memory
     {4, 4, 2, 256, false, 0, true}, {4, 4, 2, 512, false, 0, true}, {4, 4, 2, 256, false, 0},
     {4, 4, 2, 512, false, 0},       {8, 2, 2, 512, false, 0},       {8, 4, 2, 256, false, 0},
@@ -1957,6 +1974,14 @@ static int ftile_ntiles(const Geometry& g, int i) {
   return (g.L[0] / f.tx) * (g.L[1] / f.ty) * (g.L[2] / f.tz);
 }
 
+// z-slabs per right-hand side for XCD units: the smallest divisor zs of the
+// tile count in z with nrhs * zs a multiple of the eight XCDs (0: none).
+static int xcd_units_zs(int ntz, int nrhs) {
+  for (int zs = 1; zs <= ntz; ++zs)
+    if (ntz % zs == 0 && (nrhs * zs) % 8 == 0) return zs;
+  return 0;
+}
+
 // t-slices per workgroup.  target: site-pair kernel, the chunk itself;
 // LDS-exchange kernels with asynchronous links, the workgroups wanted over
 // all right-hand sides (long chunks when many right-hand sides fill the chip:
@@ -1978,7 +2003,8 @@ bool dslash_ftile_desc(const Geometry& g, int i, int nrhs, int desc[4], int* fla
   desc[1] = kFTiles[i].ty;
   desc[2] = kFTiles[i].tz;
   desc[3] = ftile_chunk(g, i, nrhs);
-  *flags = (kFTiles[i].eight_loads ? 1 : 0) | (kFTiles[i].fold ? 2 : 0) | (kFTiles[i].one_per_cu ? 4 : 0) |
+  *flags = (kFTiles[i].eight_loads ? 1 : 0) | (kFTiles[i].fold == 1 ? 2 : 0) | (kFTiles[i].fold == 2 ? 512 : 0) |
+           (kFTiles[i].one_per_cu ? 4 : 0) |
            (kFTiles[i].lds_links ? 8 : 0) | (kFTiles[i].pipelined ? 16 : 0) | (kFTiles[i].ws ? 32 : 0) |
            (kFTiles[i].xchg ? 64 : 0) | (kFTiles[i].alinks ? 256 : 0);
   return true;
@@ -2163,8 +2189,12 @@ void dslash_ex(const C2* in, C2* out, const C2* b, const C2* gauge, const Geomet
     ta.tc = ftile_chunk(g, i, nrhs);
     ta.fold = f.fold;
     ta.nrhs = nrhs;
+    if (f.fold == 2) {  // the smallest z-slab count giving whole rounds of eight units; else plain order
+      ta.zs = xcd_units_zs(ta.ntz, nrhs);
+      if (ta.zs == 0 || ta.tc < g.L[3]) { ta.fold = 0; ta.zs = 1; }
+    }
     const int nb = dslash_nblocks<C2>(g, nrhs);
-    const dim3 grid = f.fold ? dim3(nb * nrhs, 1) : dim3(nb, nrhs);
+    const dim3 grid = ta.fold ? dim3(nb * nrhs, 1) : dim3(nb, nrhs);
     launch_tpair(in, out, b, gauge, ta, partial, dagger, mode, grid, dim3(f.tx * f.ty * f.tz * g.Ls / 2), i, st);
     MG_LAUNCH_CHECK();
     return;
