@@ -24,5 +24,6 @@ from .lattice import (  # noqa: F401
     gaussian_fermion,
     point_sources,
     random_starts,
+    random_coarse_starts,
     random_gauge_transform,
 )

@@ -164,6 +164,14 @@ def random_starts(L: Sequence[int], Ls: int, nvec: int, seed: int) -> np.ndarray
     return gaussian_fermion(L, Ls, seed, n=nvec)
 
 
+def random_coarse_starts(Lc: Sequence[int], nv: int, n: int, seed: int) -> np.ndarray:
+    """Random starting vectors on a coarse lattice (a third multigrid level's
+    setup): shape (n, Lt_c, Lz_c, Ly_c, Lx_c, 2, nv), Re, Im i.i.d. N(0,1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shp = (n,) + tuple(Lc[::-1]) + (2, nv)
+    return rng.standard_normal(shp) + 1j * rng.standard_normal(shp)
+
+
 def random_gauge_transform(L: Sequence[int], seed: int, eps: float = 1.0) -> np.ndarray:
     """One random SU(3) matrix per 4D site, shape (Lt, Lz, Ly, Lx, 3, 3)."""
     rng = np.random.Generator(np.random.PCG64(seed))

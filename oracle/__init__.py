@@ -25,6 +25,9 @@ Algorithms for Domain-Wall Fermions", Lattice 2011):
                    ran (Sec. 3 first paragraph, Sec. 4): basis of D^+D's
                    near-null vectors, A_c = P^+ D^+D P (33-offset stencil),
                    MR smoothing on D^+D, CG on A_c.
+* ``threelevel`` -- a third level under the squared two-level method: near-null
+                   vectors of A_c, their block basis, A_cc = R2 A_c P2, the
+                   level-2 cycle, V- and W-cycles (Sec. 2, recursion).
 * ``lowmodes``  -- lowest eigenpairs of D^+D from a dense eigensolver and the
                    fraction |P R e|^2 / |e|^2 of a field in the coarse space
                    (Sec. 2, Fig. 1 right).
