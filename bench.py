@@ -266,7 +266,7 @@ def squared_leg(mg, U_dev, B_main, log):
 def low_modes_leg(mg, log):
     """Low modes and the coarse space (paper Sec. 2, Fig. 1 right) on the
     small shape: 4^4 x Ls=8, m_f = 0.01, eps = 0.3 links, 2^4 blocks.  The
-    lowest 40 eigenpairs of D^+D by 120 Lanczos steps on (D^+D)^-1 (each two
+    lowest 24 eigenpairs of D^+D by 60 Lanczos steps on (D^+D)^-1 (each two
     FP64 squared-operator multigrid solves to 1e-12), and the fraction |P R e|^2 / |e|^2 of
     each inside three coarse spaces of 32 dof per block: the 9-point setup's
     (8 adaptive vectors and their reflections), the squared setup's (16
@@ -277,6 +277,7 @@ def low_modes_leg(mg, log):
     from inputs import gaussian_fermion, prepare_gauge, random_starts
 
     Lq, Lsq, mfq, blk = (4, 4, 4, 4), 8, 0.01, (2, 2, 2, 2)
+    NLM = 24
     t0 = time.perf_counter()
     U = torch.from_numpy(prepare_gauge(Lq, 0.3, 11)).cuda()
     kw = dict(sweeps=1, sweep0_iters=100, nu_pre=4, nu_post=4, coarse_tol=0.1, coarse_maxiter=200,
@@ -289,20 +290,24 @@ def low_modes_leg(mg, log):
     mg.mgdwf_setup(hs, mg.make_mg_params(blk, 16, squared=True, **kw),
                    torch.from_numpy(random_starts(Lq, Lsq, 16, 21)).cuda())
     t = time.perf_counter()
-    ev, E, res = mg.mgdwf_low_modes(hs, torch.from_numpy(gaussian_fermion(Lq, Lsq, 31)).cuda(), 40, 120,
+    ev, E, res = mg.mgdwf_low_modes(hs, torch.from_numpy(gaussian_fermion(Lq, Lsq, 31)).cuda(), NLM, 60,
                                     solve_tol=1e-12)
     lanczos_s = time.perf_counter() - t
-    cov = {"nine_point_setup": mg.mgdwf_coarse_coverage(h9, E, 40),
-           "squared_setup": mg.mgdwf_coarse_coverage(hs, E, 40)}
+    cov = {"nine_point_setup": mg.mgdwf_coarse_coverage(h9, E, NLM),
+           "squared_setup": mg.mgdwf_coarse_coverage(hs, E, NLM)}
     mg.mgdwf_set_nullvecs(hs, blk, E[:16].contiguous(), 16)
-    cov["lowest_16_modes"] = mg.mgdwf_coarse_coverage(hs, E, 40)
+    cov["lowest_16_modes"] = mg.mgdwf_coarse_coverage(hs, E, NLM)
     h9.close()
     hs.close()
-    out = {"lattice": "4^4 x Ls=8, m_f=0.01, eps=0.3, 2^4 blocks", "lanczos_steps": 120, "lanczos_s": lanczos_s,
-           "eigenvalues": ev, "max_eig_residual": max(res),
-           "coverage": {k: [round(x, 6) for x in v] for k, v in cov.items()},
-           "summary": {k: {"modes_0_15_min": float(np.min(v[:16])), "modes_16_39_mean": float(np.mean(v[16:])),
-                           "modes_16_39_min": float(np.min(v[16:]))} for k, v in cov.items()},
+    # the near-zero modes end at the largest relative gap of the spectrum
+    lam = np.array(ev)
+    k = int(np.argmax(lam[1:] / lam[:-1])) + 1
+    out = {"lattice": "4^4 x Ls=8, m_f=0.01, eps=0.3, 2^4 blocks", "lanczos_steps": 60, "lanczos_s": lanczos_s,
+           "eigenvalues": ev, "max_eig_residual": max(res), "near_zero_modes": k,
+           "coverage": {kk: [round(x, 6) for x in v] for kk, v in cov.items()},
+           "summary": {kk: {"near_zero_min": float(np.min(v[:k])), "near_zero_mean": float(np.mean(v[:k])),
+                            "rest_mean": float(np.mean(v[k:])), "modes_0_15_min": float(np.min(v[:16]))}
+                       for kk, v in cov.items()},
            "seconds": time.perf_counter() - t0}
     log(f"low modes: lambda {ev[0]:.3e} .. {ev[-1]:.3e}, residual {max(res):.1e}, summary {out['summary']}")
     return out
@@ -441,16 +446,21 @@ def learned_leg(mg, h_main, fields_future, c5_future, log):
     mg.mgdwf_trim(h_main)
     torch.cuda.empty_cache()
     t0 = time.perf_counter()
-    Uc5 = c5_future.result()
+    Uc5 = torch.from_numpy(c5_future.result()).cuda()
     out["c5_gauge_wait_s"] = time.perf_counter() - t0
-    h = mg.Handle(L_C5, LS, M5, MF)
-    mg.mgdwf_set_gauge(h, torch.from_numpy(Uc5).cuda())
-    del Uc5
+    # each setup below gets a handle of its own, closed after its solve: one
+    # handle holding one setup's basis (about 100 GB here) at a time
+    def fresh():
+        hh = mg.Handle(L_C5, LS, M5, MF)
+        mg.mgdwf_set_gauge(hh, Uc5)
+        return hh
+
+    h = fresh()
     # one point source (spin 0, colour 0 at the origin, on the wall s = Ls - 1)
     b = torch.zeros(h.nfine, dtype=torch.complex128, device="cuda")
     b[(LS - 1) * 12] = 1.0
 
-    def solve_iters():
+    def solve_iters(h):
         mg.mgdwf_trim(h)  # the setup's workspaces go first
         mem("learned leg, before a 24^3x48 solve")
         mg.mgdwf_set_mg_params(h, mg_params(mg, "f32", "f16"))
@@ -461,7 +471,7 @@ def learned_leg(mg, h_main, fields_future, c5_future, log):
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         del x
-        mg.mgdwf_trim(h)  # the solve's workspaces (about 60 GB here) go before the next setup
+        mg.mgdwf_trim(h)
         torch.cuda.empty_cache()
         mem("learned leg, after a 24^3x48 solve")
         return r["outer_iters"], r["true_relres"] < 1e-10, el
@@ -474,22 +484,28 @@ def learned_leg(mg, h_main, fields_future, c5_future, log):
     rep = ln.targets(h, mg_params(mg, "f64", "f64"), 12)
     torch.cuda.synchronize()
     full_s = time.perf_counter() - t
-    it_full, conv, s_full = solve_iters()
+    it_full, conv, s_full = solve_iters(h)
+    h.close()
+    torch.cuda.empty_cache()
     out["full_setup"] = {"sweep0_iters": 400, "setup_s": full_s, "null_residual": rep["null_residual"][-1],
                          "mg_iters": it_full, "converged": conv, "solve_s": s_full}
     # (c) the same short sweep from random starts: the reference of the fallback check
+    h = fresh()
     torch.cuda.synchronize()
     t = time.perf_counter()
     rep = mg.mgdwf_setup(h, short, ln.random_starts(h, NVEC // 2, 21))
     torch.cuda.synchronize()
     st = time.perf_counter() - t
-    it, conv, s_r = solve_iters()
+    it, conv, s_r = solve_iters(h)
+    h.close()
+    torch.cuda.empty_cache()
     ref_null = rep["null_residual"][-1]
     out["random_short_setup"] = {"sweep0_iters": 100, "setup_s": st, "null_residual": ref_null,
                                  "mg_iters": it, "converged": conv, "solve_s": s_r}
     # (b) the network's proposals and the same short sweep, with the fallback
+    h = fresh()
     r = ln.learned_setup(net, h, short, mg_params(mg, "f64", "f64"), seed=11, reference_null=ref_null)
-    it, conv, s_l = solve_iters()
+    it, conv, s_l = solve_iters(h)
     fb = r["fallback"]
     if not fb and ln.needs_fallback(it, it_full):
         t = time.perf_counter()
@@ -497,7 +513,7 @@ def learned_leg(mg, h_main, fields_future, c5_future, log):
         torch.cuda.synchronize()
         r["setup_s"] += time.perf_counter() - t
         fb = True
-        it, conv, s_l = solve_iters()
+        it, conv, s_l = solve_iters(h)
     out["learned_setup"] = {"sweep0_iters": 100, "setup_s": r["setup_s"], "null_residual": r["null_residual"],
                             "fallback": fb, "mg_iters": it, "converged": conv, "solve_s": s_l,
                             "setup_speedup_vs_full": full_s / r["setup_s"]}
@@ -508,7 +524,7 @@ def learned_leg(mg, h_main, fields_future, c5_future, log):
     V = ln.propose(net, h, 2)
     torch.cuda.synchronize()
     out["inference_24c48_s"] = time.perf_counter() - t
-    del V
+    del V, Uc5
     h.close()
     torch.cuda.empty_cache()
     log(f"learned {out}")

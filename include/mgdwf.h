@@ -269,6 +269,65 @@ mgdwf_status mgdwf_solve(mgdwf_handle h, const double* b, double* x, int32_t nrh
  * to FP32 and return the result as complex128).  Returns after completion. */
 mgdwf_status mgdwf_apply_vcycle(mgdwf_handle h, const double* in, double* out, int32_t nrhs);
 
+/* ---- a third level (Sec. 2: the coarse solve done by the same multigrid) -- */
+
+/* Under the squared coarse operator A_c = P^+ D^+D P a further level: Nv2
+ * near-null vectors of A_c (CG on A_c w = 0, null_iters steps from each
+ * start), split by the coarse chirality and orthonormalised per block of
+ * coarse sites (R2 = W^+, P2 = W), and A_cc = R2 A_c P2 as a 33-offset
+ * stencil.  With gamma > 0 the squared V-cycle's coarse solve becomes gamma
+ * sweeps of e <- e + K2(b - A_c e) from e = 0 (gamma = 1: V-cycle, 2:
+ * W-cycle), K2 = nu MR steps on A_c, R2, CG on A_cc (coarse_tol,
+ * coarse_maxiter; residual tested every 8 iterations), P2, nu MR steps; with
+ * gamma = 0 it stays CG on A_c.  Applications of A_cc count as coarse
+ * applications in the solve report. */
+typedef struct {
+  int32_t block[4];       /* coarse sites per level-2 block, x y z t (dividing the coarse lattice) */
+  int32_t nvec;           /* Nv2: level-2 basis columns per chirality, 1..32, at most the rows of a panel */
+  int32_t null_iters;     /* CG steps on A_c w = 0 per start (>= 0)                 */
+  int32_t nu;             /* MR steps on A_c before and after the level-2 correction */
+  double coarse_tol;      /* CG on A_cc: stop at |r| <= coarse_tol |b|              */
+  int32_t coarse_maxiter; /* CG on A_cc: iteration cap (>= 1)                       */
+  int32_t gamma;          /* level-2 cycles per coarse solve: 0 off, 1 V, 2 W (<= 4) */
+} mgdwf_level2_params;
+/* Needs the squared coarse operator (a squared setup or
+ * mgdwf_build_coarse_squared).  W0: nvec starts on the coarse lattice
+ * (device, complex128 [k][Vc][2][Nv], the coarse-vector layout of
+ * mgdwf_restrict; the random numbers are an input).  null_residual (host,
+ * may be NULL): median |A_c w| / |w| of the normalised near-null vectors.
+ * A later setup or coarse build removes the level. */
+mgdwf_status mgdwf_setup_level2(mgdwf_handle h, const mgdwf_level2_params* p, const double* W0,
+                                double* null_residual);
+/* Change nu, coarse_tol, coarse_maxiter and gamma without a new level-2
+ * setup (block and nvec must be the installed ones). */
+mgdwf_status mgdwf_set_level2_params(mgdwf_handle h, const mgdwf_level2_params* p);
+/* The level-2 near-null vectors W (nvec coarse vectors), its orthonormal
+ * basis What (nvec coarse vectors; column (block, chi, j) of What_j) and
+ * A_cc (canonical [B][33][row][col] of 2Nv2 x 2Nv2 blocks, offsets in the
+ * order of the squared coarse operator); device pointers, any may be NULL. */
+mgdwf_status mgdwf_get_level2(mgdwf_handle h, double* W, double* What, double* Acc);
+
+/* ---- setup checkpoints ------------------------------------------------ */
+
+/* The adaptive setup is paid once per gauge field and reused for every
+ * right-hand side (Sec. 2): save it to restart without repeating it.
+ * mgdwf_save_setup writes to `path` (host file, overwritten) the installed
+ * orthonormal basis (Nv canonical FP64 fields), the near-null vectors it was
+ * built from, the block, the coarse operator kind (9-point or squared), the
+ * lattice geometry, M5, m_f, the boundary signs and a 64-bit checksum
+ * (FNV-1a) of the installed FP64 links.  Needs a built coarse operator.
+ * mgdwf_load_setup reads such a file into a handle whose gauge field is set:
+ * MGDWF_ERR_STATE if the geometry, the action or the gauge checksum differ,
+ * MGDWF_ERR_INVALID_ARG for an unreadable or corrupt file; it installs the
+ * basis as saved (no re-orthonormalisation, so the coarse operator and later
+ * solves repeat the saved handle's bit for bit), rebuilds the coarse operator
+ * of the saved kind and clears the solver parameters (set them with
+ * mgdwf_set_mg_params).  A file that fails after its header checks (a
+ * truncated one) leaves the handle with no basis.  Files hold Nv + (near-null count) fields of 12 V5
+ * complex128 each. */
+mgdwf_status mgdwf_save_setup(mgdwf_handle h, const char* path);
+mgdwf_status mgdwf_load_setup(mgdwf_handle h, const char* path);
+
 /* ---- low modes and the coarse space (Sec. 2, Fig. 1) ------------------ */
 
 /* Lowest nev eigenpairs of D^+D, by m Lanczos steps (nev <= m <= 256) on

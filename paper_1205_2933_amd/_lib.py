@@ -46,6 +46,12 @@ class mgdwf_mg_params(ctypes.Structure):
                 ("squared", ctypes.c_int32)]
 
 
+class mgdwf_level2_params(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32 * 4), ("nvec", ctypes.c_int32), ("null_iters", ctypes.c_int32),
+                ("nu", ctypes.c_int32), ("coarse_tol", ctypes.c_double), ("coarse_maxiter", ctypes.c_int32),
+                ("gamma", ctypes.c_int32)]
+
+
 class mgdwf_solve_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int32), ("restart", ctypes.c_int32)]
 
@@ -130,6 +136,12 @@ def _load() -> ctypes.CDLL:
         "mgdwf_apply_vcycle": ([H, P, P, i32], ctypes.c_int),
         "mgdwf_low_modes": ([H, P, i32, i32, ctypes.c_double, P, P, P], ctypes.c_int),
         "mgdwf_coarse_coverage": ([H, P, i32, P], ctypes.c_int),
+        "mgdwf_setup_level2": ([H, ctypes.POINTER(mgdwf_level2_params), P, ctypes.POINTER(ctypes.c_double)],
+                               ctypes.c_int),
+        "mgdwf_set_level2_params": ([H, ctypes.POINTER(mgdwf_level2_params)], ctypes.c_int),
+        "mgdwf_get_level2": ([H, P, P, P], ctypes.c_int),
+        "mgdwf_save_setup": ([H, ctypes.c_char_p], ctypes.c_int),
+        "mgdwf_load_setup": ([H, ctypes.c_char_p], ctypes.c_int),
         "mgdwf_trim": ([H], ctypes.c_int),
         "mgdwf_memory_bytes": ([H], ctypes.c_int64),
         "mgdwf_solve_batch": ([ctypes.POINTER(H), i32, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i32),
@@ -365,6 +377,57 @@ def mgdwf_coarse_coverage(h: Handle, e: torch.Tensor, n: int) -> list:
     fr = (ctypes.c_double * n)()
     _check(h.h, _lib.mgdwf_coarse_coverage(h.h, _dev(e, h.nfine * n, "e"), n, fr))
     return list(fr)
+
+
+def make_level2_params(block, nvec, null_iters=50, nu=2, coarse_tol=0.1, coarse_maxiter=200,
+                       gamma=1) -> mgdwf_level2_params:
+    p = mgdwf_level2_params()
+    p.block[:] = list(block)
+    p.nvec, p.null_iters, p.nu = nvec, null_iters, nu
+    p.coarse_tol, p.coarse_maxiter, p.gamma = coarse_tol, coarse_maxiter, gamma
+    return p
+
+
+def mgdwf_setup_level2(h: Handle, p: mgdwf_level2_params, W0: torch.Tensor) -> float:
+    """Third level under the squared coarse operator; returns the median |A_c w|."""
+    nr = ctypes.c_double()
+    _check(h.h, _lib.mgdwf_setup_level2(h.h, ctypes.byref(p), _dev(W0, h.ncoarse * p.nvec, "W0"), ctypes.byref(nr)))
+    h.level2 = (tuple(p.block), p.nvec)
+    return nr.value
+
+
+def mgdwf_set_level2_params(h: Handle, p: mgdwf_level2_params):
+    _check(h.h, _lib.mgdwf_set_level2_params(h.h, ctypes.byref(p)))
+
+
+def mgdwf_get_level2(h: Handle):
+    """(W, What, Acc) of the installed third level as new device tensors: W and What
+    [nvec2][Tc][Zc][Yc][Xc][2][Nv]; Acc [Tcc][Zcc][Ycc][Xcc][33][2Nv2][2Nv2]."""
+    blk, nv2 = h.level2
+    Lc = tuple(h.L[m] // h.block[m] for m in range(4))
+    Lcc = tuple(Lc[m] // blk[m] for m in range(4))
+    shp = (nv2,) + Lc[::-1] + (2, h.nvec)
+    W = torch.empty(shp, dtype=torch.complex128, device="cuda")
+    Wh = torch.empty_like(W)
+    A = torch.empty(Lcc[::-1] + (33, 2 * nv2, 2 * nv2), dtype=torch.complex128, device="cuda")
+    _check(h.h, _lib.mgdwf_get_level2(h.h, _dev(W, W.numel(), "W"), _dev(Wh, Wh.numel(), "What"),
+                                      _dev(A, A.numel(), "Acc")))
+    return W, Wh, A
+
+
+def mgdwf_save_setup(h: Handle, path):
+    _check(h.h, _lib.mgdwf_save_setup(h.h, str(path).encode()))
+
+
+def mgdwf_load_setup(h: Handle, path):
+    """Install a saved setup; the binding's block and nvec follow the file's
+    header (magic, then int32 L[4], Ls, bc[4], block[4], nvec)."""
+    _check(h.h, _lib.mgdwf_load_setup(h.h, str(path).encode()))
+    import struct
+    with open(path, "rb") as f:
+        head = f.read(8 + 4 * 14)
+    ints = struct.unpack("<14i", head[8:])
+    h.block, h.nvec = tuple(ints[9:13]), ints[13]
 
 
 def mgdwf_trim(h: Handle):

@@ -1,6 +1,8 @@
 // extern "C" entry points (include/mgdwf.h): argument validation, layout
 // conversion at the boundary, and conversion of C++ errors to status codes.
 #include <cmath>
+#include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -112,6 +114,7 @@ namespace mgdwf {
 void install_basis(mgdwf_ctx* c, const int block[4], int nvec) {
   c->have_basis = false;
   c->have_coarse = false;
+  c->have_l2 = false;
   c->cg = make_coarse(c->g, block, nvec);
   if (!orthonormalise_basis(c->V64.as<double2>(), c->g, c->cg, c->st))
     fail(MGDWF_ERR_NUMERIC, "a block panel of the near-null vectors is numerically rank deficient");
@@ -142,6 +145,7 @@ void build_coarse_squared(mgdwf_ctx* c) {
   c->ws.erase("dc_work9");
   c->ws.erase("dc_zwork9");
   c->coarse_kind = 1;
+  c->have_l2 = false;
   c->have_coarse = true;
 }
 
@@ -160,6 +164,7 @@ void build_coarse(mgdwf_ctx* c) {
   // the build workspaces are large; give them back
   c->ws.erase("dc_work9");
   c->coarse_kind = 0;
+  c->have_l2 = false;
   c->have_coarse = true;
 }
 
@@ -559,6 +564,175 @@ mgdwf_status mgdwf_coarse_coverage(mgdwf_handle h, const double* e, int32_t n, d
     double2* a = h->buf<double2>("io_a", h->fine_len() * n);
     pack_fermion_f64(reinterpret_cast<const double2*>(e), a, h->g, n, h->st);
     coarse_coverage(h, a, n, frac);
+  });
+}
+
+mgdwf_status mgdwf_setup_level2(mgdwf_handle h, const mgdwf_level2_params* p, const double* W0,
+                                double* null_residual) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(p && W0, MGDWF_ERR_INVALID_ARG, "null argument");
+    setup_level2(h, *p, reinterpret_cast<const double2*>(W0), null_residual);
+  });
+}
+
+mgdwf_status mgdwf_set_level2_params(mgdwf_handle h, const mgdwf_level2_params* p) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(p != nullptr, MGDWF_ERR_INVALID_ARG, "null argument");
+    need(h->have_l2, MGDWF_ERR_STATE, "no third level installed");
+    for (int m = 0; m < 4; ++m)
+      need(p->block[m] == h->l2p.block[m], MGDWF_ERR_INVALID_ARG, "level-2 block differs from the installed one");
+    need(p->nvec == h->l2p.nvec, MGDWF_ERR_INVALID_ARG, "level-2 nvec differs from the installed one");
+    need(p->nu >= 0 && p->coarse_maxiter >= 1 && p->gamma >= 0 && p->gamma <= 4 && p->coarse_tol >= 0.0,
+         MGDWF_ERR_INVALID_ARG, "bad level-2 parameters");
+    h->clear_graphs();
+    h->l2p = *p;
+  });
+}
+
+mgdwf_status mgdwf_get_level2(mgdwf_handle h, double* W, double* What, double* Acc) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(h->have_l2, MGDWF_ERR_STATE, "no third level installed");
+    const size_t nb = (size_t)h->l2p.nvec * h->coarse_len() * sizeof(double2);
+    if (W) MG_HIP(hipMemcpyAsync(W, h->W2null.p, nb, hipMemcpyDeviceToDevice, h->st));
+    if (What) MG_HIP(hipMemcpyAsync(What, h->W2_64.p, nb, hipMemcpyDeviceToDevice, h->st));
+    if (Acc) sq_canonical(h->Acc64.as<double2>(), reinterpret_cast<double2*>(Acc), h->cg2, h->st);
+    MG_HIP(hipStreamSynchronize(h->st));
+  });
+}
+
+// ---------------------------------------------------------------- setup checkpoints
+namespace {
+
+constexpr char kCkMagic[8] = {'M', 'G', 'D', 'W', 'F', 'C', 'K', '1'};
+
+struct CkHeader {
+  char magic[8];
+  int32_t L[4], Ls, bc[4], block[4], nvec, nnull, coarse_kind, pad;
+  double M5, mf;
+  uint64_t gauge_checksum;
+  int64_t fine_len;
+};
+
+// FNV-1a over the bytes of the installed FP64 links (internal layout)
+uint64_t gauge_checksum(mgdwf_ctx* h) {
+  std::vector<unsigned char> host(h->U64.bytes);
+  MG_HIP(hipMemcpyAsync(host.data(), h->U64.p, host.size(), hipMemcpyDeviceToHost, h->st));
+  MG_HIP(hipStreamSynchronize(h->st));
+  uint64_t x = 1469598103934665603ULL;
+  for (unsigned char c : host) {
+    x ^= c;
+    x *= 1099511628211ULL;
+  }
+  return x;
+}
+
+struct File {
+  FILE* f = nullptr;
+  ~File() { if (f) fclose(f); }
+};
+
+// n fields of the internal FP64 layout, written or read as canonical complex128
+void write_fields(mgdwf_ctx* h, FILE* f, const double2* dev, int n) {
+  const long long nf = h->fine_len();
+  double2* canon = h->buf<double2>("ck_canon", nf);
+  std::vector<double2> host(nf);
+  for (int k = 0; k < n; ++k) {
+    unpack_fermion_f64(dev + k * nf, canon, h->g, 1, h->st);
+    MG_HIP(hipMemcpyAsync(host.data(), canon, nf * sizeof(double2), hipMemcpyDeviceToHost, h->st));
+    MG_HIP(hipStreamSynchronize(h->st));
+    need(fwrite(host.data(), sizeof(double2), nf, f) == (size_t)nf, MGDWF_ERR_INVALID_ARG, "checkpoint write failed");
+  }
+}
+
+void read_fields(mgdwf_ctx* h, FILE* f, double2* dev, int n) {
+  const long long nf = h->fine_len();
+  double2* canon = h->buf<double2>("ck_canon", nf);
+  std::vector<double2> host(nf);
+  for (int k = 0; k < n; ++k) {
+    need(fread(host.data(), sizeof(double2), nf, f) == (size_t)nf, MGDWF_ERR_INVALID_ARG, "checkpoint is truncated");
+    MG_HIP(hipMemcpyAsync(canon, host.data(), nf * sizeof(double2), hipMemcpyHostToDevice, h->st));
+    pack_fermion_f64(canon, dev + k * nf, h->g, 1, h->st);
+    MG_HIP(hipStreamSynchronize(h->st));
+  }
+}
+
+}  // namespace
+
+mgdwf_status mgdwf_save_setup(mgdwf_handle h, const char* path) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(path != nullptr, MGDWF_ERR_INVALID_ARG, "null path");
+    need(h->have_gauge && h->have_basis && h->have_coarse, MGDWF_ERR_STATE,
+         "nothing to save: set the gauge field and run a setup first");
+    CkHeader hd{};
+    std::memcpy(hd.magic, kCkMagic, 8);
+    for (int m = 0; m < 4; ++m) {
+      hd.L[m] = h->g.L[m];
+      hd.bc[m] = h->g.bc[m];
+      hd.block[m] = h->cg.block[m];
+    }
+    hd.Ls = h->g.Ls;
+    hd.nvec = h->cg.Nv;
+    hd.nnull = h->nnull;
+    hd.coarse_kind = h->coarse_kind;
+    hd.M5 = h->M5;
+    hd.mf = h->mf;
+    hd.gauge_checksum = gauge_checksum(h);
+    hd.fine_len = h->fine_len();
+    File fh;
+    fh.f = fopen(path, "wb");
+    need(fh.f != nullptr, MGDWF_ERR_INVALID_ARG, (std::string("cannot open ") + path + " for writing").c_str());
+    need(fwrite(&hd, sizeof hd, 1, fh.f) == 1, MGDWF_ERR_INVALID_ARG, "checkpoint write failed");
+    write_fields(h, fh.f, h->V64.as<double2>(), hd.nvec);
+    if (hd.nnull > 0) write_fields(h, fh.f, h->Vnull.as<double2>(), hd.nnull);
+    need(fflush(fh.f) == 0, MGDWF_ERR_INVALID_ARG, "checkpoint write failed");
+    h->ws.erase("ck_canon");
+    ++h->ws_gen;
+  });
+}
+
+mgdwf_status mgdwf_load_setup(mgdwf_handle h, const char* path) {
+  if (!h) return MGDWF_ERR_INVALID_ARG;
+  return guarded(h, [&] {
+    need(path != nullptr, MGDWF_ERR_INVALID_ARG, "null path");
+    need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
+    File fh;
+    fh.f = fopen(path, "rb");
+    need(fh.f != nullptr, MGDWF_ERR_INVALID_ARG, (std::string("cannot open ") + path).c_str());
+    CkHeader hd{};
+    need(fread(&hd, sizeof hd, 1, fh.f) == 1 && std::memcmp(hd.magic, kCkMagic, 8) == 0, MGDWF_ERR_INVALID_ARG,
+         "not a setup checkpoint");
+    bool same = hd.Ls == h->g.Ls && hd.M5 == h->M5 && hd.mf == h->mf && hd.fine_len == h->fine_len();
+    for (int m = 0; m < 4; ++m) same = same && hd.L[m] == h->g.L[m] && hd.bc[m] == h->g.bc[m];
+    need(same, MGDWF_ERR_STATE, "the checkpoint was taken on another lattice or action");
+    need(hd.gauge_checksum == gauge_checksum(h), MGDWF_ERR_STATE, "the checkpoint was taken on another gauge field");
+    need(hd.nvec >= 1 && hd.nnull >= 0 && (hd.coarse_kind == 0 || hd.coarse_kind == 1), MGDWF_ERR_INVALID_ARG,
+         "corrupt checkpoint header");
+    h->clear_graphs();
+    h->have_basis = h->have_coarse = h->have_params = false;
+    const CoarseGeometry cg = make_coarse(h->g, hd.block, hd.nvec);
+    const long long nf = h->fine_len();
+    h->V64.alloc((size_t)hd.nvec * nf * sizeof(double2));
+    read_fields(h, fh.f, h->V64.as<double2>(), hd.nvec);
+    if (hd.nnull > 0) {
+      h->Vnull.alloc((size_t)hd.nnull * nf * sizeof(double2));
+      read_fields(h, fh.f, h->Vnull.as<double2>(), hd.nnull);
+    }
+    h->nnull = hd.nnull;
+    // the basis as saved (already orthonormal: installed as is, so the
+    // coarse operator and every later solve repeat the saved handle's bitwise)
+    h->cg = cg;
+    h->V32.alloc((size_t)hd.nvec * nf * sizeof(float2));
+    convert<double2, float2>(h->V64.as<double2>(), h->V32.as<float2>(), (long long)hd.nvec * nf, h->st);
+    MG_HIP(hipStreamSynchronize(h->st));
+    h->have_basis = true;
+    if (hd.coarse_kind == 1) build_coarse_squared(h);
+    else build_coarse(h);
+    h->ws.erase("ck_canon");
+    ++h->ws_gen;
   });
 }
 

@@ -26,6 +26,11 @@ struct mgdwf_ctx {
   mgdwf::CoarseStore Dc, DcH;  // coarse operator and its adjoint stencil, all precisions
   mgdwf::CoarseStore Asq;      // squared-operator coarse operator (33 offsets; FP64 and FP32 copies)
   int coarse_kind = 0;         // which coarse operator is built: 0 the 9-point D_c, 1 the squared A_c
+  // third level under the squared coarse operator (mgdwf_setup_level2)
+  bool have_l2 = false;
+  mgdwf_level2_params l2p{};
+  mgdwf::CoarseGeometry cg2{};   // level-2 lattice: Lc = blocks, Vc, Nv = Nv2, n2, block = coarse sites per block
+  mgdwf::DevBuf W2null, W2_64, W2_32, Acc64, Acc32;
 
   mgdwf_mg_params mp{};
   bool have_params = false;

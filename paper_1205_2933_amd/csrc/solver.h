@@ -20,6 +20,8 @@ void low_modes(mgdwf_ctx* c, const double2* v0, int nev, int m, double tol, doub
                double* resid);
 // frac[i] = |P R e_i|^2 / |e_i|^2 for n internal FP64 fields, installed basis
 void coarse_coverage(mgdwf_ctx* c, const double2* e, int n, double* frac);
+// third level under the squared coarse operator (W0: internal = canonical coarse layout)
+void setup_level2(mgdwf_ctx* c, const mgdwf_level2_params& p, const double2* W0, double* null_residual);
 void cgne_solve(mgdwf_ctx* c, double2* b, double2* x, const mgdwf_solve_params& sp, mgdwf_solve_report* rep);
 
 }  // namespace mgdwf

@@ -352,6 +352,18 @@ inline void sq_op(mgdwf_ctx* c, const float2* x, float2* y, int nrhs) {
   c->coarse_applies += 1;
 }
 
+inline void l2_op(mgdwf_ctx* c, const double2* x, double2* y, int nrhs) {
+  sq_apply64(c->Acc64.as<double2>(), x, y, c->cg2, nrhs, c->st);
+  c->coarse_applies += 1;
+}
+inline void l2_op(mgdwf_ctx* c, const float2* x, float2* y, int nrhs) {
+  sq_apply32(c->Acc32.as<float2>(), x, y, c->cg2, nrhs, c->st);
+  c->coarse_applies += 1;
+}
+template <class F2> const F2* l2_basis(mgdwf_ctx* c);
+template <> const double2* l2_basis<double2>(mgdwf_ctx* c) { return c->W2_64.as<double2>(); }
+template <> const float2* l2_basis<float2>(mgdwf_ctx* c) { return c->W2_32.as<float2>(); }
+
 template <class F2>
 struct TwoLevelSq {
   mgdwf_ctx* c;
@@ -399,8 +411,114 @@ struct TwoLevelSq {
     }
   }
 
-  // CG on A_c x = b from x = 0, to |r| <= tol |b| tested every 8 iterations, or maxiter
+  // CG from x = 0 on the Hermitian operator op (vectors of n per RHS), to
+  // |r| <= tol |b| tested every 8 iterations, or maxiter; r, p, q: workspaces
+  template <class Op>
+  void cg(Op op, const F2* b, F2* x, long long n, F2* r, F2* pv, F2* qv, double tol, int maxiter) {
+    copy(c, b, r, n * nrhs);
+    copy(c, b, pv, n * nrhs);
+    norm_into<F2>(c, r, nullptr, n, nrhs, S_CRR0);
+    norm_into<F2>(c, r, nullptr, n, nrhs, S_CRR_A);
+    int cur = S_CRR_A, nxt = S_CRR_B;
+    const double tol2 = tol * tol;
+    double* part = c->buf<double>("vpart", (size_t)VEC_BLOCKS * nrhs * (2 * 16 + 3));
+    for (int it = 0; it < maxiter;) {
+      op(pv, qv);                                                           // q = A p
+      norm_into<F2>(c, pv, qv, n, nrhs, S_CPQ);                             // <p, q> at S_CPQ + 1
+      mr_update<F2>(x, r, pv, qv, n, nrhs, sl, cur, S_CPQ + 1, it == 0, part, c->st);  // x += a p, r -= a q
+      finalize_rhs(part, vec_blocks(n), 1, sl, nxt, nrhs, c->st);           // |r|^2
+      cg_dir<F2>(pv, r, n, nrhs, sl, nxt, cur, nullptr, c->st);             // p = r + beta p
+      std::swap(cur, nxt);
+      ++it;
+      if (it % 8 == 0 && it < maxiter) {
+        std::vector<double> h = read_slots(c, nrhs);
+        bool done = true;
+        for (int rr = 0; rr < nrhs; ++rr)
+          if (!(h[rr * NSLOT + cur] <= tol2 * h[rr * NSLOT + S_CRR0])) done = false;
+        if (done) break;
+      }
+    }
+  }
+
+  // ---- third level (a level-2 basis is installed and gamma > 0): the coarse
+  // solve is gamma sweeps of e <- e + K2(b - A_c e), K2 the level-2 cycle
+  F2 *e2 = nullptr, *f2 = nullptr, *s2a = nullptr, *s2b = nullptr, *s2r = nullptr, *s2q = nullptr;
+  F2 *c3b = nullptr, *c3x = nullptr, *c3r = nullptr, *c3p = nullptr, *c3q = nullptr;
+  long long n3 = 0;
+
+  void l2_buffers() {
+    if (e2) return;
+    const std::string tg = Prec<F2>::tag;
+    n3 = (long long)c->cg2.Vc * c->cg2.n2;
+    e2 = c->buf<F2>("l2_e" + tg, nc * nrhs);
+    f2 = c->buf<F2>("l2_f" + tg, nc * nrhs);
+    s2a = c->buf<F2>("l2_sa" + tg, nc * nrhs);
+    s2b = c->buf<F2>("l2_sb" + tg, nc * nrhs);
+    s2r = c->buf<F2>("l2_sr" + tg, nc * nrhs);
+    s2q = c->buf<F2>("l2_sq" + tg, nc * nrhs);
+    c3b = c->buf<F2>("l3_b" + tg, n3 * nrhs);
+    c3x = c->buf<F2>("l3_x" + tg, n3 * nrhs);
+    c3r = c->buf<F2>("l3_r" + tg, n3 * nrhs);
+    c3p = c->buf<F2>("l3_p" + tg, n3 * nrhs);
+    c3q = c->buf<F2>("l3_q" + tg, n3 * nrhs);
+  }
+
+  // nu minimal-residual steps on A_c e = f along the residual (e from 0 or
+  // added to); the last residual goes to rout unless it is null
+  void smooth2(const F2* f, F2* e, F2* rout, int nu, bool add) {
+    const F2* rin = f;
+    for (int i = 0; i < nu; ++i) {
+      sq_op(c, rin, s2q, nrhs);                                             // q = A_c r
+      norm_into<F2>(c, s2q, rin, nc, nrhs, S_SQ);                           // |q|^2, <q, r>
+      F2* rnew = (i + 1 == nu && rout) ? rout : (rin == s2a ? s2b : s2a);
+      mrh_update<F2>(e, rnew, rin, s2q, nc, nrhs, sl, S_SQ + 1, S_SQ, i == 0 && !add, c->st);
+      rin = rnew;
+    }
+  }
+
+  // e = K2 f: smoothing on A_c, R2, CG on A_cc, P2, residual, smoothing
+  void k2(const F2* f, F2* e) {
+    const mgdwf_level2_params& q = c->l2p;
+    const F2* W = l2_basis<F2>(c);
+    const F2* r1 = f;
+    if (q.nu > 0) {
+      smooth2(f, e, s2r, q.nu, false);
+      r1 = s2r;
+    } else {
+      zero<F2>(e, nc * nrhs, c->st);
+    }
+    restrict2<F2>(W, r1, c3b, c->cg, c->cg2, nrhs, c->st);
+    cg([&](const F2* a, F2* b) { l2_op(c, a, b, nrhs); }, c3b, c3x, n3, c3r, c3p, c3q, q.coarse_tol,
+       q.coarse_maxiter);
+    prolong2<F2>(W, c3x, e, true, c->cg, c->cg2, nrhs, c->st);
+    if (q.nu > 0) {
+      sq_op(c, e, s2q, nrhs);
+      sub_into<F2>(s2r, f, s2q, nc * nrhs, c->st);                           // f - A_c e
+      smooth2(s2r, e, nullptr, q.nu, true);
+    }
+  }
+
+  void coarse_solve3(const F2* b, F2* x) {
+    l2_buffers();
+    for (int g = 0; g < c->l2p.gamma; ++g) {
+      if (g == 0) {
+        k2(b, x);
+      } else {
+        sq_op(c, x, s2q, nrhs);
+        sub_into<F2>(f2, b, s2q, nc * nrhs, c->st);                          // b - A_c x
+        k2(f2, e2);
+        add_to<F2, F2>(x, e2, nc * nrhs, c->st);
+      }
+    }
+  }
+
+  // CG on A_c x = b from x = 0, to |r| <= tol |b| tested every 8 iterations, or
+  // maxiter; with a third level, the level-2 cycles instead
   void coarse_solve(const F2* b, F2* x) {
+    if (c->have_l2 && c->l2p.gamma > 0) {
+      coarse_solve3(b, x);
+      return;
+    }
     copy(c, b, cr, nc * nrhs);
     copy(c, b, cp, nc * nrhs);
     norm_into<F2>(c, cr, nullptr, nc, nrhs, S_CRR0);
@@ -814,6 +932,98 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
 }
 
 // CGNE control (paper Sec. 3): CG on D D^+ y = b, x = D^+ y, FP64.
+// Third level under the squared coarse operator: near-null vectors of A_c by
+// CG on A_c w = 0 (all starts at once), normalised; their chirality-split
+// block basis; A_cc = R2 A_c P2.
+static void require(bool cond, mgdwf_status code, const char* msg) {
+  if (!cond) fail(code, msg);
+}
+
+void setup_level2(mgdwf_ctx* c, const mgdwf_level2_params& p, const double2* W0, double* null_residual) {
+  require(c->have_coarse && c->coarse_kind == 1, MGDWF_ERR_STATE,
+       "the third level needs the squared coarse operator (a squared setup or mgdwf_build_coarse_squared)");
+  const CoarseGeometry& cg = c->cg;
+  CoarseGeometry c2{};
+  c2.bvol = 1;
+  c2.Vc = 1;
+  for (int m = 0; m < 4; ++m) {
+    require(p.block[m] >= 1 && cg.Lc[m] % p.block[m] == 0, MGDWF_ERR_INVALID_ARG,
+         "level-2 blocks must divide the coarse lattice");
+    c2.block[m] = p.block[m];
+    c2.Lc[m] = cg.Lc[m] / p.block[m];
+    c2.bvol *= p.block[m];
+    c2.Vc *= c2.Lc[m];
+  }
+  require(p.nvec >= 1 && p.nvec <= 32 && p.nvec <= c2.bvol * cg.Nv, MGDWF_ERR_INVALID_ARG,
+       "level-2 nvec must be 1..32 and at most the rows of a block panel");
+  require(p.null_iters >= 0 && p.nu >= 0 && p.coarse_maxiter >= 1 && p.gamma >= 0 && p.gamma <= 4 &&
+           p.coarse_tol >= 0.0,
+       MGDWF_ERR_INVALID_ARG, "bad level-2 parameters");
+  c2.Nv = p.nvec;
+  c2.n2 = 2 * p.nvec;
+  c->have_l2 = false;
+  c->clear_graphs();
+  const int n = p.nvec;
+  const long long nc = c->coarse_len();
+  double* sl = c->buf<double>("slots", (size_t)n * NSLOT);
+  double* vpart = c->buf<double>("vpart", (size_t)VEC_BLOCKS * n * (2 * 16 + 3));
+  c->W2null.alloc((size_t)n * nc * sizeof(double2));
+  double2* w = c->W2null.as<double2>();
+  MG_HIP(hipMemcpyAsync(w, W0, (size_t)n * nc * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
+  double2* r = c->buf<double2>("l2s_r", n * nc);
+  double2* pv = c->buf<double2>("l2s_p", n * nc);
+  double2* q = c->buf<double2>("l2s_q", n * nc);
+  const double2* Ac = c->Asq.m64.as<double2>();
+  if (p.null_iters > 0) {  // CG on A_c w = 0 from w: r = -A_c w, p = r
+    sq_apply64(Ac, w, q, cg, n, c->st);
+    zero<double2>(r, n * nc, c->st);
+    sub_into<double2>(r, r, q, n * nc, c->st);
+    copy(c, r, pv, n * nc);
+    norm_into<double2>(c, r, nullptr, nc, n, S_CRR_A);
+    int cur = S_CRR_A, nxt = S_CRR_B;
+    for (int it = 0; it < p.null_iters; ++it) {
+      sq_apply64(Ac, pv, q, cg, n, c->st);                                   // q = A_c p
+      norm_into<double2>(c, pv, q, nc, n, S_CPQ);                            // <p, q>
+      mr_update<double2>(w, r, pv, q, nc, n, sl, cur, S_CPQ + 1, false, vpart, c->st);  // w += a p, r -= a q
+      finalize_rhs(vpart, vec_blocks(nc), 1, sl, nxt, n, c->st);
+      cg_dir<double2>(pv, r, nc, n, sl, nxt, cur, nullptr, c->st);
+      std::swap(cur, nxt);
+    }
+    c->coarse_applies += p.null_iters + 1;
+  }
+  norm_into<double2>(c, w, nullptr, nc, n, S_TMP);
+  scale_by_rsqrt_slot<double2>(w, w, nc, n, sl, S_TMP, c->st);
+  if (null_residual) {  // median |A_c w| for the unit vectors
+    sq_apply64(Ac, w, q, cg, n, c->st);
+    norm_into<double2>(c, q, nullptr, nc, n, S_TMP);
+    std::vector<double> h = read_slots(c, n);
+    std::vector<double> v(n);
+    for (int k = 0; k < n; ++k) v[k] = std::sqrt(h[k * NSLOT + S_TMP]);
+    std::sort(v.begin(), v.end());
+    *null_residual = n % 2 ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
+  }
+  c->W2_64.alloc((size_t)n * nc * sizeof(double2));
+  copy(c, w, c->W2_64.as<double2>(), n * nc);
+  if (!orthonormalise_level2(c->W2_64.as<double2>(), cg, c2, c->buf<int>("l2s_err", 1), c->st))
+    fail(MGDWF_ERR_NUMERIC, "a level-2 block panel of the near-null vectors is numerically rank deficient");
+  c->W2_32.alloc((size_t)n * nc * sizeof(float2));
+  convert<double2, float2>(c->W2_64.as<double2>(), c->W2_32.as<float2>(), n * nc, c->st);
+  c->Acc64.alloc(sq_coarse_entries(c2) * sizeof(double2));
+  double2* probes = c->buf<double2>("l2s_probe", (size_t)c2.n2 * nc);
+  double2* applied = c->buf<double2>("l2s_applied", (size_t)c2.n2 * nc);
+  double2* rr = c->buf<double2>("l2s_rr", (size_t)c2.n2 * c2.Vc * c2.n2);
+  build_level2_op(Ac, c->W2_64.as<double2>(), c->Acc64.as<double2>(), probes, applied, rr, cg, c2, c->st);
+  c->coarse_applies += c2.Vc;
+  c->Acc32.alloc(sq_coarse_entries(c2) * sizeof(float2));
+  sq_to_f32(c->Acc64.as<double2>(), c->Acc32.as<float2>(), c2, c->st);
+  MG_HIP(hipStreamSynchronize(c->st));
+  for (const char* nm : {"l2s_r", "l2s_p", "l2s_q", "l2s_probe", "l2s_applied", "l2s_rr"}) c->ws.erase(nm);
+  ++c->ws_gen;
+  c->cg2 = c2;
+  c->l2p = p;
+  c->have_l2 = true;
+}
+
 void cgne_solve(mgdwf_ctx* c, double2* b, double2* x, const mgdwf_solve_params& sp, mgdwf_solve_report* rep) {
   const long long nf = c->fine_len();
   const int nrhs = 1;

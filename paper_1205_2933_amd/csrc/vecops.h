@@ -112,4 +112,23 @@ void sq_canonical(const double2* Ac, double2* out, const CoarseGeometry& cg, hip
 void sq_apply64(const double2* Ac, const double2* x, double2* y, const CoarseGeometry& cg, int nrhs, hipStream_t st);
 void sq_apply32(const float2* Ac32, const float2* x, float2* y, const CoarseGeometry& cg, int nrhs, hipStream_t st);
 
+// level2.hip: a third level under the squared method.  cg: the coarse lattice
+// (level 1), c2: the level-2 lattice (Lc = blocks, Vc = blocks, Nv = Nv2,
+// block = coarse sites per block).  W: Nv2 coarse vectors [j][Vc][2][Nv].
+bool orthonormalise_level2(double2* W, const CoarseGeometry& cg, const CoarseGeometry& c2, int* err_dev,
+                           hipStream_t st);
+template <class F2>
+void restrict2(const F2* W, const F2* in, F2* out, const CoarseGeometry& cg, const CoarseGeometry& c2, int nrhs,
+               hipStream_t st);
+template <class F2>
+void prolong2(const F2* W, const F2* cc, F2* out, bool acc, const CoarseGeometry& cg, const CoarseGeometry& c2,
+              int nrhs, hipStream_t st);
+// out = a - b
+template <class F2>
+void sub_into(F2* out, const F2* a, const F2* b, long long n, hipStream_t st);
+// A_cc = R2 A_c P2 into the 33-offset form (Vcc x 33 column-major 2Nv2 blocks);
+// probes and applied: 2 Nv2 coarse vectors each, rr: 2 Nv2 level-2 vectors
+void build_level2_op(const double2* Ac, const double2* W, double2* Acc, double2* probes, double2* applied,
+                     double2* rr, const CoarseGeometry& cg, const CoarseGeometry& c2, hipStream_t st);
+
 }  // namespace mgdwf
