@@ -248,6 +248,8 @@ def squared_leg(mg, U_dev, B_main, log):
     r64 = mg.mgdwf_solve(h, B_main[0].contiguous(), x1, nrhs=1, tol=1e-10, max_outer=400, restart=8)[0]
     torch.cuda.synchronize()
     s64 = time.perf_counter() - t
+    del x1
+    three = three_level_leg(mg, h, B_main, log)
     h.close()
     torch.cuda.empty_cache()
     r0 = reps[0]
@@ -258,8 +260,55 @@ def squared_leg(mg, U_dev, B_main, log):
            "mixed_max_true_relres": max(r["true_relres"] for r in reps),
            "mixed_phases_s": r0["phase_seconds"],
            "fp64_s_per_rhs": s64, "fp64_outer_iters": r64["outer_iters"], "fp64_fine_applies": r64["fine_applies"],
-           "note": "coarse operator P^+ D^+D P (33-point stencil), FP32 coarse level, coarse solve as launched kernels"}
+           "note": "coarse operator P^+ D^+D P (33-point stencil), FP32 coarse level, coarse solve as launched kernels",
+           "three_level": three}
     log(f"squared-operator multigrid {out}")
+    return out
+
+
+L2_BLOCK, L2_NVEC, L2_NULL, L2_NU, L2_CTOL, L2_CMAX = (2, 2, 2, 2), 16, 50, 2, 0.1, 100
+
+
+def three_level_leg(mg, h, B_main, log):
+    """A third level under the squared multigrid of the squared leg (paper
+    Sec. 2, recursion): 16 near-null vectors of A_c (50 CG steps from random
+    coarse starts, seed 22), level-2 blocks of 2^4 coarse sites (a 2x2x2x4
+    level-2 lattice, 32 dof per site), 2 + 2 MR steps on A_c, CG on A_cc to 0.1;
+    the squared V-cycle's coarse solve (CG on A_c to 0.3) becomes one (V) or
+    two (W) level-2 cycles.  12-RHS mixed-precision steps, FP32 levels."""
+    import torch
+
+    from inputs import random_coarse_starts
+
+    Lc = tuple(L_MAIN[m] // BLOCK[m] for m in range(4))
+    W0 = torch.from_numpy(random_coarse_starts(Lc, SQ_NVEC, L2_NVEC, 22)).cuda()
+    out = {"block": L2_BLOCK, "nvec": L2_NVEC, "null_iters": L2_NULL, "nu": L2_NU, "coarse_tol": L2_CTOL,
+           "coarse_maxiter": L2_CMAX}
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out["null_residual"] = mg.mgdwf_setup_level2(
+        h, mg.make_level2_params(L2_BLOCK, L2_NVEC, L2_NULL, L2_NU, L2_CTOL, L2_CMAX, gamma=1), W0)
+    torch.cuda.synchronize()
+    out["setup_s"] = time.perf_counter() - t
+    del W0
+    mg.mgdwf_set_mg_params(h, sq_params(mg, "f32", "f32"))
+    for gamma, name in ((1, "v_cycle"), (2, "w_cycle")):
+        mg.mgdwf_set_level2_params(h, mg.make_level2_params(L2_BLOCK, L2_NVEC, L2_NULL, L2_NU, L2_CTOL, L2_CMAX,
+                                                            gamma=gamma))
+        X = torch.zeros_like(B_main)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = mg.mgdwf_solve(h, B_main, X, nrhs=12, tol=1e-10, max_outer=400, restart=8, allow_not_converged=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        del X
+        r0 = reps[0]
+        out[name] = {"s_per_rhs": el / 12, "outer_iters": r0["outer_iters"], "fine_applies_per_rhs": r0["fine_applies"],
+                     "coarse_applies_per_rhs": r0["coarse_applies"], "coarse_phase_s": r0["phase_seconds"][1],
+                     "max_true_relres": max(r["true_relres"] for r in reps)}
+        log(f"three-level {name}: {out[name]}")
+    mg.mgdwf_set_level2_params(h, mg.make_level2_params(L2_BLOCK, L2_NVEC, L2_NULL, L2_NU, L2_CTOL, L2_CMAX,
+                                                        gamma=0))
     return out
 
 
