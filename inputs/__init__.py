@@ -11,6 +11,8 @@ Canonical interchange layout (C order, complex128):
   x, y, z, t.
 * fermion field: shape ``(Lt, Lz, Ly, Lx, Ls, 4, 3)`` = (site, s, spin, colour).
 * gauge field: shape ``(Lt, Lz, Ly, Lx, 4, 3, 3)`` = U_mu(x)[a, b].
+
+The two-dimensional U(1) problem has its own generators (``u1_2d``).
 """
 
 from .lattice import (  # noqa: F401
@@ -26,4 +28,13 @@ from .lattice import (  # noqa: F401
     random_starts,
     random_coarse_starts,
     random_gauge_transform,
+)
+from .u1_2d import (  # noqa: F401
+    fermion2d_shape,
+    plaquette_angles,
+    quenched_u1_2d,
+    gaussian_fermion2d,
+    point_sources2d,
+    random_starts2d,
+    random_u1_transform,
 )

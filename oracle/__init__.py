@@ -31,7 +31,10 @@ Algorithms for Domain-Wall Fermions", Lattice 2011):
 * ``lowmodes``  -- lowest eigenpairs of D^+D from a dense eigensolver and the
                    fraction |P R e|^2 / |e|^2 of a field in the coarse space
                    (Sec. 2, Fig. 1 right).
-* ``dense``     -- explicit matrices on tiny lattices (pins only).
+* ``u1_2d``     -- the paper's 2D U(1) test problem (Sec. 3, Fig. 2): the 2D
+                   domain-wall operator, its chirality-split block basis and
+                   transfer, A_c = P^+ D^+D P as a 9-offset stencil, the
+                   squared V-cycle and setup.
 * ``nullnet``   -- forward/backward of the gauge-covariant proposal network.
 
 Every function works in complex128.
