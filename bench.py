@@ -421,6 +421,66 @@ def mass_leg(mg, U_dev, B_main, log):
     return out
 
 
+L_U1, LS_U1, BETA_U1, SEED_U1, M5_U1 = (20, 20), 8, 4.0, 7, 1.0
+
+
+def u1_2d_leg(mg, log):
+    """The paper's 2D U(1) test (Sec. 3, Fig. 2): 20^2 x 8, a quenched U(1)
+    field (Wilson action, beta = 4, Metropolis, seed 7), 16 near-null vectors,
+    blocks 4^2 x 8, m_f = 0.01 .. 0.10.  Per mass: the squared-operator
+    multigrid (setup: CG on D^+D v = 0, 100 iterations; V-cycle: 4 + 4 MR
+    steps, coarse CG to 0.1) preconditioning flexible GCR, against CG on the
+    normal equations, both in FP64 on the two spin point sources lifted to the
+    walls, to |b - D x| / |b| < 1e-10.  Cost in applications of the squared
+    fine operator D^+D (half the D and D^+ applications), and the coarse
+    operator applications per V-cycle (the coarse level's critical slowing,
+    Fig. 2 right)."""
+    import torch
+
+    from inputs import point_sources2d, quenched_u1_2d, random_starts2d
+
+    U = torch.from_numpy(quenched_u1_2d(L_U1, BETA_U1, SEED_U1)).cuda()
+    b = torch.from_numpy(point_sources2d(L_U1, LS_U1)).cuda()
+    starts = torch.from_numpy(random_starts2d(L_U1, LS_U1, 16, 21)).cuda()
+    rows = []
+    for k in range(1, 11):
+        mf = 0.01 * k
+        h = mg.Handle2D(L_U1, LS_U1, M5_U1, mf)
+        mg.mgdwf_set_gauge(h, U)
+        p = mg.make_mg_params((4, 4, 1, 1), 16, sweeps=1, sweep0_iters=100, nu_pre=4, nu_post=4, coarse_tol=0.1,
+                              coarse_maxiter=500, fine_prec="f64", coarse_prec="f64", squared=True)
+        t = time.perf_counter()
+        srep = mg.mgdwf_setup(h, p, starts)
+        setup_s = time.perf_counter() - t
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = mg.mgdwf_solve(h, b, x, nrhs=2, tol=1e-10, max_outer=300, restart=8, allow_not_converged=True)
+        torch.cuda.synchronize()
+        mg_s = time.perf_counter() - t
+        cg_iters, cg_applies, cg_s = [], [], 0.0
+        for r_ in range(2):
+            y = torch.zeros_like(b[r_])
+            t = time.perf_counter()
+            c = mg.mgdwf_cgne(h, b[r_].contiguous(), y, tol=1e-10, max_iter=200000)
+            torch.cuda.synchronize()
+            cg_s += time.perf_counter() - t
+            cg_iters.append(c["outer_iters"])
+            cg_applies.append(c["fine_applies"])
+        outer = r[0]["outer_iters"]
+        row = {"m_f": round(mf, 2), "null_residual": srep["null_residual"][0], "setup_s": setup_s,
+               "mg_outer_iters": outer, "mg_squared_applies_per_rhs": r[0]["fine_applies"] / 2.0,
+               "mg_coarse_applies_per_vcycle": r[0]["coarse_applies"] / max(outer, 1),
+               "mg_true_relres": max(q["true_relres"] for q in r), "mg_s_2rhs": mg_s,
+               "cg_iters": cg_iters, "cg_squared_applies_per_rhs": sum(cg_applies) / 4.0, "cg_s_2rhs": cg_s}
+        row["cg_over_mg_squared_applies"] = row["cg_squared_applies_per_rhs"] / row["mg_squared_applies_per_rhs"]
+        log(f"2D U(1) {row}")
+        rows.append(row)
+        h.close()
+    return {"lattice": "20^2 x 8", "beta": BETA_U1, "seed": SEED_U1, "M5": M5_U1, "nvec": 16, "block": [4, 4],
+            "rows": rows}
+
+
 N_TRAIN, N_EVAL = 200, 8
 
 
@@ -592,6 +652,7 @@ def main():
     ap.add_argument("--no-mass-scan", action="store_true", help="skip the iteration count versus m_f")
     ap.add_argument("--no-squared", action="store_true", help="skip the squared-operator multigrid step")
     ap.add_argument("--no-low-modes", action="store_true", help="skip the low-mode coverage on the 4^4 lattice")
+    ap.add_argument("--no-u1", action="store_true", help="skip the 2D U(1) test problem")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -806,6 +867,8 @@ def main():
         out["squared_operator_mg"] = squared_leg(mg, U_dev, B, log)
     if not args.no_low_modes:
         out["low_mode_coverage"] = low_modes_leg(mg, log)
+    if not args.no_u1:
+        out["u1_2d"] = u1_2d_leg(mg, log)
     if not args.no_mass_scan:
         mg.mgdwf_trim(h)
         torch.cuda.empty_cache()

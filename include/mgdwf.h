@@ -76,6 +76,34 @@ typedef struct {
   int32_t bc[4];
 } mgdwf_action;
 
+/* The two-dimensional U(1) test problem of Sec. 3 (Fig. 2): the same Shamir
+ * form on a 2D lattice with U(1) links,
+ *   (D psi)(x,s) = (3 - M5) psi(x,s)
+ *       - 1/2 sum_{mu=x,y} [(1 - g_mu) U_mu(x) psi(x+mu,s) + (1 + g_mu) conj(U_mu(x-mu)) psi(x-mu,s)]
+ *       - P_- psi(x,s+1) - P_+ psi(x,s-1),  walls closed by +m_f,
+ * g_x = sigma_1, g_y = sigma_2, g5 = sigma_3 (P_+ keeps spin 0).  Canonical
+ * arrays of a 2D handle (complex128, C order):
+ *   2D site     x2 = y*Lx + x
+ *   fermion     (x2*Ls + s)*2 + spin                    (2*Ls*Lx*Ly complex)
+ *   gauge       x2*2 + mu = U_mu(x), |U| = 1            (2*Lx*Ly complex)
+ *   coarse vec  (X2*2 + chi)*Nv + k, chi = spin; blocks are {bx, by, 1, 1}
+ *   coarse op   the squared form of mgdwf_get_coarse_op with LZ = LT = 1
+ *               (only the offsets self, +-x, +-y and the four xy diagonals
+ *               are nonzero).
+ * A 2D handle runs the squared-operator multigrid (squared = 1, which the
+ * paper used for this test) and every call of the fine level, the transfer,
+ * the coarse operator, the solvers, the third level and the checkpoints;
+ * the 9-point coarse operator, low_modes, tune, set_tiling, time_kernel and
+ * the network calls return MGDWF_ERR_INVALID_ARG for it.  Every extent must
+ * be >= 2. */
+typedef struct {
+  int32_t L[2];
+  int32_t Ls;
+  double M5;
+  double mf;
+  int32_t bc[2];
+} mgdwf_action2d;
+
 /* Two-level multigrid parameters (Sec. 2). */
 typedef struct {
   int32_t block[4];       /* 4D block; each block spans all of Ls (Sec. 2)       */
@@ -160,6 +188,8 @@ typedef struct {
 /* Create a handle for one lattice and action, bound to `hip_stream` (a
  * hipStream_t, NULL for the default stream) on the current device. */
 mgdwf_status mgdwf_create(const mgdwf_action* action, void* hip_stream, mgdwf_handle* out);
+/* A handle for the 2D U(1) problem (Sec. 3, Fig. 2; layouts above). */
+mgdwf_status mgdwf_create_2d(const mgdwf_action2d* action, void* hip_stream, mgdwf_handle* out);
 mgdwf_status mgdwf_destroy(mgdwf_handle h);
 /* Message of the last failure on h, or of the last failed create if h is NULL. */
 const char* mgdwf_last_error(mgdwf_handle h);

@@ -20,7 +20,7 @@ min(1, exp(-dS)), dS the change of its two plaquettes.  Per set the draws
 are the proposals for the whole (Ly, Lx) array of that direction, then the
 acceptance uniforms for the same array, both from
 ``numpy.random.Generator(PCG64(seed))``; entries outside the set are unused.
-Both extents must be even.
+Both extents must be even (with sweeps = 0, the random start, any extents).
 """
 
 from __future__ import annotations
@@ -46,7 +46,7 @@ def quenched_u1_2d(L: Sequence[int], beta: float, seed: int, sweeps: int = 500,
                    step: float = 1.5) -> np.ndarray:
     """A U(1) gauge field after ``sweeps`` Metropolis sweeps of the Wilson action."""
     Lx, Ly = L
-    if Lx % 2 or Ly % 2:
+    if sweeps > 0 and (Lx % 2 or Ly % 2):
         raise ValueError("both extents must be even")
     rng = np.random.Generator(np.random.PCG64(seed))
     theta = rng.uniform(-np.pi, np.pi, size=(Ly, Lx, 2))

@@ -6,4 +6,4 @@ package fails loudly if the library has not been built.
 """
 
 from ._lib import *  # noqa: F401,F403
-from ._lib import Handle, MgdwfError, make_mg_params, exported_symbols  # noqa: F401
+from ._lib import Handle, Handle2D, MgdwfError, make_mg_params, exported_symbols  # noqa: F401

@@ -37,6 +37,11 @@ class mgdwf_action(ctypes.Structure):
                 ("mf", ctypes.c_double), ("bc", ctypes.c_int32 * 4)]
 
 
+class mgdwf_action2d(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 2), ("Ls", ctypes.c_int32), ("M5", ctypes.c_double),
+                ("mf", ctypes.c_double), ("bc", ctypes.c_int32 * 2)]
+
+
 class mgdwf_mg_params(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32 * 4), ("nvec", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("sweep0_iters", ctypes.c_int32), ("sweep_iters", ctypes.c_int32),
@@ -114,6 +119,7 @@ def _load() -> ctypes.CDLL:
     i32 = ctypes.c_int32
     sig = {
         "mgdwf_create": ([ctypes.POINTER(mgdwf_action), P, ctypes.POINTER(H)], ctypes.c_int),
+        "mgdwf_create_2d": ([ctypes.POINTER(mgdwf_action2d), P, ctypes.POINTER(H)], ctypes.c_int),
         "mgdwf_destroy": ([H], ctypes.c_int),
         "mgdwf_last_error": ([H], ctypes.c_char_p),
         "mgdwf_set_gauge": ([H, P], ctypes.c_int),
@@ -216,6 +222,8 @@ class Handle:
         self.L, self.Ls, self.M5, self.mf, self.bc = tuple(L), Ls, M5, mf, tuple(bc)
         self.V4 = int(L[0] * L[1] * L[2] * L[3])
         self.nfine = 12 * self.V4 * Ls
+        self.ngauge = 36 * self.V4
+        self.site_shape = (Ls, 4, 3)  # per-site axes of a canonical fermion field
         self.block = None
         self.nvec = None
 
@@ -231,6 +239,10 @@ class Handle:
             pass
 
     @property
+    def fermion_shape(self):
+        return tuple(self.L[::-1]) + self.site_shape
+
+    @property
     def ncoarse(self):
         Vc = 1
         for m in range(4):
@@ -238,10 +250,42 @@ class Handle:
         return Vc * 2 * self.nvec
 
 
+class Handle2D(Handle):
+    """A handle of the 2D U(1) problem: L = (Lx, Ly); internally the extents
+    are (Lx, Ly, 1, 1), so blocks are given as (bx, by, 1, 1)."""
+
+    def __init__(self, L, Ls, M5, mf, bc=(1, 1), stream=None):
+        a = mgdwf_action2d()
+        a.L[:] = list(L)
+        a.Ls, a.M5, a.mf = Ls, M5, mf
+        a.bc[:] = list(bc)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(None, _lib.mgdwf_create_2d(ctypes.byref(a), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.L, self.Ls, self.M5, self.mf = (L[0], L[1], 1, 1), Ls, M5, mf
+        self.bc = (bc[0], bc[1], 1, 1)
+        self.V4 = int(L[0] * L[1])
+        self.nfine = 2 * self.V4 * Ls
+        self.ngauge = 2 * self.V4
+        self.site_shape = (Ls, 2)
+        self.block = None
+        self.nvec = None
+
+    @property
+    def fermion_shape(self):
+        return (self.L[1], self.L[0]) + self.site_shape
+
+
 # ---- thin wrappers, one per C entry point ---------------------------------
 
 def mgdwf_create(L, Ls, M5, mf, bc=(1, 1, 1, 1), stream=None) -> Handle:
     return Handle(L, Ls, M5, mf, bc, stream)
+
+
+def mgdwf_create_2d(L, Ls, M5, mf, bc=(1, 1), stream=None) -> Handle2D:
+    return Handle2D(L, Ls, M5, mf, bc, stream)
 
 
 def mgdwf_destroy(h: Handle):
@@ -254,7 +298,7 @@ def mgdwf_last_error(h: Handle | None) -> str:
 
 
 def mgdwf_set_gauge(h: Handle, U: torch.Tensor):
-    _check(h.h, _lib.mgdwf_set_gauge(h.h, _dev(U, 36 * h.V4, "U")))
+    _check(h.h, _lib.mgdwf_set_gauge(h.h, _dev(U, h.ngauge, "U")))
 
 
 def mgdwf_apply_dwf(h: Handle, inp: torch.Tensor, out: torch.Tensor, dagger=False, prec="f64", nrhs=1):
@@ -272,7 +316,7 @@ def mgdwf_get_nullvecs(h: Handle) -> torch.Tensor:
     """The near-null vectors behind the installed basis, as a new device tensor."""
     n = ctypes.c_int32()
     _check(h.h, _lib.mgdwf_get_nullvecs(h.h, None, ctypes.byref(n)))
-    shape = (n.value,) + tuple(h.L[::-1]) + (h.Ls, 4, 3)
+    shape = (n.value,) + h.fermion_shape
     V = torch.empty(shape, dtype=torch.complex128, device="cuda")
     _check(h.h, _lib.mgdwf_get_nullvecs(h.h, _dev(V, h.nfine * n.value, "V"), ctypes.byref(n)))
     return V
@@ -366,7 +410,7 @@ def mgdwf_low_modes(h: Handle, v0: torch.Tensor, nev: int, m: int, solve_tol=1e-
     """(eigenvalues ascending, eigenvectors [nev] device tensor or None, relative residuals)."""
     ev = (ctypes.c_double * nev)()
     rs = (ctypes.c_double * nev)()
-    vecs = torch.empty((nev,) + tuple(h.L[::-1]) + (h.Ls, 4, 3), dtype=torch.complex128, device="cuda") \
+    vecs = torch.empty((nev,) + h.fermion_shape, dtype=torch.complex128, device="cuda") \
         if want_vectors else None
     _check(h.h, _lib.mgdwf_low_modes(h.h, _dev(v0, h.nfine, "v0"), nev, m, float(solve_tol), ev,
                                      _dev(vecs, h.nfine * nev, "evecs") if want_vectors else None, rs))

@@ -64,7 +64,8 @@ void check_prec_fine(mgdwf_prec p) {
   need(p == MGDWF_F64 || p == MGDWF_F32, MGDWF_ERR_INVALID_ARG, "fine precision must be F64 or F32");
 }
 
-CoarseGeometry make_coarse(const Geometry& g, const int32_t block[4], int nvec) {
+CoarseGeometry make_coarse(const mgdwf_ctx* c, const int32_t block[4], int nvec) {
+  const Geometry& g = c->g;
   CoarseGeometry cg{};
   cg.bvol = 1;
   cg.Vc = 1;
@@ -76,21 +77,37 @@ CoarseGeometry make_coarse(const Geometry& g, const int32_t block[4], int nvec) 
     cg.Vc *= cg.Lc[m];
   }
   need(nvec >= 1 && nvec <= 32, MGDWF_ERR_INVALID_ARG, "nvec must be in 1..32");
-  need(nvec <= 6 * g.Ls * cg.bvol, MGDWF_ERR_INVALID_ARG, "nvec exceeds the block's dof per chirality");
+  // dof of a block per chirality: Ls x (2 spins x 3 colours) in 4D, Ls x 1 spin in 2D
+  need(nvec <= (c->model == 0 ? 6 : 1) * g.Ls * cg.bvol, MGDWF_ERR_INVALID_ARG,
+       "nvec exceeds the block's dof per chirality");
   cg.Nv = nvec;
   cg.n2 = 2 * nvec;
   return cg;
 }
 
+// The squared coarse stencil needs block extents >= 2 along the lattice's
+// directions (the 2D model's z and t extents are 1, and so are its blocks there).
+void check_sq_blocks(const mgdwf_ctx* c, const int32_t block[4]) {
+  for (int m = 0; m < 4; ++m) {
+    if (c->model == 1 && m >= 2) continue;
+    need(block[m] >= 2, MGDWF_ERR_INVALID_ARG, "the squared-operator coarse stencil needs block extents >= 2");
+  }
+}
+
+// The calls that exist for the 4D operator only.
+void need_4d(const mgdwf_ctx* c, const char* what) {
+  if (c->model != 0) fail(MGDWF_ERR_INVALID_ARG, std::string(what) + " is not available for the 2D U(1) model");
+}
+
 void check_params(const mgdwf_ctx* c, const mgdwf_mg_params* p) {
   need(p != nullptr, MGDWF_ERR_INVALID_ARG, "null parameters");
   need(p->squared == 0 || p->squared == 1, MGDWF_ERR_INVALID_ARG, "squared must be 0 or 1");
+  need(c->model == 0 || p->squared == 1, MGDWF_ERR_INVALID_ARG, "the 2D U(1) model runs the squared-operator multigrid");
   if (p->squared) {
     need(p->nvec >= 1, MGDWF_ERR_INVALID_ARG, "nvec must be >= 1");
     need(p->coarse_prec == MGDWF_F64 || p->coarse_prec == MGDWF_F32, MGDWF_ERR_INVALID_ARG,
          "the squared-operator coarse level runs in F64 or F32");
-    for (int m = 0; m < 4; ++m)
-      need(p->block[m] >= 2, MGDWF_ERR_INVALID_ARG, "the squared-operator coarse stencil needs block extents >= 2");
+    check_sq_blocks(c, p->block);
   } else {
     need(p->nvec >= 2 && p->nvec % 2 == 0, MGDWF_ERR_INVALID_ARG, "nvec must be even (vectors are paired with their reflections)");
   }
@@ -103,7 +120,7 @@ void check_params(const mgdwf_ctx* c, const mgdwf_mg_params* p) {
   check_prec_fine(p->fine_prec);
   need(p->coarse_prec >= MGDWF_F64 && p->coarse_prec <= MGDWF_BF16, MGDWF_ERR_INVALID_ARG, "bad coarse precision");
   need(p->coarse_graph >= 0 && p->coarse_graph <= 2, MGDWF_ERR_INVALID_ARG, "coarse_graph must be 0, 1 or 2");
-  (void)make_coarse(c->g, p->block, p->nvec);
+  (void)make_coarse(c, p->block, p->nvec);
 }
 
 }  // namespace
@@ -115,8 +132,8 @@ void install_basis(mgdwf_ctx* c, const int block[4], int nvec) {
   c->have_basis = false;
   c->have_coarse = false;
   c->have_l2 = false;
-  c->cg = make_coarse(c->g, block, nvec);
-  if (!orthonormalise_basis(c->V64.as<double2>(), c->g, c->cg, c->st))
+  c->cg = make_coarse(c, block, nvec);
+  if (!fine_orthonormalise(c))
     fail(MGDWF_ERR_NUMERIC, "a block panel of the near-null vectors is numerically rank deficient");
   const long long n = c->fine_len() * nvec;
   c->V32.alloc(n * sizeof(float2));
@@ -128,11 +145,22 @@ void install_basis(mgdwf_ctx* c, const int block[4], int nvec) {
 void build_coarse_squared(mgdwf_ctx* c) {
   need(c->have_basis, MGDWF_ERR_STATE, "no basis installed");
   const CoarseGeometry& cg = c->cg;
-  for (int m = 0; m < 4; ++m)
-    need(cg.block[m] >= 2, MGDWF_ERR_INVALID_ARG, "the squared-operator coarse stencil needs block extents >= 2");
+  check_sq_blocks(c, cg.block);
   const long long field = c->fine_len();
   c->have_coarse = false;
   c->Asq.m64.alloc(sq_coarse_entries(cg) * sizeof(double2));
+  if (c->model == 1) {
+    build_sq_coarse_2d(c);
+    c->Asq.m32.alloc(sq_coarse_entries(cg) * sizeof(float2));
+    sq_to_f32(c->Asq.m64.as<double2>(), c->Asq.m32.as<float2>(), cg, c->st);
+    MG_HIP(hipStreamSynchronize(c->st));
+    for (const char* nm : {"dc_probe", "dc_applied", "dc_tmp", "dc_rr"}) c->ws.erase(nm);
+    ++c->ws_gen;
+    c->coarse_kind = 1;
+    c->have_l2 = false;
+    c->have_coarse = true;
+    return;
+  }
   double2* work9 = c->buf<double2>("dc_work9", 9 * field);
   double2* zwork9 = c->buf<double2>("dc_zwork9", 9 * field);
   double2* cwork = c->buf<double2>("dc_cwork", 9LL * cg.Vc * cg.n2);
@@ -150,6 +178,7 @@ void build_coarse_squared(mgdwf_ctx* c) {
 }
 
 void build_coarse(mgdwf_ctx* c) {
+  need_4d(c, "the 9-point coarse operator");
   need(c->have_basis, MGDWF_ERR_STATE, "no basis installed");
   const CoarseGeometry& cg = c->cg;
   const long long ndc = (long long)cg.Vc * 9 * cg.n2 * cg.n2;
@@ -220,6 +249,55 @@ mgdwf_status mgdwf_create(const mgdwf_action* a, void* hip_stream, mgdwf_handle*
   });
 }
 
+mgdwf_status mgdwf_create_2d(const mgdwf_action2d* a, void* hip_stream, mgdwf_handle* out) {
+  return guarded(nullptr, [&] {
+    need(a != nullptr && out != nullptr, MGDWF_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    need(a->Ls >= 1, MGDWF_ERR_INVALID_ARG, "Ls must be >= 1");
+    for (int m = 0; m < 2; ++m) {
+      need(a->L[m] >= 2, MGDWF_ERR_INVALID_ARG, "every extent must be >= 2");
+      need(a->bc[m] == 1 || a->bc[m] == -1, MGDWF_ERR_INVALID_ARG, "bc must be +1 or -1");
+    }
+    need(std::isfinite(a->M5) && std::isfinite(a->mf), MGDWF_ERR_INVALID_ARG, "non-finite M5 or mf");
+    const long long V2 = (long long)a->L[0] * a->L[1];
+    need(V2 * a->Ls * 2 < (1LL << 31), MGDWF_ERR_INVALID_ARG, "lattice too large for 32-bit site indices");
+    auto* c = new mgdwf_ctx();
+    c->model = 1;
+    c->g.L[0] = a->L[0];
+    c->g.L[1] = a->L[1];
+    c->g.L[2] = c->g.L[3] = 1;
+    c->g.bc[0] = a->bc[0];
+    c->g.bc[1] = a->bc[1];
+    c->g.bc[2] = c->g.bc[3] = 1;
+    c->g.Ls = a->Ls;
+    c->g.V4 = (int)V2;
+    c->g.V5 = (int)(V2 * a->Ls);
+    // the fine lattice seen as a lattice of coarse-vector sites: [x2][spin][s]
+    c->fg.Lc[0] = a->L[0];
+    c->fg.Lc[1] = a->L[1];
+    c->fg.Lc[2] = c->fg.Lc[3] = 1;
+    for (int m = 0; m < 4; ++m) c->fg.block[m] = 1;
+    c->fg.bvol = 1;
+    c->fg.Vc = (int)V2;
+    c->fg.Nv = a->Ls;
+    c->fg.n2 = 2 * a->Ls;
+    c->M5 = a->M5;
+    c->mf = a->mf;
+    c->st = static_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+      delete c;
+      fail(MGDWF_ERR_HIP, "no HIP device");
+    }
+    try {
+      c->scratch = scratch_address(c->device);
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+  });
+}
+
 mgdwf_status mgdwf_destroy(mgdwf_handle h) {
   if (!h) return MGDWF_OK;
   (void)hipStreamSynchronize(h->st);
@@ -233,10 +311,7 @@ mgdwf_status mgdwf_set_gauge(mgdwf_handle h, const double* U) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     need(U != nullptr, MGDWF_ERR_INVALID_ARG, "null gauge field");
-    const long long n = 36LL * h->g.V4;
-    h->U64.alloc(n * sizeof(double2));
-    h->U32.alloc(3 * n * sizeof(float2));  // component-major links, a site-major copy, a phase-folded copy
-    pack_gauge(reinterpret_cast<const double2*>(U), h->U64.as<double2>(), h->U32.as<float2>(), h->g, h->st);
+    pack_gauge_field(h, reinterpret_cast<const double2*>(U));
     MG_HIP(hipStreamSynchronize(h->st));
     h->have_gauge = true;
     h->have_basis = false;
@@ -255,17 +330,17 @@ mgdwf_status mgdwf_apply_dwf(mgdwf_handle h, const double* in, double* out, int3
     const long long n = h->fine_len() * nrhs;
     double2* a = h->buf<double2>("io_a", n);
     double2* b = h->buf<double2>("io_b", n);
-    pack_fermion_f64(reinterpret_cast<const double2*>(in), a, h->g, nrhs, h->st);
+    pack_field(h, reinterpret_cast<const double2*>(in), a, nrhs);
     if (prec == MGDWF_F64) {
-      dslash_ex<double2>(a, b, nullptr, h->U64.as<double2>(), h->g, h->M5, h->mf, dagger != 0, 0, nrhs, nullptr, h->st);
+      fine_dslash<double2>(h, a, b, nullptr, dagger != 0, 0, nrhs, nullptr, h->st);
     } else {
       float2* a32 = h->buf<float2>("io_a32", n);
       float2* b32 = h->buf<float2>("io_b32", n);
       convert<double2, float2>(a, a32, n, h->st);
-      dslash_ex<float2>(a32, b32, nullptr, h->U32.as<float2>(), h->g, h->M5, h->mf, dagger != 0, 0, nrhs, nullptr, h->st);
+      fine_dslash<float2>(h, a32, b32, nullptr, dagger != 0, 0, nrhs, nullptr, h->st);
       convert<float2, double2>(b32, b, n, h->st);
     }
-    unpack_fermion_f64(b, reinterpret_cast<double2*>(out), h->g, nrhs, h->st);
+    unpack_field(h, b, reinterpret_cast<double2*>(out), nrhs);
   });
 }
 
@@ -275,10 +350,10 @@ mgdwf_status mgdwf_set_nullvecs(mgdwf_handle h, const int32_t block[4], const do
     h->clear_graphs();
     need(block && V, MGDWF_ERR_INVALID_ARG, "null argument");
     need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
-    (void)make_coarse(h->g, block, nvec);
+    (void)make_coarse(h, block, nvec);
     const long long n = h->fine_len() * nvec;
     h->V64.alloc(n * sizeof(double2));
-    pack_fermion_f64(reinterpret_cast<const double2*>(V), h->V64.as<double2>(), h->g, nvec, h->st);
+    pack_field(h, reinterpret_cast<const double2*>(V), h->V64.as<double2>(), nvec);
     h->Vnull.alloc(n * sizeof(double2));
     MG_HIP(hipMemcpyAsync(h->Vnull.p, h->V64.p, n * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
     h->nnull = nvec;
@@ -293,7 +368,7 @@ mgdwf_status mgdwf_get_nullvecs(mgdwf_handle h, double* V, int32_t* n) {
     need(h->have_basis && h->nnull > 0, MGDWF_ERR_STATE, "no near-null vectors: run setup or set_nullvecs first");
     *n = h->nnull;
     if (!V) return;
-    unpack_fermion_f64(h->Vnull.as<double2>(), reinterpret_cast<double2*>(V), h->g, h->nnull, h->st);
+    unpack_field(h, h->Vnull.as<double2>(), reinterpret_cast<double2*>(V), h->nnull);
     MG_HIP(hipStreamSynchronize(h->st));
   });
 }
@@ -303,7 +378,7 @@ mgdwf_status mgdwf_get_basis(mgdwf_handle h, double* Vhat) {
   return guarded(h, [&] {
     need(Vhat != nullptr, MGDWF_ERR_INVALID_ARG, "null output");
     need(h->have_basis, MGDWF_ERR_STATE, "no basis installed");
-    unpack_fermion_f64(h->V64.as<double2>(), reinterpret_cast<double2*>(Vhat), h->g, h->cg.Nv, h->st);
+    unpack_field(h, h->V64.as<double2>(), reinterpret_cast<double2*>(Vhat), h->cg.Nv);
     MG_HIP(hipStreamSynchronize(h->st));
   });
 }
@@ -316,17 +391,15 @@ mgdwf_status mgdwf_restrict(mgdwf_handle h, const double* fine, double* coarse, 
     need(h->have_basis, MGDWF_ERR_STATE, "no basis installed");
     const long long n = h->fine_len() * nrhs;
     double2* a = h->buf<double2>("io_a", n);
-    double* part = h->buf<double>("rpart", restrict_partial_doubles(h->cg, nrhs));
-    pack_fermion_f64(reinterpret_cast<const double2*>(fine), a, h->g, nrhs, h->st);
+    pack_field(h, reinterpret_cast<const double2*>(fine), a, nrhs);
     if (prec == MGDWF_F64) {
-      restrict_op<double2, double2>(h->V64.as<double2>(), a, reinterpret_cast<double2*>(coarse), part, h->g, h->cg,
-                                    nrhs, h->st);
+      fine_restrict<double2>(h, h->V64.as<double2>(), a, reinterpret_cast<double2*>(coarse), nrhs);
     } else {
       const long long nc = h->coarse_len() * nrhs;
       float2* a32 = h->buf<float2>("io_a32", n);
       float2* c32 = h->buf<float2>("io_c32", nc);
       convert<double2, float2>(a, a32, n, h->st);
-      restrict_op<float2, float2>(h->V32.as<float2>(), a32, c32, part, h->g, h->cg, nrhs, h->st);
+      fine_restrict<float2>(h, h->V32.as<float2>(), a32, c32, nrhs);
       convert<float2, double2>(c32, reinterpret_cast<double2*>(coarse), nc, h->st);
     }
   });
@@ -340,17 +413,16 @@ mgdwf_status mgdwf_prolong(mgdwf_handle h, const double* coarse, double* fine, i
     const long long n = h->fine_len() * nrhs;
     double2* a = h->buf<double2>("io_a", n);
     if (prec == MGDWF_F64) {
-      prolong_op<double2, double2>(h->V64.as<double2>(), reinterpret_cast<const double2*>(coarse), a, false, h->g,
-                                   h->cg, nrhs, h->st);
+      fine_prolong<double2>(h, h->V64.as<double2>(), reinterpret_cast<const double2*>(coarse), a, false, nrhs);
     } else {
       const long long nc = h->coarse_len() * nrhs;
       float2* a32 = h->buf<float2>("io_a32", n);
       float2* c32 = h->buf<float2>("io_c32", nc);
       convert<double2, float2>(reinterpret_cast<const double2*>(coarse), c32, nc, h->st);
-      prolong_op<float2, float2>(h->V32.as<float2>(), c32, a32, false, h->g, h->cg, nrhs, h->st);
+      fine_prolong<float2>(h, h->V32.as<float2>(), c32, a32, false, nrhs);
       convert<float2, double2>(a32, a, n, h->st);
     }
-    unpack_fermion_f64(a, reinterpret_cast<double2*>(fine), h->g, nrhs, h->st);
+    unpack_field(h, a, reinterpret_cast<double2*>(fine), nrhs);
   });
 }
 mgdwf_status mgdwf_build_coarse(mgdwf_handle h) {
@@ -474,7 +546,7 @@ mgdwf_status mgdwf_setup(mgdwf_handle h, const mgdwf_mg_params* p, const double*
     if (report) std::memset(report, 0, sizeof(*report));
     const int nh = p->squared ? p->nvec : p->nvec / 2;
     double2* W = h->buf<double2>("setup_w", h->fine_len() * nh);
-    pack_fermion_f64(reinterpret_cast<const double2*>(V0), W, h->g, nh, h->st);
+    pack_field(h, reinterpret_cast<const double2*>(V0), W, nh);
     mg_setup(h, *p, W, report);
   });
 }
@@ -506,13 +578,13 @@ mgdwf_status mgdwf_solve(mgdwf_handle h, const double* b, double* x, int32_t nrh
     const long long n = h->fine_len() * nrhs;
     double2* b64 = h->buf<double2>("sol_b", n);
     x64 = h->buf<double2>("sol_x", n);
-    pack_fermion_f64(reinterpret_cast<const double2*>(b), b64, h->g, nrhs, h->st);
-    pack_fermion_f64(reinterpret_cast<const double2*>(x), x64, h->g, nrhs, h->st);
+    pack_field(h, reinterpret_cast<const double2*>(b), b64, nrhs);
+    pack_field(h, reinterpret_cast<const double2*>(x), x64, nrhs);
     mg_solve(h, b64, x64, nrhs, *p, reports);
   });
   if ((st == MGDWF_OK || st == MGDWF_ERR_NOT_CONVERGED) && x64) {
     mgdwf_status s2 = guarded(h, [&] {
-      unpack_fermion_f64(x64, reinterpret_cast<double2*>(x), h->g, nrhs, h->st);
+      unpack_field(h, x64, reinterpret_cast<double2*>(x), nrhs);
       MG_HIP(hipStreamSynchronize(h->st));
     });
     if (s2 != MGDWF_OK) return s2;
@@ -528,9 +600,9 @@ mgdwf_status mgdwf_apply_vcycle(mgdwf_handle h, const double* in, double* out, i
     const long long n = h->fine_len() * nrhs;
     double2* a = h->buf<double2>("io_a", n);
     double2* b = h->buf<double2>("io_b", n);
-    pack_fermion_f64(reinterpret_cast<const double2*>(in), a, h->g, nrhs, h->st);
+    pack_field(h, reinterpret_cast<const double2*>(in), a, nrhs);
     vcycle_apply(h, a, b, nrhs);
-    unpack_fermion_f64(b, reinterpret_cast<double2*>(out), h->g, nrhs, h->st);
+    unpack_field(h, b, reinterpret_cast<double2*>(out), nrhs);
     MG_HIP(hipStreamSynchronize(h->st));
   });
 }
@@ -540,6 +612,7 @@ mgdwf_status mgdwf_low_modes(mgdwf_handle h, const double* v0, int32_t nev, int3
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     need(v0 && evals, MGDWF_ERR_INVALID_ARG, "null argument");
+    need_4d(h, "mgdwf_low_modes");
     need(nev >= 1 && m >= nev && m <= 256, MGDWF_ERR_INVALID_ARG, "need 1 <= nev <= m <= 256");
     need(solve_tol > 0.0 && solve_tol <= 1e-3, MGDWF_ERR_INVALID_ARG, "solve_tol must be in (0, 1e-3]");
     need(h->have_coarse && h->have_params, MGDWF_ERR_STATE, "the Lanczos steps solve with the multigrid: set it up first");
@@ -562,7 +635,7 @@ mgdwf_status mgdwf_coarse_coverage(mgdwf_handle h, const double* e, int32_t n, d
     need(e && frac && n >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
     need(h->have_basis, MGDWF_ERR_STATE, "no basis installed");
     double2* a = h->buf<double2>("io_a", h->fine_len() * n);
-    pack_fermion_f64(reinterpret_cast<const double2*>(e), a, h->g, n, h->st);
+    pack_field(h, reinterpret_cast<const double2*>(e), a, n);
     coarse_coverage(h, a, n, frac);
   });
 }
@@ -640,7 +713,7 @@ void write_fields(mgdwf_ctx* h, FILE* f, const double2* dev, int n) {
   double2* canon = h->buf<double2>("ck_canon", nf);
   std::vector<double2> host(nf);
   for (int k = 0; k < n; ++k) {
-    unpack_fermion_f64(dev + k * nf, canon, h->g, 1, h->st);
+    unpack_field(h, dev + k * nf, canon, 1);
     MG_HIP(hipMemcpyAsync(host.data(), canon, nf * sizeof(double2), hipMemcpyDeviceToHost, h->st));
     MG_HIP(hipStreamSynchronize(h->st));
     need(fwrite(host.data(), sizeof(double2), nf, f) == (size_t)nf, MGDWF_ERR_INVALID_ARG, "checkpoint write failed");
@@ -654,7 +727,7 @@ void read_fields(mgdwf_ctx* h, FILE* f, double2* dev, int n) {
   for (int k = 0; k < n; ++k) {
     need(fread(host.data(), sizeof(double2), nf, f) == (size_t)nf, MGDWF_ERR_INVALID_ARG, "checkpoint is truncated");
     MG_HIP(hipMemcpyAsync(canon, host.data(), nf * sizeof(double2), hipMemcpyHostToDevice, h->st));
-    pack_fermion_f64(canon, dev + k * nf, h->g, 1, h->st);
+    pack_field(h, canon, dev + k * nf, 1);
     MG_HIP(hipStreamSynchronize(h->st));
   }
 }
@@ -713,7 +786,7 @@ mgdwf_status mgdwf_load_setup(mgdwf_handle h, const char* path) {
          "corrupt checkpoint header");
     h->clear_graphs();
     h->have_basis = h->have_coarse = h->have_params = false;
-    const CoarseGeometry cg = make_coarse(h->g, hd.block, hd.nvec);
+    const CoarseGeometry cg = make_coarse(h, hd.block, hd.nvec);
     const long long nf = h->fine_len();
     h->V64.alloc((size_t)hd.nvec * nf * sizeof(double2));
     read_fields(h, fh.f, h->V64.as<double2>(), hd.nvec);
@@ -796,13 +869,13 @@ mgdwf_status mgdwf_cgne(mgdwf_handle h, const double* b, double* x, const mgdwf_
     const long long n = h->fine_len();
     double2* b64 = h->buf<double2>("sol_b", n);
     x64 = h->buf<double2>("sol_x", n);
-    pack_fermion_f64(reinterpret_cast<const double2*>(b), b64, h->g, 1, h->st);
-    pack_fermion_f64(reinterpret_cast<const double2*>(x), x64, h->g, 1, h->st);
+    pack_field(h, reinterpret_cast<const double2*>(b), b64, 1);
+    pack_field(h, reinterpret_cast<const double2*>(x), x64, 1);
     cgne_solve(h, b64, x64, *p, report);
   });
   if ((st == MGDWF_OK || st == MGDWF_ERR_NOT_CONVERGED) && x64) {
     mgdwf_status s2 = guarded(h, [&] {
-      unpack_fermion_f64(x64, reinterpret_cast<double2*>(x), h->g, 1, h->st);
+      unpack_field(h, x64, reinterpret_cast<double2*>(x), 1);
       MG_HIP(hipStreamSynchronize(h->st));
     });
     if (s2 != MGDWF_OK) return s2;
@@ -814,6 +887,7 @@ mgdwf_status mgdwf_time_kernel(mgdwf_handle h, mgdwf_kernel k, mgdwf_prec prec, 
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     need(ms && iters >= 1 && nrhs >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
+    need_4d(h, "mgdwf_time_kernel");
     if (k == MGDWF_K_COARSE)
       need(prec >= MGDWF_F64 && prec <= MGDWF_BF16, MGDWF_ERR_INVALID_ARG, "bad coarse precision");
     else
@@ -899,6 +973,7 @@ mgdwf_status mgdwf_tune(mgdwf_handle h, int32_t nrhs, int32_t iters, mgdwf_tune_
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     need(rep && iters >= 1 && nrhs >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
+    need_4d(h, "mgdwf_tune");
     need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
     std::memset(rep, 0, sizeof(*rep));
     rep->chosen = -1;
@@ -1007,6 +1082,7 @@ mgdwf_status mgdwf_set_tiling(mgdwf_handle h, int32_t id) {
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     int desc[4], flags = 0;
+    need_4d(h, "mgdwf_set_tiling");
     need(id == -1 || dslash_ftile_desc(h->g, id, 1, desc, &flags), MGDWF_ERR_INVALID_ARG,
          "tiling does not apply to this lattice");
     h->g.ftile = id;
@@ -1028,6 +1104,7 @@ namespace {
 template <class F>
 mgdwf_status guarded_net(mgdwf_net n, mgdwf_handle h, F&& f) {
   try {
+    if (h) need_4d(h, "the near-null proposal network");
     f();
     return MGDWF_OK;
   } catch (const Error& e) {

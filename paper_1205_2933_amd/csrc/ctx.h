@@ -9,7 +9,11 @@
 #include "vecops.h"
 
 struct mgdwf_ctx {
+  // 0: the 4D SU(3) operator; 1: the 2D U(1) operator (g.L = {Lx, Ly, 1, 1},
+  // V4 = Lx * Ly, two spins, layouts in u1_2d.hip)
+  int model = 0;
   mgdwf::Geometry g{};
+  mgdwf::CoarseGeometry fg{};  // 2D model: the fine lattice as a coarse-vector lattice (Nv = Ls, chirality = spin)
   double M5 = 0.0, mf = 0.0;
   hipStream_t st = nullptr;
   int device = 0;
@@ -105,6 +109,29 @@ struct mgdwf_ctx {
     }
     return b.as<T>();
   }
-  long long fine_len() const { return 12LL * g.V5; }       // complex numbers per fine field
+  long long fine_len() const { return (model == 0 ? 12LL : 2LL) * g.V5; }  // complex numbers per fine field
   long long coarse_len() const { return (long long)cg.Vc * cg.n2; }
 };
+
+namespace mgdwf {
+
+// Fine-level operations of the handle's model (u1_2d.hip): the 4D kernels for
+// model 0, the 2D ones for model 1.
+void pack_field(const mgdwf_ctx* c, const double2* canon, double2* field, int nrhs);
+void unpack_field(const mgdwf_ctx* c, const double2* field, double2* canon, int nrhs);
+// allocates and fills U64 / U32 in the model's internal gauge layouts
+void pack_gauge_field(mgdwf_ctx* c, const double2* canon);
+// workgroups (partial sums per right-hand side) of fine_dslash with a partial buffer
+template <class F2> int fine_nblocks(const mgdwf_ctx* c, int nrhs);
+// out = D in (D^+ for dag); mode 1: out = b - D in; partial: per-workgroup |out|^2
+template <class F2>
+void fine_dslash(const mgdwf_ctx* c, const F2* in, F2* out, const F2* b, bool dag, int mode, int nrhs,
+                 double* partial, hipStream_t st);
+template <class F2> void fine_restrict(mgdwf_ctx* c, const F2* V, const F2* in, F2* out, int nrhs);
+template <class F2> void fine_prolong(mgdwf_ctx* c, const F2* V, const F2* cc, F2* out, bool acc, int nrhs);
+// chirality split + block orthonormalisation of the nvec fields in V64 on c->cg
+bool fine_orthonormalise(mgdwf_ctx* c);
+// A_c = P^+ D^+D P of the 2D model into c->Asq.m64 (allocated by the caller)
+void build_sq_coarse_2d(mgdwf_ctx* c);
+
+}  // namespace mgdwf

@@ -295,6 +295,13 @@ template void prolong2<float2>(const float2*, const float2*, float2*, bool, cons
 
 void build_level2_op(const double2* Ac, const double2* W, double2* Acc, double2* probes, double2* applied,
                      double2* rr, const CoarseGeometry& cg, const CoarseGeometry& c2, hipStream_t st) {
+  build_galerkin_op([&](const double2* x, double2* y, int n) { sq_apply64(Ac, x, y, cg, n, st); }, W, Acc, probes,
+                    applied, rr, cg, c2, st);
+}
+
+void build_galerkin_op(const std::function<void(const double2*, double2*, int)>& apply, const double2* W,
+                       double2* Acc, double2* probes, double2* applied, double2* rr, const CoarseGeometry& cg,
+                       const CoarseGeometry& c2, hipStream_t st) {
   const long long entries = (long long)c2.Vc * 33 * c2.n2 * c2.n2;
   hipLaunchKernelGGL(k_zero2, dim3(nblk(entries)), dim3(256), 0, st, Acc, entries);
   MG_LAUNCH_CHECK();
@@ -304,7 +311,7 @@ void build_level2_op(const double2* Ac, const double2* W, double2* Acc, double2*
   for (int B = 0; B < c2.Vc; ++B) {
     hipLaunchKernelGGL(k_probe2, dim3(nblk(pn)), dim3(256), 0, st, W, probes, g, c2.Nv, B);
     MG_LAUNCH_CHECK();
-    sq_apply64(Ac, probes, applied, cg, np, st);
+    apply(probes, applied, np);
     restrict2<double2>(W, applied, rr, cg, c2, np, st);
     const long long sn = (long long)c2.Vc * c2.n2 * np;
     hipLaunchKernelGGL(k_scatter2, dim3(nblk(sn)), dim3(256), 0, st, rr, Acc, c2, B);

@@ -240,12 +240,11 @@ void coarse_coverage(mgdwf_ctx* c, const double2* e, int n, double* frac) {
   const long long nf = c->fine_len(), nc = c->coarse_len();
   double2* cv = c->buf<double2>("lm_cv", nc);
   double2* pe = c->buf<double2>("lm_pe", nf);
-  double* part = c->buf<double>("rpart", restrict_partial_doubles(c->cg, 1));
   c->buf<double>("slots", NSLOT);
   for (int i = 0; i < n; ++i) {
     const double2* ei = e + (long long)i * nf;
-    restrict_op<double2, double2>(c->V64.as<double2>(), ei, cv, part, c->g, c->cg, 1, c->st);
-    prolong_op<double2, double2>(c->V64.as<double2>(), cv, pe, false, c->g, c->cg, 1, c->st);
+    fine_restrict<double2>(c, c->V64.as<double2>(), ei, cv, 1);
+    fine_prolong<double2>(c, c->V64.as<double2>(), cv, pe, false, 1);
     const double num = norm2(c, pe), den = norm2(c, ei);
     frac[i] = den > 0.0 ? num / den : 0.0;
   }

@@ -76,9 +76,9 @@ template <> const float2* basis_of<float2>(mgdwf_ctx* c) { return c->V32.as<floa
 template <class F2>
 void fine_op(mgdwf_ctx* c, const F2* in, F2* out, const F2* b, bool dag, int mode, int nrhs, int dst) {
   double* partial = nullptr;
-  const int nb = dslash_nblocks<F2>(c->g, nrhs);
+  const int nb = fine_nblocks<F2>(c, nrhs);
   if (dst >= 0) partial = c->buf<double>("dpart", (size_t)nb * nrhs);
-  dslash_ex<F2>(in, out, b, gauge_of<F2>(c), c->g, c->M5, c->mf, dag, mode, nrhs, partial, c->st);
+  fine_dslash<F2>(c, in, out, b, dag, mode, nrhs, partial, c->st);
   if (dst >= 0) finalize_rhs(partial, nb, 1, c->buf<double>("slots", (size_t)nrhs * NSLOT), dst, nrhs, c->st);
   c->fine_applies += 1;
 }
@@ -553,12 +553,11 @@ struct TwoLevelSq {
       copy(c, g, r1, nf * nrhs);
       zero<F2>(z, nf * nrhs, c->st);
     }
-    restrict_op<F2, F2>(V, r1, cb, c->buf<double>("rpart", restrict_partial_doubles(c->cg, nrhs)), c->g, c->cg,
-                        nrhs, c->st);                                       // g2 = R r1
+    fine_restrict<F2>(c, V, r1, cb, nrhs);                                // g2 = R r1
     c->phase_mark(1);
     coarse_solve(cb, cx);                                                   // x2 = CG(A_c, g2)
     c->phase_mark(2);
-    prolong_op<F2, F2>(V, cx, z, true, c->g, c->cg, nrhs, c->st);          // x1 + P x2
+    fine_prolong<F2>(c, V, cx, z, true, nrhs);                              // x1 + P x2
     if (p.nu_post > 0) {
       fine_op<F2>(c, z, t, nullptr, false, 0, nrhs, -1);                    // g3 = g - N (x1 + P x2)
       fine_op<F2>(c, t, r3, g, true, 1, nrhs, -1);
@@ -858,6 +857,10 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
   const double field_bytes = (double)nf * sizeof(double2);
   const int g0 = std::max(1, std::min(nh, std::min(4, (int)(48e9 / (6.0 * field_bytes)))));
   for (int k0 = 0; k0 < nh; k0 += g0) cgnr_null(c, W + (long long)k0 * nf, std::min(g0, nh - k0), p.sweep0_iters);
+  // the CG fields are not needed again: give them back before the basis and
+  // the coarse operator are built (the build's peak on large lattices)
+  for (const char* nm : {"cg_r", "cg_p", "cg_t", "cg_ap", "cg_zero"}) c->ws.erase(nm);
+  ++c->ws_gen;
   normalise(c, W, nh);
   auto rebuild = [&]() {
     // basis fields: the nh vectors and their fifth-dimension reflections
@@ -869,10 +872,9 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
       build_coarse_squared(c);
       return;
     }
-    double2* V = c->buf<double2>("setup_vfull", nf * p.nvec);
+    double2* V = c->V64.as<double2>();
     copy(c, W, V, nf * nh);
     reflect5<double2>(W, V + nf * nh, c->g, nh, c->st);
-    copy(c, V, c->V64.as<double2>(), nf * p.nvec);
     install_basis(c, p.block, p.nvec);
     build_coarse(c);
   };

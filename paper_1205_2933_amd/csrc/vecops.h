@@ -1,6 +1,8 @@
 // Host wrappers of the solver vector kernels (vecops.hip).
 #pragma once
 
+#include <functional>
+
 #include "mg_internal.h"
 
 namespace mgdwf {
@@ -126,6 +128,13 @@ void prolong2(const F2* W, const F2* cc, F2* out, bool acc, const CoarseGeometry
 // out = a - b
 template <class F2>
 void sub_into(F2* out, const F2* a, const F2* b, long long n, hipStream_t st);
+// Galerkin operator W^+ A W of a Hermitian operator A on the lattice cg into
+// the 33-offset form over c2 (Vcc x 33 column-major 2Nv2 blocks), read off per
+// source block: apply(in, out, n) applies A to n vectors of cg; probes and
+// applied: 2 Nv2 vectors of cg each, rr: 2 Nv2 vectors of c2
+void build_galerkin_op(const std::function<void(const double2*, double2*, int)>& apply, const double2* W,
+                       double2* Acc, double2* probes, double2* applied, double2* rr, const CoarseGeometry& cg,
+                       const CoarseGeometry& c2, hipStream_t st);
 // A_cc = R2 A_c P2 into the 33-offset form (Vcc x 33 column-major 2Nv2 blocks);
 // probes and applied: 2 Nv2 coarse vectors each, rr: 2 Nv2 level-2 vectors
 void build_level2_op(const double2* Ac, const double2* W, double2* Acc, double2* probes, double2* applied,
