@@ -79,10 +79,13 @@ def mem(tag):
         f"torch reserved {torch.cuda.memory_reserved() / 2**30:.1f} GiB")
 
 
+SWEEP0_CHECK = 25  # sweep 0 keeps each vector's best iterate, checked every 25 CG iterations
+
+
 def mg_params(mg, fine, coarse, coarse_graph=True):
     return mg.make_mg_params(BLOCK, NVEC, sweeps=1, sweep0_iters=400, sweep_iters=4, nu_pre=12, nu_post=12,
                              coarse_tol=0.1, coarse_maxiter=400, fine_prec=fine, coarse_prec=coarse,
-                             coarse_graph=coarse_graph)
+                             coarse_graph=coarse_graph, sweep0_check=SWEEP0_CHECK)
 
 
 def cpu_baseline(counts, x_mixed, b_mixed):
@@ -586,7 +589,8 @@ def learned_leg(mg, h_main, fields_future, c5_future, log):
         return r["outer_iters"], r["true_relres"] < 1e-10, el
 
     short = mg.make_mg_params(BLOCK, NVEC, sweeps=1, sweep0_iters=100, sweep_iters=4, nu_pre=12, nu_post=12,
-                              coarse_tol=0.1, coarse_maxiter=400, fine_prec="f64", coarse_prec="f64")
+                              coarse_tol=0.1, coarse_maxiter=400, fine_prec="f64", coarse_prec="f64",
+                              sweep0_check=SWEEP0_CHECK)
     # (a) the full setup from random starts
     torch.cuda.synchronize()
     t = time.perf_counter()

@@ -146,6 +146,15 @@ typedef struct {
                              same flexible GCR on D x = b.  Needs every block
                              extent >= 2 and an F64 or F32 coarse level; the
                              coarse solve runs as launched kernels.            */
+  int32_t sweep0_check;   /* 0: sweep 0 returns its last CG iterate.  k > 0: of
+                             the iterates after every k CG iterations and
+                             after the last, each vector keeps the one with
+                             the smallest |D v| / |v| (the earliest on a tie):
+                             the Krylov sweep of Sec. 2 is stopped while the
+                             vector holds the slowly removed modes (once CG
+                             resolves the lowest modes too, the ratio rises
+                             again).  One more application of D per vector
+                             every k iterations.                               */
 } mgdwf_mg_params;
 
 /* Outer flexible GCR (Sec. 3).  Every restart recomputes the true residual

@@ -54,6 +54,7 @@ class MGParams:
     coarse_tol: float = 0.1
     coarse_maxiter: int = 100
     coarse_restart: int = 16
+    sweep0_check: int = 0           # > 0: sweep 0 keeps its best iterate (cgnr_null_best)
 
 
 def _smoother_fn(kind: str):
@@ -120,6 +121,42 @@ def cgnr_null_steps(A, x0: np.ndarray, niter: int) -> np.ndarray:
     return x
 
 
+def cgnr_null_best(A, x0: np.ndarray, niter: int, check: int) -> np.ndarray:
+    """Sweep 0 with a stopping rule: the CG iterations of ``cgnr_null_steps``;
+    of the iterates after every ``check`` iterations and after the last one,
+    the one with the smallest null residual |A x| / |x| is returned (the
+    earliest on a tie).  The Krylov sweep is meant to stop while x holds the
+    modes the solver removes slowly (Sec. 2, adaptive paragraph); once CG
+    resolves the lowest modes as well, |A x| / |x| rises again."""
+    x = x0.copy()
+    r = -A.dag(A(x))
+    p = r.copy()
+    rr = _sol.vdot(r, r).real
+    best, best_q = x0.copy(), np.inf
+    for k in range(1, niter + 1):
+        Ap = A.dag(A(p))
+        pAp = _sol.vdot(p, Ap).real
+        if pAp == 0.0 or rr == 0.0:
+            break
+        a = rr / pAp
+        x += a * p
+        r -= a * Ap
+        rn = _sol.vdot(r, r).real
+        p = r + (rn / rr) * p
+        rr = rn
+        if k % check == 0 or k == niter:
+            q = null_residual(A, x)
+            if q < best_q or (k == niter and best_q == np.inf):
+                best, best_q = x.copy(), q
+    return best
+
+
+def sweep0(A, x0: np.ndarray, niter: int, check: int = 0) -> np.ndarray:
+    """Sweep 0 of the adaptive setup: the last CG iterate, or with check > 0
+    the best one (``cgnr_null_best``)."""
+    return cgnr_null_best(A, x0, niter, check) if check > 0 else cgnr_null_steps(A, x0, niter)
+
+
 def null_residual(A, v: np.ndarray) -> float:
     """|A v| / |v|, the quality measure of a near-null vector."""
     return _sol.norm(A(v)) / _sol.norm(v)
@@ -134,7 +171,7 @@ def adaptive_setup(A: _dwf.DWF, V0: np.ndarray, params: MGParams) -> MG:
     zero = np.zeros_like(V[0])
     norms = []
     for k in range(V.shape[0]):
-        x = cgnr_null_steps(A, V[k], params.sweep0_iters)
+        x = sweep0(A, V[k], params.sweep0_iters, params.sweep0_check)
         norms.append(_sol.norm(x))
         V[k] = x / norms[-1]
     mg.sweep_norms.append(norms)

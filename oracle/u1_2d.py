@@ -302,6 +302,7 @@ class U1Params:
     nu_post: int = 4
     coarse_tol: float = 0.1
     coarse_maxiter: int = 200
+    sweep0_check: int = 0
 
 
 @dataclass
@@ -335,7 +336,7 @@ def u1_setup(A: DWF2, V0: np.ndarray, params: U1Params, stencil: bool = False) -
     if V0.shape[0] != params.nvec:
         raise ValueError("expected nvec random starts")
     mg = U1MG(A, params, null_residuals=[])
-    V = np.array([_setup.cgnr_null_steps(A, v, params.sweep0_iters) for v in V0])
+    V = np.array([_setup.sweep0(A, v, params.sweep0_iters, params.sweep0_check) for v in V0])
     V = np.array([v / _sol.norm(v) for v in V])
     mg.rebuild(V, stencil)
     mg.null_residuals.append(float(np.median([_setup.null_residual(A, v) for v in V])))

@@ -795,8 +795,11 @@ void mg_solve(mgdwf_ctx* c, double2* b64, double2* x64, int nrhs, const mgdwf_so
   }
 }
 
-// CG on D^+D x = 0 from x (nrhs vectors in place): the Krylov sweep of the setup.
-static void cgnr_null(mgdwf_ctx* c, double2* x, int nrhs, int iters) {
+// CG on D^+D x = 0 from x (nrhs vectors in place): the Krylov sweep of the
+// setup.  With check > 0 each vector ends as the iterate, of those after every
+// check iterations and after the last, with the smallest |D x| / |x| (the
+// earliest on a tie).
+static void cgnr_null(mgdwf_ctx* c, double2* x, int nrhs, int iters, int check) {
   const long long nf = c->fine_len();
   double* sl = c->buf<double>("slots", (size_t)nrhs * NSLOT);
   double* vpart = c->buf<double>("vpart", (size_t)VEC_BLOCKS * nrhs * (2 * 16 + 3));
@@ -810,14 +813,29 @@ static void cgnr_null(mgdwf_ctx* c, double2* x, int nrhs, int iters) {
   fine_op<double2>(c, t, r, z, true, 1, nrhs, S_GRR_A);  // r = -D^+ D x
   copy(c, r, p, nf * nrhs);
   int cur = S_GRR_A, nxt = S_GRR_B;
-  for (int i = 0; i < iters; ++i) {
+  double2* best = check > 0 ? c->buf<double2>("cg_best", nf * nrhs) : nullptr;
+  std::vector<double> best_q(nrhs, INFINITY);
+  for (int i = 1; i <= iters; ++i) {
     fine_op<double2>(c, p, t, nullptr, false, 0, nrhs, S_GPAP);  // t = D p, <p, D^+D p> = |t|^2
     fine_op<double2>(c, t, Ap, nullptr, true, 0, nrhs, -1);
     mr_update<double2>(x, r, p, Ap, nf, nrhs, sl, cur, S_GPAP, false, vpart, c->st);
     finalize_rhs(vpart, vec_blocks(nf), 1, sl, nxt, nrhs, c->st);
     cg_dir<double2>(p, r, nf, nrhs, sl, nxt, cur, nullptr, c->st);
     std::swap(cur, nxt);
+    if (check > 0 && (i % check == 0 || i == iters)) {
+      fine_op<double2>(c, x, t, nullptr, false, 0, nrhs, S_TMP + 3);  // |D x|^2
+      norm_into<double2>(c, x, nullptr, nf, nrhs, S_TMP);              // |x|^2
+      std::vector<double> h = read_slots(c, nrhs);
+      for (int k = 0; k < nrhs; ++k) {
+        const double q = h[k * NSLOT + S_TMP + 3] / h[k * NSLOT + S_TMP];
+        if (q < best_q[k] || (i == iters && best_q[k] == INFINITY)) {
+          best_q[k] = q;
+          copy(c, x + (long long)k * nf, best + (long long)k * nf, nf);
+        }
+      }
+    }
   }
+  if (check > 0 && iters > 0) copy(c, best, x, nf * nrhs);
 }
 
 static void normalise(mgdwf_ctx* c, double2* v, int nrhs) {
@@ -856,10 +874,11 @@ void mg_setup(mgdwf_ctx* c, const mgdwf_mg_params& p, double2* W, mgdwf_setup_re
   // per-vector sum is the same as in one batch.
   const double field_bytes = (double)nf * sizeof(double2);
   const int g0 = std::max(1, std::min(nh, std::min(4, (int)(48e9 / (6.0 * field_bytes)))));
-  for (int k0 = 0; k0 < nh; k0 += g0) cgnr_null(c, W + (long long)k0 * nf, std::min(g0, nh - k0), p.sweep0_iters);
+  for (int k0 = 0; k0 < nh; k0 += g0)
+    cgnr_null(c, W + (long long)k0 * nf, std::min(g0, nh - k0), p.sweep0_iters, p.sweep0_check);
   // the CG fields are not needed again: give them back before the basis and
   // the coarse operator are built (the build's peak on large lattices)
-  for (const char* nm : {"cg_r", "cg_p", "cg_t", "cg_ap", "cg_zero"}) c->ws.erase(nm);
+  for (const char* nm : {"cg_r", "cg_p", "cg_t", "cg_ap", "cg_zero", "cg_best"}) c->ws.erase(nm);
   ++c->ws_gen;
   normalise(c, W, nh);
   auto rebuild = [&]() {

@@ -86,3 +86,28 @@ def test_default_setup_is_the_tested_path(cuda):
     back = mg.mgdwf_get_nullvecs(h).cpu().numpy()
     assert np.array_equal(back, V)
     h.close()
+
+
+def test_sweep0_stopping_rule_matches_oracle(cuda):
+    """sweep0_check: each vector keeps its best checked CG iterate; on this
+    lattice the rule picks an intermediate one (iteration 75 of 100 for the
+    first start), and the GPU's vectors equal the oracle's."""
+    import paper_1205_2933_amd as mg
+    from oracle import setup as osu
+    L, Ls, mf = (6, 6, 6, 6), 8, 0.001
+    U = prepare_gauge(L, 0.3, 11, ape_steps=2)
+    V0 = random_starts(L, Ls, 2, 21)
+    h = mg.Handle(L, Ls, 1.8, mf)
+    mg.mgdwf_set_gauge(h, dev(U))
+    p = mg.make_mg_params((3, 3, 3, 3), 4, sweeps=1, sweep0_iters=100, fine_prec="f64", coarse_prec="f64",
+                          sweep0_check=25)
+    mg.mgdwf_setup(h, p, dev(V0))
+    got = mg.mgdwf_get_nullvecs(h).cpu().numpy()
+    A = dwf.DWF(U, 1.8, mf)
+    for k in range(2):
+        w = osu.cgnr_null_best(A, V0[k], 100, 25)
+        w = w / np.linalg.norm(w)
+        e = np.linalg.norm(got[k] - w) / np.linalg.norm(w)
+        print(f"sweep-0 stopping rule, vector {k}: {e:.2e}", flush=True)
+        assert e < 1e-8
+    h.close()

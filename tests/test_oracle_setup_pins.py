@@ -141,3 +141,23 @@ def test_adaptive_sweep_with_exact_coarse_solve_removes_the_coarse_space():
     x, r = osv.gcr_fixed(A, np.zeros_like(v), v, 1, M=M)
     assert np.linalg.norm(x) / np.linalg.norm(v) < 1e-10
     assert np.linalg.norm(r) / np.linalg.norm(A(v)) < 1e-10
+
+
+def test_sweep0_stopping_rule_picks_the_best_checked_iterate():
+    """cgnr_null_best against brute force: the same number of CG iterations
+    run afresh for every checked count, the smallest |A x|/|x| among them;
+    with one check at the end it is plain sweep 0."""
+    L, Ls = (6, 6, 6, 6), 8
+    A = dwf.DWF(prepare_gauge(L, 0.3, 11, ape_steps=2), M5, 0.001)
+    v = random_starts(L, Ls, 1, 21)[0]
+    niter, check = 100, 25
+    cands = [k for k in range(check, niter + 1, check)]
+    xs = [osu.cgnr_null_steps(A, v, k) for k in cands]
+    q = [osu.null_residual(A, x) for x in xs]
+    assert cands[int(np.argmin(q))] == 75  # an intermediate iterate wins here (the ratio rises after it)
+    want = xs[int(np.argmin(q))]
+    got = osu.cgnr_null_best(A, v, niter, check)
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    last = osu.cgnr_null_best(A, v, 40, 1000)
+    assert np.array_equal(last, osu.cgnr_null_steps(A, v, 40))
+    assert np.array_equal(osu.sweep0(A, v, 40), osu.cgnr_null_steps(A, v, 40))
