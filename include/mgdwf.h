@@ -451,7 +451,7 @@ typedef enum {
   MGDWF_K_DSLASH = 0,    /* fine operator on internal-layout fields  */
   MGDWF_K_RESTRICT = 1,  /* R                                       */
   MGDWF_K_PROLONG = 2,   /* P                                       */
-  MGDWF_K_COARSE = 3     /* D_c apply                               */
+  MGDWF_K_COARSE = 3     /* D_c apply (A_c after build_coarse_squared) */
 } mgdwf_kernel;
 
 /* Autotuning of the FP32 Dslash: every tiling of the t-march kernels that
@@ -504,7 +504,8 @@ mgdwf_status mgdwf_set_tiling(mgdwf_handle h, int32_t id);
 
 /* Launch kernel `k` `iters` times back to back on the handle's stream on
  * internal buffers and return the mean time per launch in *ms, measured with
- * HIP events recorded on that stream. */
+ * HIP events recorded on that stream.  On a 2D handle the kernels are the 2D
+ * model's (its Dslash, R, P and A_c). */
 mgdwf_status mgdwf_time_kernel(mgdwf_handle h, mgdwf_kernel k, mgdwf_prec prec, int32_t nrhs,
                                int32_t iters, double* ms);
 

@@ -888,7 +888,6 @@ mgdwf_status mgdwf_time_kernel(mgdwf_handle h, mgdwf_kernel k, mgdwf_prec prec, 
   if (!h) return MGDWF_ERR_INVALID_ARG;
   return guarded(h, [&] {
     need(ms && iters >= 1 && nrhs >= 1, MGDWF_ERR_INVALID_ARG, "bad argument");
-    need_4d(h, "mgdwf_time_kernel");
     if (k == MGDWF_K_COARSE)
       need(prec >= MGDWF_F64 && prec <= MGDWF_BF16, MGDWF_ERR_INVALID_ARG, "bad coarse precision");
     else
@@ -902,30 +901,28 @@ mgdwf_status mgdwf_time_kernel(mgdwf_handle h, mgdwf_kernel k, mgdwf_prec prec, 
       for (int i = 0; i < reps; ++i) {
         if (k == MGDWF_K_DSLASH) {
           if (prec == MGDWF_F64)
-            dslash_ex<double2>(h->buf<double2>("t_a", nf), h->buf<double2>("t_b", nf), nullptr, h->U64.as<double2>(),
-                               h->g, h->M5, h->mf, false, 0, nrhs, nullptr, h->st);
+            fine_dslash<double2>(h, h->buf<double2>("t_a", nf), h->buf<double2>("t_b", nf), nullptr, false, 0, nrhs,
+                                 nullptr, h->st);
           else
-            dslash_ex<float2>(h->buf<float2>("t_a32", nf), h->buf<float2>("t_b32", nf), nullptr, h->U32.as<float2>(),
-                              h->g, h->M5, h->mf, false, 0, nrhs, nullptr, h->st);
+            fine_dslash<float2>(h, h->buf<float2>("t_a32", nf), h->buf<float2>("t_b32", nf), nullptr, false, 0, nrhs,
+                                nullptr, h->st);
         } else {
           need(h->have_coarse, MGDWF_ERR_STATE, "coarse operator not built");
           const long long nc = h->coarse_len() * nrhs;
           if (k == MGDWF_K_RESTRICT) {
             if (prec == MGDWF_F64)
-              restrict_op<double2, double2>(h->V64.as<double2>(), h->buf<double2>("t_a", nf), h->buf<double2>("t_c", nc),
-                                            h->buf<double>("rpart", restrict_partial_doubles(h->cg, nrhs)), h->g, h->cg,
-                                            nrhs, h->st);
+              fine_restrict<double2>(h, h->V64.as<double2>(), h->buf<double2>("t_a", nf), h->buf<double2>("t_c", nc),
+                                     nrhs);
             else
-              restrict_op<float2, float2>(h->V32.as<float2>(), h->buf<float2>("t_a32", nf), h->buf<float2>("t_c32", nc),
-                                          h->buf<double>("rpart", restrict_partial_doubles(h->cg, nrhs)), h->g, h->cg,
-                                          nrhs, h->st);
+              fine_restrict<float2>(h, h->V32.as<float2>(), h->buf<float2>("t_a32", nf), h->buf<float2>("t_c32", nc),
+                                    nrhs);
           } else if (k == MGDWF_K_PROLONG) {
             if (prec == MGDWF_F64)
-              prolong_op<double2, double2>(h->V64.as<double2>(), h->buf<double2>("t_c", nc), h->buf<double2>("t_a", nf),
-                                           false, h->g, h->cg, nrhs, h->st);
+              fine_prolong<double2>(h, h->V64.as<double2>(), h->buf<double2>("t_c", nc), h->buf<double2>("t_a", nf),
+                                    false, nrhs);
             else
-              prolong_op<float2, float2>(h->V32.as<float2>(), h->buf<float2>("t_c32", nc), h->buf<float2>("t_a32", nf),
-                                         false, h->g, h->cg, nrhs, h->st);
+              fine_prolong<float2>(h, h->V32.as<float2>(), h->buf<float2>("t_c32", nc), h->buf<float2>("t_a32", nf),
+                                   false, nrhs);
           } else if (k == MGDWF_K_COARSE && h->coarse_kind == 1) {
             need(prec == MGDWF_F64 || prec == MGDWF_F32, MGDWF_ERR_INVALID_ARG, "the squared coarse operator is F64 or F32");
             if (prec == MGDWF_F64)

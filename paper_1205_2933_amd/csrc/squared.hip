@@ -131,35 +131,58 @@ __global__ void k_sq_to_f32(const double2* __restrict__ in, float2* __restrict__
 
 // y[rhs](X) = sum_o A[X][o] x[rhs](X + o) for up to NR right-hand sides.
 // Workgroup = one coarse site, nine wavefronts; wavefront w takes the
-// offsets o = w, w + 9, w + 18, w + 27 (< 33); lane = output row; the nine
+// offsets o = w, w + 9, w + 18, w + 27 (< 33); lane = output row.  Per offset
+// the wavefront first copies the neighbour's coarse vectors of all NR
+// right-hand sides into its own LDS panel ([col][rhs], zero past the last
+// right-hand side), so the inner loop reads one coalesced matrix column per
+// step from memory and the NR vector entries as LDS broadcasts.  The nine
 // partial sums are added in a fixed order through LDS.
 template <class MC2, class VC2, int NR>
 __global__ __launch_bounds__(576) void k_sq_apply(const MC2* __restrict__ M, const VC2* __restrict__ x,
                                                   VC2* __restrict__ y, SqArgs a, int nrhs, int rhs0) {
   using T = typename real_of<VC2>::type;
-  __shared__ T red[NR][64][2];
+  __shared__ VC2 xs[9][64 * NR];  // per wavefront: [col][rhs]; reused for the reduction at the end
   const int X = blockIdx.x;
   const int n2 = a.n2;
   const int w = threadIdx.x >> 6, row = threadIdx.x & 63;
   const int nr = min(NR, nrhs - rhs0);
   const long long vs = (long long)a.Vc * n2;
+  VC2* panel = xs[w];
   VC2 acc[NR];
 #pragma unroll
   for (int j = 0; j < NR; ++j) acc[j] = cmk<VC2>(0, 0);
-  if (row < n2) {
-    for (int o = w; o < 33; o += 9) {
+  for (int k = 0; k < 4; ++k) {  // every wavefront takes four turns (the barriers need them all)
+    const int o = w + 9 * k;
+    const bool act = o < 33;
+    if (act) {
       const int Y = sq_neighbour(a, X, o);
-      const MC2* Mo = M + ((long long)X * 33 + o) * n2 * n2;
       const VC2* xv = x + (long long)rhs0 * vs + (long long)Y * n2;
-      for (int c = 0; c < n2; ++c) {
+      for (int e = row; e < NR * n2; e += 64) {
+        const int j = e / n2, c = e - j * n2;
+        panel[c * NR + j] = j < nr ? xv[(long long)j * vs + c] : cmk<VC2>(0, 0);
+      }
+    }
+    __syncthreads();
+    if (act && row < n2) {
+      const MC2* Mo = M + ((long long)X * 33 + o) * n2 * n2;
+      auto column = [&](int c) {
         const MC2 m = Mo[c * n2 + row];
         const VC2 mv = cmk<VC2>((T)m.x, (T)m.y);
 #pragma unroll
-        for (int j = 0; j < NR; ++j)
-          if (j < nr) cfma(acc[j], mv, xv[j * vs + c]);
+        for (int j = 0; j < NR; ++j) cfma(acc[j], mv, panel[c * NR + j]);
+      };
+      if constexpr (sizeof(T) == 4) {
+        // FP32: four columns in flight (202 against 262 us at 12 RHS on
+        // 512 sites x 48 dof); FP64 runs faster without (307 against 338 us)
+#pragma unroll 4
+        for (int c = 0; c < n2; ++c) column(c);
+      } else {
+        for (int c = 0; c < n2; ++c) column(c);
       }
     }
+    __syncthreads();
   }
+  T (*red)[64][2] = reinterpret_cast<T (*)[64][2]>(&xs[0][0]);  // [rhs][row][re, im]
   for (int q = 0; q < 9; ++q) {
     if (w == q)
 #pragma unroll
@@ -233,12 +256,24 @@ void sq_canonical(const double2* Ac, double2* out, const CoarseGeometry& cg, hip
   MG_LAUNCH_CHECK();
 }
 
+// The right-hand sides go in launches of at most NRMAX; each launch uses the
+// smallest compiled panel width that holds its count (the inner loop runs
+// over the whole width).
+template <class MC2, class VC2, int NR>
+static void sq_launch(const MC2* A, const VC2* x, VC2* y, const SqArgs& a, int Vc, int nrhs, int r0, hipStream_t st) {
+  hipLaunchKernelGGL((k_sq_apply<MC2, VC2, NR>), dim3(Vc), dim3(576), 0, st, A, x, y, a, nrhs, r0);
+  MG_LAUNCH_CHECK();
+}
+
 void sq_apply64(const double2* Ac, const double2* x, double2* y, const CoarseGeometry& cg, int nrhs, hipStream_t st) {
   if (cg.n2 > 64) fail(MGDWF_ERR_INVALID_ARG, "2*nvec above 64 is not supported");
   const SqArgs a = sq_args(cg);
   for (int r0 = 0; r0 < nrhs; r0 += 8) {
-    hipLaunchKernelGGL((k_sq_apply<double2, double2, 8>), dim3(cg.Vc), dim3(576), 0, st, Ac, x, y, a, nrhs, r0);
-    MG_LAUNCH_CHECK();
+    const int nr = std::min(8, nrhs - r0);
+    if (nr == 1) sq_launch<double2, double2, 1>(Ac, x, y, a, cg.Vc, nrhs, r0, st);
+    else if (nr == 2) sq_launch<double2, double2, 2>(Ac, x, y, a, cg.Vc, nrhs, r0, st);
+    else if (nr <= 4) sq_launch<double2, double2, 4>(Ac, x, y, a, cg.Vc, nrhs, r0, st);
+    else sq_launch<double2, double2, 8>(Ac, x, y, a, cg.Vc, nrhs, r0, st);
   }
 }
 
@@ -246,8 +281,13 @@ void sq_apply32(const float2* Ac32, const float2* x, float2* y, const CoarseGeom
   if (cg.n2 > 64) fail(MGDWF_ERR_INVALID_ARG, "2*nvec above 64 is not supported");
   const SqArgs a = sq_args(cg);
   for (int r0 = 0; r0 < nrhs; r0 += 16) {
-    hipLaunchKernelGGL((k_sq_apply<float2, float2, 16>), dim3(cg.Vc), dim3(576), 0, st, Ac32, x, y, a, nrhs, r0);
-    MG_LAUNCH_CHECK();
+    const int nr = std::min(16, nrhs - r0);
+    if (nr == 1) sq_launch<float2, float2, 1>(Ac32, x, y, a, cg.Vc, nrhs, r0, st);
+    else if (nr == 2) sq_launch<float2, float2, 2>(Ac32, x, y, a, cg.Vc, nrhs, r0, st);
+    else if (nr <= 4) sq_launch<float2, float2, 4>(Ac32, x, y, a, cg.Vc, nrhs, r0, st);
+    else if (nr <= 8) sq_launch<float2, float2, 8>(Ac32, x, y, a, cg.Vc, nrhs, r0, st);
+    else if (nr <= 12) sq_launch<float2, float2, 12>(Ac32, x, y, a, cg.Vc, nrhs, r0, st);
+    else sq_launch<float2, float2, 16>(Ac32, x, y, a, cg.Vc, nrhs, r0, st);
   }
 }
 

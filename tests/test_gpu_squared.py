@@ -66,7 +66,10 @@ def test_squared_apply_is_r_dd_p(cuda, L, block, nvec):
     h, U, Vh = _handle(mg, L, Ls, mf, block, nvec, 52)
     A = dwf.DWF(U, 1.8, mf)
     Lc = tuple(L[m] // block[m] for m in range(4))
-    for nr, prec, tol in ((3, "f64", 1e-12), (18, "f32", 2e-6)):
+    # right-hand side counts that take every panel width of the apply
+    # (FP64: 1, 4, 8 + 1; FP32: 1, 12, 16 + 2)
+    for nr, prec, tol in ((1, "f64", 1e-12), (3, "f64", 1e-12), (9, "f64", 1e-12), (1, "f32", 2e-6),
+                          (12, "f32", 2e-6), (18, "f32", 2e-6)):
         rng = np.random.default_rng(53)
         c = rng.standard_normal((nr,) + Lc[::-1] + (2, nvec)) + 1j * rng.standard_normal((nr,) + Lc[::-1] + (2, nvec))
         y = torch.empty_like(dev(c))
