@@ -443,6 +443,20 @@ mgdwf_status mgdwf_net_propose(mgdwf_net net, mgdwf_handle h, const double* eta,
 mgdwf_status mgdwf_net_grad(mgdwf_net net, mgdwf_handle h, const double* eta, double* loss, float* grad);
 /* One Adam step (lr; beta 0.9 / 0.999) on that loss; *loss before the step. */
 mgdwf_status mgdwf_net_train_step(mgdwf_net net, mgdwf_handle h, const double* eta, double lr, double* loss);
+/* `steps` Adam steps cycling over the n handles (each with its gauge field
+ * and the target basis installed): step k trains on hs[k % n] with input
+ * draw etas[k] (device pointers, one per step) at learning rate
+ * lr (lr_final / lr)^(k / (steps - 1)); losses (HOST, may be NULL) gets each
+ * step's loss before its update.  MGDWF_ERR_STATE if a handle lacks its
+ * gauge field or basis. */
+mgdwf_status mgdwf_net_train(mgdwf_net net, const mgdwf_handle* hs, int32_t n, const double* const* etas,
+                             int32_t steps, double lr, double lr_final, double* losses);
+/* Network files: the channel counts, lam, the Adam step count, the FP32
+ * master weights and both Adam moments (training resumes where it stopped).
+ * Load refuses a file of other channel counts (MGDWF_ERR_STATE) or a file
+ * that is not a complete network file (MGDWF_ERR_INVALID_ARG). */
+mgdwf_status mgdwf_net_save(mgdwf_net net, const char* path);
+mgdwf_status mgdwf_net_load(mgdwf_net net, const char* path);
 
 /* ---- measurement ------------------------------------------------------- */
 

@@ -169,6 +169,10 @@ def _load() -> ctypes.CDLL:
         "mgdwf_net_propose": ([H, H, P, P], ctypes.c_int),
         "mgdwf_net_grad": ([H, H, P, ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
         "mgdwf_net_train_step": ([H, H, P, ctypes.c_double, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "mgdwf_net_train": ([H, ctypes.POINTER(H), i32, ctypes.POINTER(P), i32, ctypes.c_double, ctypes.c_double, P],
+                            ctypes.c_int),
+        "mgdwf_net_save": ([H, ctypes.c_char_p], ctypes.c_int),
+        "mgdwf_net_load": ([H, ctypes.c_char_p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -629,3 +633,23 @@ def mgdwf_net_train_step(net: Net, h: Handle, eta: torch.Tensor, lr: float) -> f
     _net_check(net, _lib.mgdwf_net_train_step(net.n, h.h, _dev(eta, net.channels[0] * h.V4 * 3, "eta"), lr,
                                               ctypes.byref(loss)))
     return loss.value
+
+
+def mgdwf_net_train(net: Net, handles, etas, lr: float, lr_final: float | None = None) -> list:
+    """len(etas) Adam steps cycling over the handles; returns the losses."""
+    n, steps = len(handles), len(etas)
+    lr_final = lr if lr_final is None else lr_final
+    H = (ctypes.c_void_p * n)(*[h.h for h in handles])
+    E = (ctypes.c_void_p * steps)(*[_dev(e, net.channels[0] * handles[k % n].V4 * 3, "eta")
+                                     for k, e in enumerate(etas)])
+    losses = (ctypes.c_double * steps)()
+    _net_check(net, _lib.mgdwf_net_train(net.n, H, n, E, steps, lr, lr_final, losses))
+    return list(losses)
+
+
+def mgdwf_net_save(net: Net, path):
+    _net_check(net, _lib.mgdwf_net_save(net.n, str(path).encode()))
+
+
+def mgdwf_net_load(net: Net, path):
+    _net_check(net, _lib.mgdwf_net_load(net.n, str(path).encode()))

@@ -1,5 +1,6 @@
 // extern "C" entry points (include/mgdwf.h): argument validation, layout
 // conversion at the boundary, and conversion of C++ errors to status codes.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -1189,6 +1190,88 @@ mgdwf_status mgdwf_net_train_step(mgdwf_net net, mgdwf_handle h, const double* e
     need(eta && loss && lr > 0, MGDWF_ERR_INVALID_ARG, "bad argument");
     need(h->have_gauge, MGDWF_ERR_STATE, "gauge field not set");
     *loss = mgdwf::net_train_step(net->net, h, reinterpret_cast<const double2*>(eta), lr);
+  });
+}
+
+mgdwf_status mgdwf_net_train(mgdwf_net net, const mgdwf_handle* hs, int32_t n, const double* const* etas,
+                             int32_t steps, double lr, double lr_final, double* losses) {
+  if (!net || !hs || !etas || n < 1 || steps < 1) return MGDWF_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!hs[i]) return MGDWF_ERR_INVALID_ARG;
+  return guarded_net(net, nullptr, [&] {
+    need(lr > 0 && lr_final > 0, MGDWF_ERR_INVALID_ARG, "learning rates must be > 0");
+    for (int i = 0; i < n; ++i) {
+      need_4d(hs[i], "the near-null proposal network");
+      need(hs[i]->have_gauge && hs[i]->have_basis, MGDWF_ERR_STATE, "every handle needs its gauge field and target basis");
+    }
+    for (int k = 0; k < steps; ++k) {
+      need(etas[k] != nullptr, MGDWF_ERR_INVALID_ARG, "null input draw");
+      mgdwf_handle h = hs[k % n];
+      const double a = lr * std::pow(lr_final / lr, (double)k / std::max(1, steps - 1));
+      const double l = mgdwf::net_train_step(net->net, h, reinterpret_cast<const double2*>(etas[k]), a);
+      if (losses) losses[k] = l;
+    }
+  });
+}
+
+// ---- network files: magic, int32 channels[5], double lam, int64 Adam step,
+// int64 weight count, then FP32 master weights and the two Adam moments
+namespace {
+constexpr char kNetMagic[8] = {'M', 'G', 'D', 'W', 'F', 'N', 'N', '1'};
+}
+
+mgdwf_status mgdwf_net_save(mgdwf_net net, const char* path) {
+  if (!net) return MGDWF_ERR_INVALID_ARG;
+  return guarded_net(net, nullptr, [&] {
+    need(path != nullptr, MGDWF_ERR_INVALID_ARG, "null path");
+    const long long nw = net->net.nweights();
+    std::vector<float> host(3 * nw);
+    MG_HIP(hipMemcpy(host.data(), net->net.w.p, nw * sizeof(float), hipMemcpyDeviceToHost));
+    MG_HIP(hipMemcpy(host.data() + nw, net->net.m.p, nw * sizeof(float), hipMemcpyDeviceToHost));
+    MG_HIP(hipMemcpy(host.data() + 2 * nw, net->net.v.p, nw * sizeof(float), hipMemcpyDeviceToHost));
+    FILE* f = std::fopen(path, "wb");
+    need(f != nullptr, MGDWF_ERR_INVALID_ARG, "cannot open the network file for writing");
+    int32_t ch[5];
+    for (int l = 0; l < 5; ++l) ch[l] = net->net.ch[l];
+    const int64_t step = net->net.step, n64 = nw;
+    bool ok = std::fwrite(kNetMagic, 1, 8, f) == 8 && std::fwrite(ch, sizeof ch, 1, f) == 1 &&
+              std::fwrite(&net->net.lam, sizeof(double), 1, f) == 1 && std::fwrite(&step, 8, 1, f) == 1 &&
+              std::fwrite(&n64, 8, 1, f) == 1 &&
+              std::fwrite(host.data(), sizeof(float), host.size(), f) == host.size();
+    ok = (std::fclose(f) == 0) && ok;
+    need(ok, MGDWF_ERR_INVALID_ARG, "writing the network file failed");
+  });
+}
+
+mgdwf_status mgdwf_net_load(mgdwf_net net, const char* path) {
+  if (!net) return MGDWF_ERR_INVALID_ARG;
+  return guarded_net(net, nullptr, [&] {
+    need(path != nullptr, MGDWF_ERR_INVALID_ARG, "null path");
+    FILE* f = std::fopen(path, "rb");
+    need(f != nullptr, MGDWF_ERR_INVALID_ARG, "cannot open the network file");
+    char magic[8];
+    int32_t ch[5];
+    double lam = 0.0;
+    int64_t step = 0, n64 = 0;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kNetMagic, 8) == 0 &&
+              std::fread(ch, sizeof ch, 1, f) == 1 && std::fread(&lam, sizeof(double), 1, f) == 1 &&
+              std::fread(&step, 8, 1, f) == 1 && std::fread(&n64, 8, 1, f) == 1;
+    const long long nw = net->net.nweights();
+    bool same = ok && n64 == nw;
+    for (int l = 0; l < 5 && same; ++l) same = ch[l] == net->net.ch[l];
+    std::vector<float> host;
+    if (same) {
+      host.resize(3 * nw);
+      ok = std::fread(host.data(), sizeof(float), host.size(), f) == host.size();
+    }
+    std::fclose(f);
+    need(ok, MGDWF_ERR_INVALID_ARG, "not a complete network file");
+    need(same, MGDWF_ERR_STATE, "the file holds a network of other channel counts");
+    net->net.set_weights(host.data(), nullptr);  // weights and their BF16 copy (resets Adam)
+    MG_HIP(hipMemcpy(net->net.m.p, host.data() + nw, nw * sizeof(float), hipMemcpyHostToDevice));
+    MG_HIP(hipMemcpy(net->net.v.p, host.data() + 2 * nw, nw * sizeof(float), hipMemcpyHostToDevice));
+    net->net.step = step;
+    net->net.lam = lam;
   });
 }
 

@@ -53,18 +53,32 @@ def targets(h: mg.Handle, params: mg.mgdwf_mg_params, seed: int) -> dict:
     return rep
 
 
+def _lr_at(lr: float, lr_final: float, k: int, total: int) -> float:
+    return lr * (lr_final / lr) ** (k / max(1, total - 1))
+
+
+def _train_span(net: mg.Net, handles, k0: int, k1: int, total: int, lr: float, lr_final: float, seed: int) -> list:
+    """Steps k0 .. k1 - 1 of a geometric schedule over `total` steps, in one
+    mgdwf_net_train call (step k on handles[k % len(handles)], input draw
+    seed + k)."""
+    n = len(handles)
+    hs = [handles[(k0 + j) % n] for j in range(min(n, k1 - k0))]
+    etas = [noise(net.channels[0], handles[k % n].V4, seed + k) for k in range(k0, k1)]
+    return mg.mgdwf_net_train(net, hs, etas, _lr_at(lr, lr_final, k0, total), _lr_at(lr, lr_final, k1 - 1, total))
+
+
 def train(net: mg.Net, handles, steps: int, lr: float, lr_final: float | None = None, seed: int = 0,
           log=None) -> list:
     """Adam steps cycling over the handles (each with its target basis
-    installed); learning rate decays geometrically from lr to lr_final."""
+    installed); learning rate decays geometrically from lr to lr_final.  The
+    steps run in the library (mgdwf_net_train), 100 per call."""
     losses = []
     lr_final = lr if lr_final is None else lr_final
-    for k in range(steps):
-        h = handles[k % len(handles)]
-        a = lr * (lr_final / lr) ** (k / max(1, steps - 1))
-        losses.append(mg.mgdwf_net_train_step(net, h, noise(net.channels[0], h.V4, seed + k), a))
-        if log and (k % 100 == 0 or k == steps - 1):
-            log(f"train step {k}: loss {losses[-1]:.4f}")
+    for k0 in range(0, steps, 100):
+        k1 = min(steps, k0 + 100)
+        losses += _train_span(net, handles, k0, k1, steps, lr, lr_final, seed)
+        if log:
+            log(f"train step {k1 - 1}: loss {losses[-1]:.4f}")
     return losses
 
 
@@ -72,18 +86,17 @@ def train_stream(net: mg.Net, make_handle, n_lattices: int, params: mg.mgdwf_mg_
                  lr: float, lr_final: float | None = None, seed: int = 0, log=None) -> list:
     """Training that streams over lattices: for lattice i, make_handle(i)
     returns a handle with its gauge field set, a full adaptive setup installs
-    the target basis, steps_per_lattice Adam steps run on it and the handle is
-    released.  The learning rate decays geometrically over all steps."""
+    the target basis, steps_per_lattice Adam steps run on it (one
+    mgdwf_net_train call) and the handle is released.  The learning rate
+    decays geometrically over all steps."""
     losses = []
     total = n_lattices * steps_per_lattice
     lr_final = lr if lr_final is None else lr_final
     for i in range(n_lattices):
         h = make_handle(i)
         targets(h, params, seed + 7919 * i + 1)
-        for k in range(steps_per_lattice):
-            step = i * steps_per_lattice + k
-            a = lr * (lr_final / lr) ** (step / max(1, total - 1))
-            losses.append(mg.mgdwf_net_train_step(net, h, noise(net.channels[0], h.V4, seed + step), a))
+        k0 = i * steps_per_lattice
+        losses += _train_span(net, [h], k0, k0 + steps_per_lattice, total, lr, lr_final, seed)
         h.close()
         if log and (i % 25 == 0 or i == n_lattices - 1):
             log(f"lattice {i}: loss {sum(losses[-steps_per_lattice:]) / steps_per_lattice:.4f}")

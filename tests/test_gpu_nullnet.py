@@ -141,3 +141,40 @@ def test_training_lowers_the_loss(cuda):
     # leaves the first term near 1; the steps still have to lower it
     assert losses[-1] < l0 - 0.01
     assert all(np.isfinite(losses))
+
+
+def test_library_training_loop_and_network_files(cuda, tmp_path):
+    """mgdwf_net_train equals the same Adam steps taken one call at a time
+    (constant learning rate: the same arithmetic, bit for bit); a saved
+    network reloads its weights and Adam state, so training continues
+    identically; other channel counts and foreign files are refused."""
+    import paper_1205_2933_amd as mg
+    case = CASES[0]
+    L, Ls, block, nvec, ch = case
+    U, h, net, Ws, eta = make(case, mg)
+    mg.mgdwf_set_nullvecs(h, block, dev(random_starts(L, Ls, nvec, 41)), nvec)
+    etas = [dev(noise(ch[0], L, 100 + k)) for k in range(6)]
+    _, h2, net2, _, _ = make(case, mg)
+    mg.mgdwf_set_nullvecs(h2, block, dev(random_starts(L, Ls, nvec, 42)), nvec)
+    one = [mg.mgdwf_net_train_step(net, (h, h2)[k % 2], etas[k], 3e-3) for k in range(6)]
+    loop = mg.mgdwf_net_train(net2, [h, h2], etas, 3e-3, 3e-3)
+    assert one == loop
+    assert torch.equal(mg.mgdwf_net_get_weights(net), mg.mgdwf_net_get_weights(net2))
+    path = tmp_path / "net.bin"
+    mg.mgdwf_net_save(net, path)
+    net3 = mg.Net(ch, 1.0, seed=9)
+    mg.mgdwf_net_load(net3, path)
+    assert torch.equal(mg.mgdwf_net_get_weights(net3), mg.mgdwf_net_get_weights(net))
+    a = mg.mgdwf_net_train(net, [h], etas[:3], 3e-3)
+    b = mg.mgdwf_net_train(net3, [h], etas[:3], 3e-3)
+    assert a == b
+    assert torch.equal(mg.mgdwf_net_get_weights(net3), mg.mgdwf_net_get_weights(net))
+    other = mg.Net((2, 8, 8, 4, 8), 1.0)
+    with pytest.raises(mg.MgdwfError, match="STATE"):
+        mg.mgdwf_net_load(other, path)
+    junk = tmp_path / "junk.bin"
+    junk.write_bytes(b"not a network" * 8)
+    with pytest.raises(mg.MgdwfError, match="INVALID_ARG"):
+        mg.mgdwf_net_load(net3, junk)
+    for x in (h, h2):
+        x.close()

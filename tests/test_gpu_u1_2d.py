@@ -237,3 +237,31 @@ def test_4d_only_calls_refuse_a_2d_handle(cuda):
         mg.mgdwf_set_nullvecs(h, (1, 4, 1, 1), dev(random_starts2d(L, Ls, 2, 3)), 2)
         mg.mgdwf_build_coarse_squared(h)
     h.close()
+
+
+def test_2d_checkpoint_reloads_bitwise(cuda, tmp_path):
+    """A 2D setup saved and loaded into a fresh 2D handle solves bit for bit
+    as the saved one; a 4D handle refuses the file."""
+    import paper_1205_2933_amd as mg
+    L, Ls, mf = (8, 8), 4, 0.05
+    U = quenched_u1_2d(L, 4.0, 17, sweeps=20)
+    h = _handle(mg, L, Ls, mf, U)
+    p = mg.make_mg_params((4, 4, 1, 1), 4, sweeps=1, sweep0_iters=30, nu_pre=3, nu_post=3, coarse_tol=0.1,
+                          fine_prec="f64", coarse_prec="f64", squared=True)
+    mg.mgdwf_setup(h, p, dev(random_starts2d(L, Ls, 4, 18)))
+    path = tmp_path / "u1.ck"
+    mg.mgdwf_save_setup(h, path)
+    b = dev(point_sources2d(L, Ls)[0])
+    x0 = torch.zeros_like(b)
+    mg.mgdwf_solve(h, b, x0, tol=1e-10, max_outer=200, restart=8)
+    h2 = _handle(mg, L, Ls, mf, U)
+    mg.mgdwf_load_setup(h2, path)
+    mg.mgdwf_set_mg_params(h2, p)
+    x1 = torch.zeros_like(b)
+    mg.mgdwf_solve(h2, b, x1, tol=1e-10, max_outer=200, restart=8)
+    assert torch.equal(x0, x1)
+    h4 = mg.Handle((4, 4, 4, 4), Ls, M5, mf)
+    with pytest.raises(mg.MgdwfError):
+        mg.mgdwf_load_setup(h4, path)
+    for hh in (h, h2, h4):
+        hh.close()
