@@ -171,10 +171,15 @@ __global__ __launch_bounds__(576) void k_sq_apply(const MC2* __restrict__ M, con
 #pragma unroll
         for (int j = 0; j < NR; ++j) cfma(acc[j], mv, panel[c * NR + j]);
       };
-      if constexpr (sizeof(T) == 4) {
-        // FP32: four columns in flight (202 against 262 us at 12 RHS on
-        // 512 sites x 48 dof); FP64 runs faster without (307 against 338 us)
-#pragma unroll 4
+      if constexpr (sizeof(T) == 4 && NR >= 8) {
+        // FP32: columns in flight, measured on 512 sites x 48 dof: at 12 RHS
+        // 148 us with 16, 158 with 8, 202 with 4, 262 with none; at one
+        // right-hand side 57 us with 8 and 66 with 16.  FP64 runs faster
+        // without (307 against 338 us with 4)
+#pragma unroll 16
+        for (int c = 0; c < n2; ++c) column(c);
+      } else if constexpr (sizeof(T) == 4) {
+#pragma unroll 8
         for (int c = 0; c < n2; ++c) column(c);
       } else {
         for (int c = 0; c < n2; ++c) column(c);
