@@ -155,6 +155,13 @@ typedef struct {
                              resolves the lowest modes too, the ratio rises
                              again).  One more application of D per vector
                              every k iterations.                               */
+  int32_t smoother_dirs;  /* 9-point smoother: 0 keeps every MR direction of
+                             one smoother application and forms x once at the
+                             end (nu fields per right-hand side); k > 0 keeps
+                             at most k and adds them to x every k steps (less
+                             memory, one more pass over x per k steps; the
+                             sums are grouped differently, so results agree
+                             to rounding).                                     */
 } mgdwf_mg_params;
 
 /* Outer flexible GCR (Sec. 3).  Every restart recomputes the true residual

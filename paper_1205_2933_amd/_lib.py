@@ -48,7 +48,7 @@ class mgdwf_mg_params(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
                 ("coarse_tol", ctypes.c_double), ("coarse_maxiter", ctypes.c_int32),
                 ("fine_prec", ctypes.c_int), ("coarse_prec", ctypes.c_int), ("coarse_graph", ctypes.c_int32),
-                ("squared", ctypes.c_int32), ("sweep0_check", ctypes.c_int32)]
+                ("squared", ctypes.c_int32), ("sweep0_check", ctypes.c_int32), ("smoother_dirs", ctypes.c_int32)]
 
 
 class mgdwf_level2_params(ctypes.Structure):
@@ -370,7 +370,7 @@ def mgdwf_apply_coarse_noalloc(h: Handle, inp: torch.Tensor, out: torch.Tensor, 
 
 def make_mg_params(block, nvec, sweeps=1, sweep0_iters=100, sweep_iters=4, nu_pre=4, nu_post=4,
                    coarse_tol=0.1, coarse_maxiter=100, fine_prec="f64", coarse_prec="f64",
-                   coarse_graph=True, squared=False, sweep0_check=0) -> mgdwf_mg_params:
+                   coarse_graph=True, squared=False, sweep0_check=0, smoother_dirs=0) -> mgdwf_mg_params:
     p = mgdwf_mg_params()
     p.block[:] = list(block)
     p.nvec, p.sweeps, p.sweep0_iters, p.sweep_iters = nvec, sweeps, sweep0_iters, sweep_iters
@@ -380,6 +380,7 @@ def make_mg_params(block, nvec, sweeps=1, sweep0_iters=100, sweep_iters=4, nu_pr
     p.coarse_graph = 2 if coarse_graph in ("persistent", 2) else (1 if coarse_graph else 0)
     p.squared = 1 if squared else 0
     p.sweep0_check = sweep0_check
+    p.smoother_dirs = smoother_dirs
     return p
 
 

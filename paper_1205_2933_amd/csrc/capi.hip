@@ -115,6 +115,7 @@ void check_params(const mgdwf_ctx* c, const mgdwf_mg_params* p) {
   need(p->sweeps >= 1 && p->sweeps <= 8, MGDWF_ERR_INVALID_ARG, "sweeps must be in 1..8");
   need(p->sweep0_iters >= 0 && p->sweep_iters >= 1 && p->sweep0_check >= 0, MGDWF_ERR_INVALID_ARG,
        "bad sweep iteration counts");
+  need(p->smoother_dirs >= 0, MGDWF_ERR_INVALID_ARG, "smoother_dirs must be >= 0");
   need(p->nu_pre >= 0 && p->nu_post >= 0 && p->nu_pre <= 16 && p->nu_post <= 16, MGDWF_ERR_INVALID_ARG,
        "bad smoother step counts");
   need(p->coarse_tol > 0 && p->coarse_tol < 1 && p->coarse_maxiter >= 1, MGDWF_ERR_INVALID_ARG,

@@ -137,10 +137,11 @@ struct TwoLevel {
   }
 
   // nu steps of minimal residual along D^+ r on D x = b from x = 0.  The
-  // directions p_i are kept and x = sum_i alpha_i p_i is formed once at the end,
-  // so a step moves r, q and the new r only; step 0 reads b in place of r.
-  // Without need_r the last step skips the residual update nobody reads;
-  // with add_x the step sum is added to x instead of replacing it.
+  // directions p_i are kept and x = sum_i alpha_i p_i is formed once at the end
+  // (with smoother_dirs = k, at most k are kept and added to x every k
+  // steps), so a step moves r, q and the new r only; step 0 reads b in place
+  // of r.  Without need_r the last step skips the residual update nobody
+  // reads; with add_x the step sum is added to x instead of replacing it.
   void smooth(const F2* b, F2* x, F2* r, int nu, bool need_r = true, bool add_x = false) {
     if (nu == 0) {
       copy(c, b, r, nf * nrhs);
@@ -148,17 +149,23 @@ struct TwoLevel {
       return;
     }
     const std::string t = Prec<F2>::tag;
-    std::vector<F2*> P(nu);
-    for (int i = 0; i < nu; ++i) P[i] = c->buf<F2>("mr_p" + std::to_string(i) + t, nf * nrhs);
+    const int K = p.smoother_dirs > 0 ? std::min(nu, p.smoother_dirs) : nu;  // directions kept at once
+    std::vector<F2*> P(K);
+    for (int i = 0; i < K; ++i) P[i] = c->buf<F2>("mr_p" + std::to_string(i) + t, nf * nrhs);
+    // one table per number kept: with nu_pre != nu_post a shared table would
+    // be re-uploaded (with a stream synchronisation) inside captures
+    const F2* const* Pd = ptr_table<F2>(c, "ptrP" + t + std::to_string(K), P);
     for (int i = 0; i < nu; ++i) {
       const F2* rin = i == 0 ? b : r;
-      fine_op<F2>(c, rin, P[i], nullptr, true, 0, nrhs, S_MR + 2 * i);      // p_i = D^+ r, |p_i|^2
-      fine_op<F2>(c, P[i], qq, nullptr, false, 0, nrhs, S_MR + 2 * i + 1);  // q = D p_i, |q|^2
+      F2* pi = P[i % K];
+      fine_op<F2>(c, rin, pi, nullptr, true, 0, nrhs, S_MR + 2 * i);       // p_i = D^+ r, |p_i|^2
+      fine_op<F2>(c, pi, qq, nullptr, false, 0, nrhs, S_MR + 2 * i + 1);   // q = D p_i, |q|^2
       if (need_r || i + 1 < nu) res_update<F2>(r, rin, qq, nf, nrhs, sl, S_MR + 2 * i, S_MR + 2 * i + 1, c->st);
+      if ((i + 1) % K == 0 || i + 1 == nu) {  // x (+)= sum of the kept directions' steps
+        const int i0 = i - i % K;
+        lincomb<F2>(x, Pd, i - i0 + 1, nf, nrhs, sl, S_MR + 2 * i0, add_x || i0 > 0, c->st);
+      }
     }
-    // one table per smoother length: with nu_pre != nu_post a shared table
-    // would be re-uploaded (with a stream synchronisation) inside captures
-    lincomb<F2>(x, ptr_table<F2>(c, "ptrP" + t + std::to_string(nu), P), nu, nf, nrhs, sl, S_MR, add_x, c->st);
   }
 
   // CGNE on D_c: x = D_c^+ y with D_c D_c^+ y = b, to |r| < tol |b| or maxiter.

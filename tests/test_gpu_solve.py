@@ -318,3 +318,59 @@ def test_persistent_barrier_timeout_is_an_error_not_a_hang(cuda):
     with pytest.raises(mg.MgdwfError):
         mg.mgdwf_set_barrier_timeout(h, -1.0)
     h.close()
+
+
+@pytest.mark.parametrize("prec,cprec,dirs", [("f64", "f64", 3), ("f32", "f16", 4), ("f32", "f16", 1)])
+def test_smoother_with_fewer_kept_directions(cuda, prec, cprec, dirs):
+    """smoother_dirs: at most `dirs` MR directions kept, added to x every `dirs`
+    steps.  One V-cycle application equals the oracle's (the same tolerance as
+    with all directions kept); on an adaptive setup a solve converges with
+    graph replays and the handle holds less workspace than with every
+    direction kept."""
+    import paper_1205_2933_amd as mg
+    from oracle import setup as osu
+    L, Ls, mf, block = (4, 4, 4, 4), 8, 0.01, (2, 2, 2, 2)
+    U = prepare_gauge(L, 0.3, 11)
+    A = dwf.DWF(U, 1.8, mf)
+    V = random_starts(L, Ls, 8, 41)
+    prm = osu.MGParams(block=block, nvec=16, nu_pre=6, nu_post=5, smoother="mr_normal", coarse_solver="cgne",
+                       coarse_tol=1e-30, coarse_maxiter=16)
+    omg = osu.MG(A, prm)
+    omg.rebuild(V)
+    M = omg.preconditioner()
+    b = gaussian_fermion(L, Ls, 31, n=2)
+    want = np.stack([M(b[r]) for r in range(2)])
+    used = {}
+    for k in (0, dirs):
+        h = mg.Handle(L, Ls, 1.8, mf)
+        mg.mgdwf_set_gauge(h, dev(U))
+        mg.mgdwf_set_nullvecs(h, block, dev(osu.reflect_pairs(V)), 16)
+        mg.mgdwf_build_coarse(h)
+        mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, nu_pre=6, nu_post=5, coarse_tol=1e-30,
+                                                    coarse_maxiter=16, fine_prec=prec, coarse_prec=cprec,
+                                                    smoother_dirs=k))
+        z = torch.empty_like(dev(b))
+        mg.mgdwf_apply_vcycle(h, dev(b), z, nrhs=2)
+        got = z.cpu().numpy()
+        for r in range(2):
+            e = np.linalg.norm(got[r] - want[r]) / np.linalg.norm(want[r])
+            print(f"V-cycle {prec}/{cprec} smoother_dirs {k} rhs {r}: {e:.3e}", flush=True)
+            assert e < VCYCLE_TOL[(prec, cprec)]
+        h.close()
+    # a solve on an adaptive setup, with graph replays
+    kw = dict(sweeps=1, sweep0_iters=100, coarse_tol=0.1, coarse_maxiter=200, nu_pre=6, nu_post=5)
+    for k in (0, dirs):
+        h = mg.Handle(L, Ls, 1.8, mf)
+        mg.mgdwf_set_gauge(h, dev(U))
+        mg.mgdwf_setup(h, mg.make_mg_params(block, 16, fine_prec="f64", coarse_prec="f64", **kw),
+                       dev(random_starts(L, Ls, 8, 21)))
+        mg.mgdwf_trim(h)
+        mg.mgdwf_set_mg_params(h, mg.make_mg_params(block, 16, fine_prec=prec, coarse_prec=cprec, smoother_dirs=k,
+                                                    **kw))
+        x = torch.zeros_like(dev(b))
+        reps = mg.mgdwf_solve(h, dev(b), x, nrhs=2, tol=1e-10, max_outer=400, restart=8)
+        print(f"solve smoother_dirs {k}: {reps[0]['outer_iters']} outer iterations", flush=True)
+        assert max(r["true_relres"] for r in reps) < 1e-10
+        used[k] = mg.mgdwf_memory_bytes(h)
+        h.close()
+    assert used[dirs] < used[0]
